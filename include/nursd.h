@@ -1,0 +1,197 @@
+/*
+ * nursd.h -- C ABI of the MI355X NURSD / SRSD reconstruction library.
+ *
+ * Non-line-of-sight reconstruction by phasor-field Rayleigh-Sommerfeld
+ * diffraction (RSD) with non-uniform relay sampling (NURSD) and the scaled
+ * RSD (SRSD), after Sultan et al., "Optimized Sampling for Non-Line-of-Sight
+ * Imaging Using Modified Fast Fourier Transforms":
+ *   - measurement H(x_p, x_c, t) and relay positions in, as in the problem
+ *     statement of the standard RSD section (phasor-field response,
+ *     eq. PF_Response; RSD reconstruction, eq. PF_RSD_Defn);
+ *   - wavelet parameters lambda_c and sigma of the Gaussian band-pass
+ *     (eq. PFPacket_Omega_Supp);
+ *   - output on a uniform voxel grid (eq. NURSD1), on per-plane voxel lists
+ *     (eq. NURSD2 / eq. NURSD3) or on the scaled frustum (eq. SRSD_conv with
+ *     the scaled FFT of eq. SFFT).
+ *
+ * Conventions
+ *   Units: metres, seconds.  The relay plane is z = 0; planes have z > 0.
+ *   Complex arrays are interleaved float pairs (re, im) = complex64.
+ *   Every pointer named *_dev is device memory (HIP), owned by the caller;
+ *   host arrays (z lists, bins, CSR offsets) are copied at plan creation.
+ *   `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue work
+ *   on that stream and do not synchronise it, except plan creation and
+ *   nursd_plan_set_points, which read the relay positions back to the host.
+ *   Errors: every int-returning call returns NURSD_OK (0) or a negative
+ *   NURSD_ERR_* code; nursd_last_error() gives a message (thread-local).  No
+ *   C++ exception crosses this interface.  A call that fails argument checks
+ *   enqueues no work.
+ *   Workspace: the caller allocates nursd_workspace_size() bytes of device
+ *   memory (256-byte aligned) and passes it to the compute calls; its
+ *   contents need not be preserved between calls.  The plan owns only small
+ *   device tables (twiddles, deconvolution factors, binned relay lists).
+ */
+#ifndef NURSD_H
+#define NURSD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NURSD_OK 0
+#define NURSD_ERR_ARG (-1)              /* invalid argument or NULL pointer        */
+#define NURSD_ERR_GEOMETRY (-2)         /* z <= 0, points outside the period, ...   */
+#define NURSD_ERR_UNSUPPORTED_SIZE (-3) /* transform or time-axis size unsupported */
+#define NURSD_ERR_WORKSPACE (-4)        /* workspace missing or misaligned          */
+#define NURSD_ERR_HIP (-5)              /* a HIP runtime call failed                */
+#define NURSD_ERR_UNIMPLEMENTED (-6)
+
+#define NURSD_MODE_GRID 0   /* uniform voxel grid, NURSD-1                  */
+#define NURSD_MODE_POINTS 1 /* per-plane voxel lists, NURSD-3 (or NURSD-2)  */
+#define NURSD_MODE_SRSD 2   /* scaled RSD frustum                           */
+
+/* Phasor-field wavelet and temporal sampling (eq. PF_Response,
+ * eq. PFPacket_Omega_Supp).  The F frequencies are DFT bins b of the T-bin
+ * histograms, f_b = b / (T dt); by default F consecutive bins centred on
+ * round(f_c T dt), f_c = c / lambda_c.  Each bin must satisfy 0 < b < T/2.
+ * Weight of bin b: exp(-(f_b - f_c)^2 / (2 (sigma_rel f_c)^2)) e^{-j 2 pi f_b t0}. */
+typedef struct {
+    double lambda_c;      /* central wavelength [m]                              */
+    double sigma_rel;     /* sigma_f / f_c; 0.2 is the paper's sigma = c/(5 lambda_c) */
+    int32_t n_freq;       /* F >= 1                                              */
+    int32_t n_time;       /* T, a power of two in [256, 8192] for nursd_phasor   */
+    double dt;            /* bin width [s]                                       */
+    double t0;            /* time of bin 0 [s]                                   */
+    const int32_t* bins;  /* host array of F bins, or NULL for the centred band  */
+    int32_t coherent;     /* 1: V = sum_b (...), I = |V|;  0: I = sum_b |F_b|     */
+} nursd_wavelet;
+
+/* Output sampling.
+ * GRID:   voxel (ix, iy) of plane iz at (x0 + ix dx, y0 + iy dy, z[iz]);
+ *         output arrays are [nz][ny][nx] (x fastest).
+ * POINTS: plane iz owns voxels plane_ptr[iz] .. plane_ptr[iz+1]-1 of
+ *         voxel_xy_dev ([V][2] float, device); dx, dy give the FFT pitch;
+ *         outputs are [V].
+ * SRSD:   uniform relay grid of nx x ny samples at pitch (dx, dy) around
+ *         (x0, y0) (the GRID convention); plane iz is sampled at pitch
+ *         (dx, dy) / alpha_iz, alpha_iz = alpha[iz] if alpha != NULL else
+ *         zref / z[iz]; voxel (ix, iy) of plane iz lies at
+ *         c + ((ix - nx/2) dx, (iy - ny/2) dy) / alpha_iz with
+ *         c = (x0 + (nx/2) dx, y0 + (ny/2) dy).  Requires 0 < alpha <= 1. */
+typedef struct {
+    int32_t mode;
+    double x0, y0;
+    double dx, dy;
+    int32_t nx, ny;
+    int32_t nz;
+    const double* z;            /* host [nz], each > 0                          */
+    const int32_t* plane_ptr;   /* host [nz+1] (POINTS)                         */
+    const float* voxel_xy_dev;  /* device [V][2] (POINTS)                       */
+    double zref;                /* SRSD                                         */
+    const double* alpha;        /* host [nz] (SRSD) or NULL                     */
+    double xp[3];               /* illumination point x_p                       */
+} nursd_geometry;
+
+/* Numerical options. */
+typedef struct {
+    int32_t n_relay;     /* L >= 1                                              */
+    double pad;          /* zero-padding factor, >= 1 (default 2)               */
+    double sigma_os;     /* NUFFT oversampling; only 2.0 is supported           */
+    double tol;          /* NUFFT tolerance (sets the spreading width), 1e-6    */
+    int32_t M;           /* transform size, 0 = smallest that fits              */
+    int32_t freq_chunk;  /* frequencies per propagation chunk, 0 = auto         */
+    int32_t plane_chunk; /* planes per propagation chunk, 0 = auto              */
+} nursd_options;
+
+typedef struct nursd_plan nursd_plan;
+typedef struct nursd_batch nursd_batch;
+
+/* Read-only facts about a plan (the periodic frame the operator is defined
+ * on: relay x maps to 2 pi (x - cx) / (M dx)). */
+typedef struct {
+    int32_t M;            /* transform size                                    */
+    int32_t Mf;           /* oversampled NUFFT grid size                       */
+    int32_t n_freq;
+    int32_t n_relay;
+    int32_t kernel_width; /* ES spreading width                                */
+    int32_t n_voxels;     /* voxels per output volume                          */
+    double dx, dy;        /* grid pitch of the frame                           */
+    double cx, cy;        /* frame centre                                      */
+    double beta;          /* ES shape parameter                                */
+    size_t workspace_bytes;
+} nursd_plan_info_t;
+
+/* Fill the structs with defaults (pad 2, sigma_os 2, tol 1e-6, coherent,
+ * sigma_rel 0.2).  Never fails for non-NULL arguments. */
+void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options* opt);
+
+/* Create a plan: validates the geometry, chooses the frame (smallest
+ * supported M >= pad * max(nx, ny) with every relay and voxel inside the
+ * period and every relay-voxel offset inside half a period), bins the relay
+ * samples for spreading and builds the device tables.  relay_xy_dev: device
+ * [L][2] float (metres).  Synchronises `stream` once to read the positions.
+ * Errors: ARG, GEOMETRY, UNSUPPORTED_SIZE, HIP. */
+int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo,
+                      const nursd_options* opt, const float* relay_xy_dev,
+                      void* stream, nursd_plan** out);
+
+/* Replace the relay positions (same L); re-bins them.  Fails with GEOMETRY
+ * if a point leaves the plan's frame.  Synchronises `stream`. */
+int nursd_plan_set_points(nursd_plan* plan, const float* relay_xy_dev, void* stream);
+
+int nursd_plan_info(const nursd_plan* plan, nursd_plan_info_t* info);
+int nursd_workspace_size(const nursd_plan* plan, size_t* bytes);
+void nursd_plan_destroy(nursd_plan* plan);
+
+/* Step 1 alone: temporal phasor transform (eq. PF_Response with the
+ * band-pass of eq. PFPacket_Omega_Supp).  hist_dev: [L][T] float;
+ * P_dev: [F][L] complex64 output. */
+int nursd_phasor(nursd_plan* plan, const float* hist_dev, void* P_dev, void* stream);
+
+/* Steps 2-3 alone: type-1 NUFFT of P_dev ([F][L] complex64) onto the
+ * M x M modes (NUFFT section; spread, FFT, deconvolve).  U_dev: [F][M][M]
+ * complex64, row index kx, column ky, both in FFT order (k mod M); the
+ * stored value is U[k] / M^2.  Uses the workspace. */
+int nursd_spectrum(nursd_plan* plan, const void* P_dev, void* U_dev, void* ws_dev,
+                   size_t ws_bytes, void* stream);
+
+/* Full reconstruction from histograms: steps 1-7.  Writes the complex volume
+ * vol_dev (complex64, layout of the mode) and/or the intensity I_dev
+ * (float, |V| for coherent plans, sum_b |F_b| otherwise); either may be NULL
+ * but not both (vol_dev must be NULL for incoherent plans). */
+int nursd_forward_hist(nursd_plan* plan, const float* hist_dev, void* vol_dev, float* I_dev,
+                       void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Reconstruction from phasors P_dev ([F][L] complex64): steps 2-7. */
+int nursd_forward_phasor(nursd_plan* plan, const void* P_dev, void* vol_dev, float* I_dev,
+                         void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Adjoint of the coherent map P -> V (GRID plans).  grad_vol_dev: [nz][ny][nx]
+ * complex64, the upstream gradient dL/dRe V + j dL/dIm V.  Writes
+ * grad_P_dev = A^H grad_vol ([F][L] complex64) and, if grad_xy_dev != NULL,
+ * the relay-position gradient [L][2] float: Re sum_b conj(P_bl) d(...)/dx_l,
+ * which needs P_dev.  The forward state is not stored: everything is
+ * recomputed per frequency. */
+int nursd_adjoint(nursd_plan* plan, const void* grad_vol_dev, const void* P_dev,
+                  void* grad_P_dev, float* grad_xy_dev, void* ws_dev, size_t ws_bytes,
+                  void* stream);
+
+/* Batched serving: n plans (GRID mode, coherent) run as one captured HIP
+ * graph of persistent kernels.  inputs[i] = hist_dev of plan i,
+ * outputs[i] = I_dev (float) of plan i.  The batch owns its workspace and
+ * graph; nursd_batch_forward launches the graph on `stream`. */
+int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream,
+                       nursd_batch** out);
+int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev,
+                        void* stream);
+void nursd_batch_destroy(nursd_batch* batch);
+
+const char* nursd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NURSD_H */

@@ -1,0 +1,205 @@
+"""PyTorch-facing wrapper around the C ABI: device memory and streams only.
+
+Every step of the reconstruction runs in the HIP kernels of libnursd.so;
+this module allocates output tensors and the workspace with torch, passes
+raw device pointers and the current HIP stream, and raises on any error.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_int32, c_size_t, c_void_p
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import MODE_GRID, MODE_POINTS, MODE_SRSD, Geometry, Options, PlanInfo, Wavelet, check
+
+
+def _stream(stream=None) -> c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> c_void_p:
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t: torch.Tensor, dtype, shape, name):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+class Plan:
+    """One reconstruction geometry (C handle nursd_plan)."""
+
+    def __init__(self, relay_xy: torch.Tensor, *, lambda_c: float, n_time: int, dt: float, t0: float,
+                 n_freq: int, z, mode: int = MODE_GRID, x0=0.0, y0=0.0, dx=1.0, dy=1.0, nx=0, ny=0,
+                 bins=None, coherent=True, sigma_rel=0.2, pad=2.0, tol=1e-6, M=0, freq_chunk=0,
+                 plane_chunk=0, xp=(0.0, 0.0, 0.0), zref=0.0, alpha=None, plane_ptr=None,
+                 voxel_xy: torch.Tensor | None = None, stream=None):
+        self._lib = _lib.load()
+        self.handle = None
+        L = relay_xy.shape[0]
+        _need(relay_xy, torch.float32, (L, 2), "relay_xy")
+        self.L = L
+        self.mode = mode
+        self.coherent = bool(coherent)
+        wl = Wavelet()
+        geo = Geometry()
+        opt = Options()
+        self._lib.nursd_default_options(byref(wl), byref(geo), byref(opt))
+        wl.lambda_c, wl.n_time, wl.dt, wl.t0, wl.n_freq = lambda_c, n_time, dt, t0, n_freq
+        wl.sigma_rel = sigma_rel
+        wl.coherent = 1 if coherent else 0
+        self._keep = []
+        if bins is not None:
+            b = np.ascontiguousarray(bins, dtype=np.int32)
+            self._keep.append(b)
+            wl.bins = b.ctypes.data_as(POINTER(c_int32))
+            wl.n_freq = len(b)
+        zz = np.ascontiguousarray(z, dtype=np.float64)
+        self._keep.append(zz)
+        geo.mode = mode
+        geo.x0, geo.y0, geo.dx, geo.dy, geo.nx, geo.ny = x0, y0, dx, dy, nx, ny
+        geo.nz = len(zz)
+        geo.z = zz.ctypes.data_as(POINTER(c_double))
+        geo.zref = zref
+        for i in range(3):
+            geo.xp[i] = float(xp[i])
+        if alpha is not None:
+            al = np.ascontiguousarray(alpha, dtype=np.float64)
+            self._keep.append(al)
+            geo.alpha = al.ctypes.data_as(POINTER(c_double))
+        if plane_ptr is not None:
+            pp = np.ascontiguousarray(plane_ptr, dtype=np.int32)
+            self._keep.append(pp)
+            geo.plane_ptr = pp.ctypes.data_as(POINTER(c_int32))
+        if voxel_xy is not None:
+            _need(voxel_xy, torch.float32, (voxel_xy.shape[0], 2), "voxel_xy")
+            self.voxel_xy = voxel_xy
+            geo.voxel_xy_dev = voxel_xy.data_ptr()
+        opt.n_relay = L
+        opt.pad, opt.tol, opt.M = pad, tol, M
+        opt.freq_chunk, opt.plane_chunk = freq_chunk, plane_chunk
+        h = c_void_p()
+        check(self._lib.nursd_plan_create(byref(wl), byref(geo), byref(opt), _ptr(relay_xy), _stream(stream),
+                                          byref(h)), "nursd_plan_create")
+        self.handle = h
+        info = PlanInfo()
+        check(self._lib.nursd_plan_info(self.handle, byref(info)), "nursd_plan_info")
+        self.info = {k: getattr(info, k) for k, _ in PlanInfo._fields_}
+        self.F = self.info["n_freq"]
+        self.M = self.info["M"]
+        self.nx, self.ny, self.nz = nx, ny, len(zz)
+        self.n_time = n_time
+        self.device = relay_xy.device
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.nursd_plan_destroy(self.handle)
+            self.handle = None
+
+    # ------------------------------------------------------------ workspace
+    def workspace(self) -> tuple[torch.Tensor, int]:
+        n = int(self.info["workspace_bytes"])
+        if self._ws is None or self._ws.numel() < n + 256:
+            self._ws = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return self._ws, base + off
+
+    def _ws_args(self):
+        _, p = self.workspace()
+        return c_void_p(p), c_size_t(int(self.info["workspace_bytes"]))
+
+    def out_shape(self):
+        if self.mode == MODE_POINTS:
+            return (self.info["n_voxels"],)
+        return (self.nz, self.ny, self.nx)
+
+    # ------------------------------------------------------------ entry points
+    def set_points(self, relay_xy: torch.Tensor, stream=None):
+        _need(relay_xy, torch.float32, (self.L, 2), "relay_xy")
+        check(self._lib.nursd_plan_set_points(self.handle, _ptr(relay_xy), _stream(stream)),
+              "nursd_plan_set_points")
+
+    def phasor(self, hist: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(hist, torch.float32, (self.L, self.n_time), "hist")
+        P = torch.empty((self.F, self.L), dtype=torch.complex64, device=self.device)
+        check(self._lib.nursd_phasor(self.handle, _ptr(hist), _ptr(P), _stream(stream)), "nursd_phasor")
+        return P
+
+    def spectrum(self, P: torch.Tensor, stream=None) -> torch.Tensor:
+        _need(P, torch.complex64, (self.F, self.L), "P")
+        U = torch.empty((self.F, self.M, self.M), dtype=torch.complex64, device=self.device)
+        ws, n = self._ws_args()
+        check(self._lib.nursd_spectrum(self.handle, _ptr(P), _ptr(U), ws, n, _stream(stream)), "nursd_spectrum")
+        return U
+
+    def _outs(self, vol, intensity, out_vol=None, out_I=None):
+        V = I = None
+        if vol and self.coherent:
+            V = out_vol if out_vol is not None else torch.empty(self.out_shape(), dtype=torch.complex64,
+                                                                 device=self.device)
+        if intensity:
+            I = out_I if out_I is not None else torch.empty(self.out_shape(), dtype=torch.float32,
+                                                            device=self.device)
+        return V, I
+
+    def forward_hist(self, hist: torch.Tensor, vol=True, intensity=True, out_vol=None, out_I=None,
+                     stream=None):
+        _need(hist, torch.float32, (self.L, self.n_time), "hist")
+        V, I = self._outs(vol, intensity, out_vol, out_I)
+        ws, n = self._ws_args()
+        check(self._lib.nursd_forward_hist(self.handle, _ptr(hist), _ptr(V), _ptr(I), ws, n, _stream(stream)),
+              "nursd_forward_hist")
+        return V, I
+
+    def forward_phasor(self, P: torch.Tensor, vol=True, intensity=True, out_vol=None, out_I=None,
+                       stream=None):
+        _need(P, torch.complex64, (self.F, self.L), "P")
+        V, I = self._outs(vol, intensity, out_vol, out_I)
+        ws, n = self._ws_args()
+        check(self._lib.nursd_forward_phasor(self.handle, _ptr(P), _ptr(V), _ptr(I), ws, n, _stream(stream)),
+              "nursd_forward_phasor")
+        return V, I
+
+    def adjoint(self, grad_vol: torch.Tensor, P: torch.Tensor | None = None, stream=None):
+        _need(grad_vol, torch.complex64, self.out_shape(), "grad_vol")
+        gP = torch.empty((self.F, self.L), dtype=torch.complex64, device=self.device)
+        gxy = None
+        if P is not None:
+            _need(P, torch.complex64, (self.F, self.L), "P")
+            gxy = torch.empty((self.L, 2), dtype=torch.float32, device=self.device)
+        ws, n = self._ws_args()
+        check(self._lib.nursd_adjoint(self.handle, _ptr(grad_vol), _ptr(P), _ptr(gP), _ptr(gxy), ws, n,
+                                      _stream(stream)), "nursd_adjoint")
+        return gP, gxy
+
+
+def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) -> Plan:
+    """Plan for a workloads.scenes.Workload (relay positions copied to `device`)."""
+    wl, g = w.wavelet, w.grid
+    if relay_xy is None:
+        relay_xy = torch.from_numpy(np.ascontiguousarray(w.relay_xy)).to(device)
+    mode = {"grid": MODE_GRID, "points": MODE_POINTS, "srsd": MODE_SRSD}[w.mode]
+    extra = {}
+    if w.mode == "points":
+        extra["plane_ptr"] = w.plane_ptr
+        extra["voxel_xy"] = torch.from_numpy(np.ascontiguousarray(w.voxel_xy)).to(device)
+    if w.mode == "srsd":
+        extra["zref"] = w.zref
+    args = dict(lambda_c=wl.lambda_c, n_time=wl.n_time, dt=wl.dt, t0=wl.t0, n_freq=wl.n_freq, z=g.z,
+                mode=mode, x0=g.x0, y0=g.y0, dx=g.dx, dy=g.dy, nx=g.nx, ny=g.ny, bins=wl.bins,
+                sigma_rel=wl.sigma_rel, pad=w.pad, xp=tuple(w.xp))
+    args.update(extra)
+    args.update(kw)
+    return Plan(relay_xy, **args)

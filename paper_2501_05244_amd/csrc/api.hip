@@ -1,0 +1,669 @@
+// Host side of the C ABI declared in include/nursd.h: plan creation (frame
+// rule, frequency bins, device tables, binning of relay samples for the
+// spreading kernel, workspace layout) and the launch sequences of the
+// forward operator.
+#include "nursd.h"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace nursd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(NURSD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kSupportedM[] = {16, 32, 64, 128, 256, 512, 1024};
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool is_pow2(long v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// Gauss-Legendre nodes and weights on [-1, 1] (Newton on P_n).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wts) {
+    x.resize(n);
+    wts.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; ++k) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            double dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) {
+                x[i] = z;
+                wts[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+                break;
+            }
+            x[i] = z;
+            wts[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+        }
+    }
+}
+
+double es_psi(double z, double beta) {
+    double t = 1.0 - z * z;
+    return t <= 0.0 ? 0.0 : std::exp(beta * (std::sqrt(t) - 1.0));
+}
+
+}  // namespace
+
+struct nursd_plan {
+    // wavelet
+    int F = 0, T = 0, coherent = 1;
+    double lambda_c = 0, sigma_rel = 0.2, dt = 0, t0 = 0;
+    std::vector<int> bins;
+    std::vector<double> freqs;
+    // geometry
+    int mode = NURSD_MODE_GRID;
+    double x0 = 0, y0 = 0, vdx = 0, vdy = 0;
+    int nx = 0, ny = 0, nz = 0;
+    std::vector<double> z, alpha;
+    std::vector<int> plane_ptr;
+    const float* voxel_xy_dev = nullptr;
+    double zref = 0;
+    double xp[3] = {0, 0, 0};
+    int L = 0;
+    // frame
+    int M = 0, Mf = 0;
+    double dx = 0, dy = 0, cx = 0, cy = 0;
+    int w = 7;
+    double beta = 0;
+    double pad = 2.0;
+    // chunking
+    int FC = 8, ZC = 16, FCn = 16;
+    int BS = 0;
+    // device tables
+    std::vector<void*> owned;
+    float2* tw_all = nullptr;
+    size_t tw_off[kMaxLog] = {};
+    int* d_bins = nullptr;
+    float2* d_wt = nullptr;
+    float2* d_tb = nullptr;
+    double* d_f = nullptr;
+    double* d_z = nullptr;
+    double* d_px = nullptr;   // per-plane pitch (SRSD)
+    double* d_py = nullptr;
+    float* d_decx = nullptr;
+    float* d_decy = nullptr;
+    SpreadEntry* d_ent = nullptr;
+    int* d_band_ptr = nullptr;
+    int nbands = 0, n_ent = 0;
+    // workspace layout
+    size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
+
+    ~nursd_plan() {
+        for (void* p : owned) (void)hipFree(p);
+    }
+    const float2* tw(int n) const { return tw_all + tw_off[__builtin_ctz((unsigned)n)]; }
+    int nvox() const {
+        return mode == NURSD_MODE_POINTS ? (plane_ptr.empty() ? 0 : plane_ptr.back()) : nx * ny * nz;
+    }
+};
+
+namespace {
+
+template <typename T>
+int upload(nursd_plan* p, const std::vector<T>& v, T** out) {
+    *out = nullptr;
+    if (v.empty()) return NURSD_OK;
+    void* d = nullptr;
+    HIP_TRY(hipMalloc(&d, v.size() * sizeof(T)));
+    p->owned.push_back(d);
+    HIP_TRY(hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *out = static_cast<T*>(d);
+    return NURSD_OK;
+}
+
+// Frame rule: every relay and voxel inside the period around (cx, cy) and
+// every relay-voxel offset strictly inside half a period, per axis.
+bool frame_fits(int M, double dx, double dy, double cx, double cy, const std::vector<float>& rxy,
+                const double vlo[2], const double vhi[2]) {
+    const double d[2] = {dx, dy}, c[2] = {cx, cy};
+    for (int ax = 0; ax < 2; ++ax) {
+        const double Lp = M * d[ax];
+        double rmin = 1e300, rmax = -1e300;
+        for (size_t i = ax; i < rxy.size(); i += 2) {
+            rmin = std::min(rmin, (double)rxy[i]);
+            rmax = std::max(rmax, (double)rxy[i]);
+        }
+        if (rmin - c[ax] < -Lp / 2 || rmax - c[ax] >= Lp / 2) return false;
+        if (vlo[ax] - c[ax] < -Lp / 2 || vhi[ax] - c[ax] >= Lp / 2) return false;
+        if (std::max(vhi[ax] - rmin, rmax - vlo[ax]) >= Lp / 2) return false;
+    }
+    return true;
+}
+
+int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
+    const int Mf = p->Mf, w = p->w;
+    const double hw = 0.5 * w;
+    const int BR = spread_band_rows(Mf);
+    p->nbands = Mf / BR;
+    struct E {
+        int band, ix0, iy0, l;
+        float fx, fy;
+    };
+    std::vector<E> ents;
+    ents.reserve(p->L * 2);
+    for (int l = 0; l < p->L; ++l) {
+        const double u = ((double)rxy[2 * l] - p->cx) / p->dx * 2.0 + Mf / 2;
+        const double v = ((double)rxy[2 * l + 1] - p->cy) / p->dy * 2.0 + Mf / 2;
+        if (!(u >= 0.0 && u < Mf && v >= 0.0 && v < Mf))
+            return fail(NURSD_ERR_GEOMETRY, "relay sample " + std::to_string(l) + " lies outside the plan's period");
+        const int ix0 = (int)std::ceil(u - hw), iy0 = (int)std::ceil(v - hw);
+        const float fx = (float)(u - ix0), fy = (float)(v - iy0);
+        int xs[2] = {ix0, 0}, ys[2] = {iy0, 0};
+        int nxs = 1, nys = 1;
+        if (ix0 < 0) xs[nxs++] = ix0 + Mf;
+        if (ix0 + w - 1 >= Mf) xs[nxs++] = ix0 - Mf;
+        if (iy0 < 0) ys[nys++] = iy0 + Mf;
+        if (iy0 + w - 1 >= Mf) ys[nys++] = iy0 - Mf;
+        for (int a = 0; a < nxs; ++a)
+            for (int c = 0; c < nys; ++c) {
+                const int r0 = std::max(ys[c], 0), r1 = std::min(ys[c] + w - 1, Mf - 1);
+                if (r0 > r1) continue;
+                for (int band = r0 / BR; band <= r1 / BR; ++band)
+                    ents.push_back({band, xs[a], ys[c], l, fx, fy});
+            }
+    }
+    std::stable_sort(ents.begin(), ents.end(), [](const E& a, const E& b) {
+        return a.band != b.band ? a.band < b.band : a.ix0 < b.ix0;
+    });
+    std::vector<SpreadEntry> out(ents.size());
+    std::vector<int> ptr(p->nbands + 1, 0);
+    for (size_t i = 0; i < ents.size(); ++i) {
+        out[i].ix0 = (short)ents[i].ix0;
+        out[i].iy0 = (short)ents[i].iy0;
+        out[i].fx = ents[i].fx;
+        out[i].fy = ents[i].fy;
+        out[i].idx = ents[i].l;
+        ptr[ents[i].band + 1]++;
+    }
+    for (int b = 0; b < p->nbands; ++b) ptr[b + 1] += ptr[b];
+    p->n_ent = (int)out.size();
+    if (p->d_ent) {
+        // replace previous lists
+        for (auto it = p->owned.begin(); it != p->owned.end();) {
+            if (*it == (void*)p->d_ent || *it == (void*)p->d_band_ptr) {
+                (void)hipFree(*it);
+                it = p->owned.erase(it);
+            } else {
+                ++it;
+            }
+        }
+        p->d_ent = nullptr;
+        p->d_band_ptr = nullptr;
+    }
+    int rc = upload(p, out, &p->d_ent);
+    if (rc) return rc;
+    return upload(p, ptr, &p->d_band_ptr);
+}
+
+int read_points(const float* dev, size_t n2, std::vector<float>& host, hipStream_t s) {
+    host.resize(n2);
+    HIP_TRY(hipMemcpyAsync(host.data(), dev, n2 * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return NURSD_OK;
+}
+
+void layout_workspace(nursd_plan* p) {
+    size_t o = 0;
+    const size_t c8 = sizeof(float2);
+    p->off_P = o;
+    o = align_up(o + (size_t)p->F * p->L * c8);
+    p->off_T1 = o;
+    o = align_up(o + (size_t)p->FCn * p->M * p->Mf * c8);
+    p->off_U = o;
+    o = align_up(o + (size_t)p->F * p->M * p->M * c8);
+    const size_t planes = (size_t)p->FC * p->ZC;
+    p->off_Bt = o;
+    o = align_up(o + planes * (p->M / 2 + 1) * p->BS * c8);
+    p->off_Yt = o;
+    o = align_up(o + planes * p->ny * p->M * c8);
+    p->off_V = o;
+    o = align_up(o + (size_t)p->nvox() * c8);
+    p->ws_bytes = o;
+}
+
+int check_ws(const nursd_plan* p, void* ws, size_t bytes) {
+    if (!ws) return fail(NURSD_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(NURSD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (bytes < p->ws_bytes)
+        return fail(NURSD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->ws_bytes) + " bytes");
+    return NURSD_OK;
+}
+
+ChunkGeom chunk_geom(const nursd_plan* p, int b0, int nb, int z0, int nzc) {
+    ChunkGeom g;
+    g.b0 = b0;
+    g.nb = nb;
+    g.z0 = z0;
+    g.nzc = nzc;
+    g.f = p->d_f;
+    g.z = p->d_z;
+    g.pitch_x = p->d_px;
+    g.pitch_y = p->d_py;
+    g.dx = p->dx;
+    g.dy = p->dy;
+    return g;
+}
+
+int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_t s) {
+    for (int b0 = 0; b0 < p->F; b0 += p->FCn) {
+        const int nb = std::min(p->FCn, p->F - b0);
+        SpreadArgs sa{};
+        sa.P = P;
+        sa.ent = p->d_ent;
+        sa.band_ptr = p->d_band_ptr;
+        sa.T1 = reinterpret_cast<float2*>(ws + p->off_T1);
+        sa.decx = p->d_decx;
+        sa.tw = p->tw(p->Mf);
+        sa.M = p->M;
+        sa.Mf = p->Mf;
+        sa.L = p->L;
+        sa.w = p->w;
+        sa.beta = (float)p->beta;
+        sa.half_w = 0.5f * p->w;
+        sa.b0 = b0;
+        sa.nb = nb;
+        HIP_TRY(launch_spread_xfft(sa, s));
+        FineYArgs fa{};
+        fa.T1 = sa.T1;
+        fa.U = U;
+        fa.decy = p->d_decy;
+        fa.tw = p->tw(p->Mf);
+        fa.M = p->M;
+        fa.Mf = p->Mf;
+        fa.b0 = b0;
+        fa.nb = nb;
+        HIP_TRY(launch_fine_y(fa, s));
+    }
+    return NURSD_OK;
+}
+
+int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
+    float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
+    float2* Yt = reinterpret_cast<float2*>(ws + p->off_Yt);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            HIP_TRY(launch_kernel_rows(a1, s));
+            P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+            HIP_TRY(launch_propagate_cols(a2, s));
+            P3Args a3{};
+            a3.g = g;
+            a3.Yt = Yt;
+            a3.V = V;
+            a3.I = I;
+            a3.M = p->M;
+            a3.nx = p->nx;
+            a3.ny = p->ny;
+            a3.xc = p->cx;
+            a3.yc = p->cy;
+            a3.xp0 = p->xp[0];
+            a3.xp1 = p->xp[1];
+            a3.xp2 = p->xp[2];
+            a3.first = b0 == 0;
+            a3.last = b0 + nb >= p->F;
+            a3.coherent = p->coherent;
+            a3.tw = p->tw(p->M);
+            HIP_TRY(launch_propagate_rows(a3, s));
+        }
+    }
+    return NURSD_OK;
+}
+
+int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws, hipStream_t s) {
+    if (p->mode != NURSD_MODE_GRID) return fail(NURSD_ERR_UNIMPLEMENTED, "only GRID mode is implemented");
+    float2* U = reinterpret_cast<float2*>(ws + p->off_U);
+    int rc = run_spectrum(p, P, U, ws, s);
+    if (rc) return rc;
+    float2* V = vol ? static_cast<float2*>(vol) : reinterpret_cast<float2*>(ws + p->off_V);
+    if (!p->coherent) V = nullptr;
+    return run_grid_propagation(p, U, V, I, ws, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options* opt) {
+    if (wl) {
+        std::memset(wl, 0, sizeof(*wl));
+        wl->sigma_rel = 0.2;
+        wl->coherent = 1;
+    }
+    if (geo) std::memset(geo, 0, sizeof(*geo));
+    if (opt) {
+        std::memset(opt, 0, sizeof(*opt));
+        opt->pad = 2.0;
+        opt->sigma_os = 2.0;
+        opt->tol = 1e-6;
+    }
+}
+
+int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const nursd_options* opt,
+                      const float* relay_xy_dev, void* stream, nursd_plan** out) {
+    if (!out) return fail(NURSD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!wl || !geo || !opt || !relay_xy_dev) return fail(NURSD_ERR_ARG, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    auto p = new nursd_plan();
+    auto bail = [&](int rc) {
+        delete p;
+        return rc;
+    };
+    // wavelet and frequency bins
+    if (!(wl->lambda_c > 0) || !(wl->dt > 0) || wl->n_time < 2 || wl->n_freq < 1)
+        return bail(fail(NURSD_ERR_ARG, "invalid wavelet parameters"));
+    p->F = wl->n_freq;
+    p->T = wl->n_time;
+    p->lambda_c = wl->lambda_c;
+    p->sigma_rel = wl->sigma_rel;
+    p->dt = wl->dt;
+    p->t0 = wl->t0;
+    p->coherent = wl->coherent ? 1 : 0;
+    const double df = 1.0 / (p->T * p->dt);
+    const double fc = kC / p->lambda_c;
+    if (wl->bins) {
+        p->bins.assign(wl->bins, wl->bins + p->F);
+    } else {
+        const long k0 = std::lround(fc / df);
+        for (int j = 0; j < p->F; ++j) p->bins.push_back((int)(k0 - p->F / 2 + j));
+    }
+    for (int b : p->bins)
+        if (b <= 0 || 2L * b >= p->T) return bail(fail(NURSD_ERR_ARG, "frequency bin outside (0, T/2)"));
+    for (int b : p->bins) p->freqs.push_back(b * df);
+    // geometry
+    p->mode = geo->mode;
+    if (p->mode != NURSD_MODE_GRID && p->mode != NURSD_MODE_POINTS && p->mode != NURSD_MODE_SRSD)
+        return bail(fail(NURSD_ERR_ARG, "unknown mode"));
+    if (geo->nz < 1 || !geo->z) return bail(fail(NURSD_ERR_ARG, "no planes"));
+    p->nz = geo->nz;
+    p->z.assign(geo->z, geo->z + geo->nz);
+    for (double zz : p->z)
+        if (!(zz > 0)) return bail(fail(NURSD_ERR_GEOMETRY, "plane depth must be > 0"));
+    p->x0 = geo->x0;
+    p->y0 = geo->y0;
+    p->vdx = geo->dx;
+    p->vdy = geo->dy;
+    p->nx = geo->nx;
+    p->ny = geo->ny;
+    std::memcpy(p->xp, geo->xp, sizeof(p->xp));
+    if (!(geo->dx > 0) || !(geo->dy > 0)) return bail(fail(NURSD_ERR_ARG, "pitch must be > 0"));
+    if (opt->n_relay < 1) return bail(fail(NURSD_ERR_ARG, "n_relay must be >= 1"));
+    p->L = opt->n_relay;
+    p->pad = opt->pad > 0 ? opt->pad : 2.0;
+    if (opt->sigma_os != 0.0 && opt->sigma_os != 2.0)
+        return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "only NUFFT oversampling 2 is supported"));
+    const double tol = opt->tol > 0 ? opt->tol : 1e-6;
+    p->w = std::min(8, std::max(2, (int)std::ceil(std::log10(1.0 / tol)) + 1));
+    p->beta = 2.30 * p->w;
+
+    std::vector<float> rxy;
+    int rc = read_points(relay_xy_dev, (size_t)p->L * 2, rxy, s);
+    if (rc) return bail(rc);
+    for (float v : rxy)
+        if (!std::isfinite(v)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite relay position"));
+
+    double vlo[2], vhi[2], mmin = 0;
+    if (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_SRSD) {
+        if (p->nx < 1 || p->ny < 1) return bail(fail(NURSD_ERR_ARG, "nx, ny must be >= 1"));
+        p->dx = p->vdx;
+        p->dy = p->vdy;
+        p->cx = p->x0 + (p->nx / 2) * p->dx;
+        p->cy = p->y0 + (p->ny / 2) * p->dy;
+        vlo[0] = p->x0;
+        vlo[1] = p->y0;
+        vhi[0] = p->x0 + (p->nx - 1) * p->dx;
+        vhi[1] = p->y0 + (p->ny - 1) * p->dy;
+        mmin = p->pad * std::max(p->nx, p->ny);
+        if (p->mode == NURSD_MODE_SRSD) {
+            p->zref = geo->zref;
+            for (int i = 0; i < p->nz; ++i) {
+                const double a = geo->alpha ? geo->alpha[i] : geo->zref / p->z[i];
+                if (!(a > 0 && a <= 1)) return bail(fail(NURSD_ERR_GEOMETRY, "SRSD scale alpha must be in (0, 1]"));
+                p->alpha.push_back(a);
+            }
+        }
+    } else {
+        if (!geo->plane_ptr || !geo->voxel_xy_dev) return bail(fail(NURSD_ERR_ARG, "POINTS mode needs plane_ptr and voxel_xy_dev"));
+        p->plane_ptr.assign(geo->plane_ptr, geo->plane_ptr + p->nz + 1);
+        p->voxel_xy_dev = geo->voxel_xy_dev;
+        p->dx = p->vdx;
+        p->dy = p->vdy;
+        const int V = p->plane_ptr.back();
+        std::vector<float> vxy;
+        rc = read_points(geo->voxel_xy_dev, (size_t)V * 2, vxy, s);
+        if (rc) return bail(rc);
+        double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
+        for (int i = 0; i < V; ++i)
+            for (int a = 0; a < 2; ++a) {
+                vlo[a] = std::min(i ? vlo[a] : 1e300, (double)vxy[2 * i + a]);
+                vhi[a] = std::max(i ? vhi[a] : -1e300, (double)vxy[2 * i + a]);
+            }
+        for (int a = 0; a < 2; ++a) {
+            lo[a] = vlo[a];
+            hi[a] = vhi[a];
+        }
+        for (int l = 0; l < p->L; ++l)
+            for (int a = 0; a < 2; ++a) {
+                lo[a] = std::min(lo[a], (double)rxy[2 * l + a]);
+                hi[a] = std::max(hi[a], (double)rxy[2 * l + a]);
+            }
+        p->cx = 0.5 * (lo[0] + hi[0]);
+        p->cy = 0.5 * (lo[1] + hi[1]);
+    }
+    p->M = 0;
+    for (int Mc : kSupportedM) {
+        if (opt->M > 0 && Mc != opt->M) continue;
+        if (Mc >= mmin && frame_fits(Mc, p->dx, p->dy, p->cx, p->cy, rxy, vlo, vhi)) {
+            p->M = Mc;
+            break;
+        }
+    }
+    if (!p->M) {
+        if (opt->M > 0 && !is_pow2(opt->M)) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "M must be a power of two in [16, 1024]"));
+        return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
+    }
+    p->Mf = 2 * p->M;
+    p->BS = (p->M / 2 + 1 + 7) / 8 * 8;
+    if (p->nx * 8 > 4096 && p->mode != NURSD_MODE_POINTS)
+        return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "nx must be <= 512"));
+
+    // chunking: about 128 planes of 512^2 per propagation chunk
+    const long target = std::max(16L, std::min(4096L, 128L * (512L * 512L) / ((long)p->M * p->M)));
+    p->FC = opt->freq_chunk > 0 ? opt->freq_chunk : std::min(p->F, 8);
+    p->FC = std::min(p->FC, p->F);
+    p->ZC = opt->plane_chunk > 0 ? opt->plane_chunk : (int)std::max(1L, target / p->FC);
+    p->ZC = std::min(p->ZC, p->nz);
+    p->FCn = std::min(p->F, 16);
+
+    // device tables
+    {
+        std::vector<float2> tw;
+        for (int n = 0; n < kMaxLog; ++n) {
+            p->tw_off[n] = tw.size();
+            const int N = 1 << n;
+            for (int m = 0; m < N; ++m) {
+                const double a = -2.0 * M_PI * (double)m / N;
+                tw.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+            }
+        }
+        if ((rc = upload(p, tw, &p->tw_all))) return bail(rc);
+    }
+    {
+        std::vector<float2> wt, tb;
+        const double sf = p->sigma_rel * fc;
+        for (int j = 0; j < p->F; ++j) {
+            const double f = p->freqs[j];
+            const double g = std::exp(-(f - fc) * (f - fc) / (2.0 * sf * sf));
+            const double ph = -2.0 * M_PI * std::fmod(f * p->t0, 1.0);
+            wt.push_back(make_float2((float)(g * std::cos(ph)), (float)(g * std::sin(ph))));
+            const double a = -2.0 * M_PI * (double)p->bins[j] / p->T;
+            tb.push_back(make_float2((float)std::cos(a), (float)std::sin(a)));
+        }
+        if ((rc = upload(p, p->bins, &p->d_bins))) return bail(rc);
+        if ((rc = upload(p, wt, &p->d_wt))) return bail(rc);
+        if ((rc = upload(p, tb, &p->d_tb))) return bail(rc);
+        if ((rc = upload(p, p->freqs, &p->d_f))) return bail(rc);
+        if ((rc = upload(p, p->z, &p->d_z))) return bail(rc);
+        if (p->mode == NURSD_MODE_SRSD) {
+            std::vector<double> px, py;
+            for (double a : p->alpha) {
+                px.push_back(p->dx / a);
+                py.push_back(p->dy / a);
+            }
+            if ((rc = upload(p, px, &p->d_px))) return bail(rc);
+            if ((rc = upload(p, py, &p->d_py))) return bail(rc);
+        }
+    }
+    {
+        // deconvolution: phihat(k) = (w/2) int_{-1}^{1} psi(z) cos(pi k w z / Mf) dz
+        std::vector<double> gx, gw;
+        gauss_legendre(128, gx, gw);
+        std::vector<float> decx(p->M), decy(p->M);
+        for (int km = 0; km < p->M; ++km) {
+            const int k = km < p->M / 2 ? km : km - p->M;
+            double s = 0;
+            for (size_t q = 0; q < gx.size(); ++q)
+                s += gw[q] * es_psi(gx[q], p->beta) * std::cos(M_PI * k * p->w * gx[q] / p->Mf);
+            const double ph = 0.5 * p->w * s;
+            const double sgn = (k & 1) ? -1.0 : 1.0;
+            decy[km] = (float)(sgn / ph);
+            decx[km] = (float)(sgn / (ph * (double)p->M * p->M));
+        }
+        if ((rc = upload(p, decx, &p->d_decx))) return bail(rc);
+        if ((rc = upload(p, decy, &p->d_decy))) return bail(rc);
+    }
+    if ((rc = build_spread_lists(p, rxy))) return bail(rc);
+    layout_workspace(p);
+    *out = p;
+    return NURSD_OK;
+}
+
+int nursd_plan_set_points(nursd_plan* p, const float* relay_xy_dev, void* stream) {
+    if (!p || !relay_xy_dev) return fail(NURSD_ERR_ARG, "NULL argument");
+    std::vector<float> rxy;
+    int rc = read_points(relay_xy_dev, (size_t)p->L * 2, rxy, static_cast<hipStream_t>(stream));
+    if (rc) return rc;
+    return build_spread_lists(p, rxy);
+}
+
+int nursd_plan_info(const nursd_plan* p, nursd_plan_info_t* info) {
+    if (!p || !info) return fail(NURSD_ERR_ARG, "NULL argument");
+    info->M = p->M;
+    info->Mf = p->Mf;
+    info->n_freq = p->F;
+    info->n_relay = p->L;
+    info->kernel_width = p->w;
+    info->n_voxels = p->nvox();
+    info->dx = p->dx;
+    info->dy = p->dy;
+    info->cx = p->cx;
+    info->cy = p->cy;
+    info->beta = p->beta;
+    info->workspace_bytes = p->ws_bytes;
+    return NURSD_OK;
+}
+
+int nursd_workspace_size(const nursd_plan* p, size_t* bytes) {
+    if (!p || !bytes) return fail(NURSD_ERR_ARG, "NULL argument");
+    *bytes = p->ws_bytes;
+    return NURSD_OK;
+}
+
+void nursd_plan_destroy(nursd_plan* p) { delete p; }
+
+int nursd_phasor(nursd_plan* p, const float* hist, void* P, void* stream) {
+    if (!p || !hist || !P) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!is_pow2(p->T) || p->T < 256 || p->T > 8192)
+        return fail(NURSD_ERR_UNSUPPORTED_SIZE, "T must be a power of two in [256, 8192]");
+    PhasorArgs a{};
+    a.hist = hist;
+    a.P = static_cast<float2*>(P);
+    a.L = p->L;
+    a.T = p->T;
+    a.F = p->F;
+    a.bins = p->d_bins;
+    a.wt = p->d_wt;
+    a.tb = p->d_tb;
+    a.tw = p->tw(p->T / 2);
+    HIP_TRY(launch_phasor(a, static_cast<hipStream_t>(stream)));
+    return NURSD_OK;
+}
+
+int nursd_spectrum(nursd_plan* p, const void* P, void* U, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !P || !U) return fail(NURSD_ERR_ARG, "NULL argument");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    return run_spectrum(p, static_cast<const float2*>(P), static_cast<float2*>(U), static_cast<char*>(ws),
+                        static_cast<hipStream_t>(stream));
+}
+
+int nursd_forward_phasor(nursd_plan* p, const void* P, void* vol, float* I, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!p || !P) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!vol && !I) return fail(NURSD_ERR_ARG, "vol and I are both NULL");
+    if (!p->coherent && vol) return fail(NURSD_ERR_ARG, "incoherent plans produce intensity only");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    return forward_from_P(p, static_cast<const float2*>(P), vol, I, static_cast<char*>(ws),
+                          static_cast<hipStream_t>(stream));
+}
+
+int nursd_forward_hist(nursd_plan* p, const float* hist, void* vol, float* I, void* ws, size_t ws_bytes,
+                       void* stream) {
+    if (!p || !hist) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!vol && !I) return fail(NURSD_ERR_ARG, "vol and I are both NULL");
+    if (!p->coherent && vol) return fail(NURSD_ERR_ARG, "incoherent plans produce intensity only");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    char* w = static_cast<char*>(ws);
+    float2* P = reinterpret_cast<float2*>(w + p->off_P);
+    if ((rc = nursd_phasor(p, hist, P, stream))) return rc;
+    return forward_from_P(p, P, vol, I, w, static_cast<hipStream_t>(stream));
+}
+
+int nursd_adjoint(nursd_plan*, const void*, const void*, void*, float*, void*, size_t, void*) {
+    return fail(NURSD_ERR_UNIMPLEMENTED, "adjoint not implemented yet");
+}
+
+int nursd_batch_create(nursd_plan* const*, int32_t, int32_t, void*, nursd_batch** out) {
+    if (out) *out = nullptr;
+    return fail(NURSD_ERR_UNIMPLEMENTED, "batched mode not implemented yet");
+}
+
+int nursd_batch_forward(nursd_batch*, const float* const*, float* const*, void*) {
+    return fail(NURSD_ERR_UNIMPLEMENTED, "batched mode not implemented yet");
+}
+
+void nursd_batch_destroy(nursd_batch*) {}
+
+const char* nursd_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Steps 2-3: type-1 NUFFT of the phasors of one frequency onto M x M modes
+// (the three steps of the NUFFT section: spread with a blur kernel onto an
+// oversampled grid, FFT, deconvolve by the kernel's Fourier coefficients).
+//
+// Blur kernel: exponential of semicircle psi(z) = exp(beta (sqrt(1 - z^2) - 1)),
+// |z| <= 1, over w fine cells; oversampling sigma = 2 (fine grid Mf = 2M).
+//
+// k_spread_xfft: one workgroup owns a band of kBandRows fine rows (all Mf
+// columns) of one frequency in LDS.  Relay samples are pre-binned per band
+// and sorted by x; each wavefront owns a disjoint range of columns and walks
+// the samples overlapping it, one sample per step with one lane per kernel
+// tap, so every LDS cell is updated by one wave in a fixed order: no atomics,
+// bitwise reproducible.  The band is then FFT'd along x in LDS and only the
+// M kept modes are written, scaled by the x deconvolution factor.
+// k_fine_y: FFT along y of each kept kx row, keep M modes, deconvolve in y.
+#include "fft.hpp"
+#include "kernels.hpp"
+
+namespace nursd {
+
+constexpr int kSpreadThreads = 1024;
+
+__device__ __forceinline__ float es_kernel(float z, float beta) {
+    const float t = fmaxf(1.0f - z * z, 0.0f);
+    return __expf(beta * (sqrtf(t) - 1.0f));
+}
+
+template <int MF>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
+    constexpr int kBandRows = spread_band_rows(MF);
+    extern __shared__ float2 tile[];   // [kBandRows][MF]
+    const int band = blockIdx.x;
+    const int b = a.b0 + blockIdx.y;
+    const int tid = threadIdx.x;
+    const int e0 = a.band_ptr[band], e1 = a.band_ptr[band + 1];
+    const int M = a.M;
+    const int y0 = band * kBandRows;
+    float2* T1 = a.T1 + (size_t)blockIdx.y * M * MF;
+    if (e0 == e1) {
+        // empty band: its transform is zero
+        for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
+            const int k = i / kBandRows, r = i % kBandRows;
+            T1[(size_t)k * MF + y0 + r] = make_float2(0.f, 0.f);
+        }
+        return;
+    }
+    for (int i = tid; i < kBandRows * MF; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
+    __syncthreads();
+
+    constexpr int kWaves = kSpreadThreads / 64;
+    constexpr int kCols = MF / kWaves;          // columns owned by one wave
+    const int wave = tid >> 6, lane = tid & 63;
+    const int c_lo = wave * kCols, c_hi = c_lo + kCols;
+    const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
+    const float hw = a.half_w;
+    const int w = a.w;
+    // entries are sorted by ix0 within the band: the wave needs
+    // ix0 in [c_lo - w + 1, c_hi - 1]
+    auto lower = [&](int key) {
+        int lo = e0, hi = e1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int)a.ent[mid].ix0 < key) lo = mid + 1; else hi = mid;
+        }
+        return lo;
+    };
+    const int s0 = lower(c_lo - w + 1);
+    const int s1 = lower(c_hi);
+    const float2* Pb = a.P + (size_t)b * a.L;
+    const bool tap_ok = ti < w && tj < w;
+    for (int e = s0; e < s1; ++e) {
+        const SpreadEntry en = a.ent[e];
+        const int cx = (int)en.ix0 + ti, cy = (int)en.iy0 + tj;
+        const float2 p = Pb[en.idx];
+        if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
+            const float wgt = es_kernel(((float)ti - en.fx) / hw, a.beta) *
+                              es_kernel(((float)tj - en.fy) / hw, a.beta);
+            float2* cell = &tile[(cy - y0) * MF + cx];
+            float2 c = *cell;
+            c.x = fmaf(p.x, wgt, c.x);
+            c.y = fmaf(p.y, wgt, c.y);
+            *cell = c;
+        }
+    }
+    __syncthreads();
+    fft_lines<MF, kSpreadThreads / kBandRows, false>(tile, MF, kBandRows, a.tw);
+    // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
+    for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
+        const int km = i / kBandRows, r = i % kBandRows;      // km = kx mod M
+        const int kf = km < M / 2 ? km : km + (MF - M);       // kx mod MF
+        const float2 v = tile[r * MF + kf];
+        T1[(size_t)km * MF + y0 + r] = cscale(v, a.decx[km]);
+    }
+}
+
+constexpr int kFineYThreads = 256;
+constexpr int kFineYLines = 4;
+
+template <int MF>
+__global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
+    extern __shared__ float2 buf[];    // [kFineYLines][MF]
+    const int M = a.M;
+    const int kx0 = blockIdx.x * kFineYLines;
+    const int fb = blockIdx.y;
+    const float2* T1 = a.T1 + (size_t)fb * M * MF;
+    float2* U = a.U + (size_t)(a.b0 + fb) * M * M;
+    const int tid = threadIdx.x;
+    for (int i = tid; i < kFineYLines * MF; i += kFineYThreads) {
+        const int l = i / MF, c = i % MF;
+        buf[i] = T1[(size_t)(kx0 + l) * MF + c];
+    }
+    __syncthreads();
+    fft_lines<MF, kFineYThreads / kFineYLines, false>(buf, MF, kFineYLines, a.tw);
+    for (int i = tid; i < kFineYLines * M; i += kFineYThreads) {
+        const int l = i / M, km = i % M;
+        const int kf = km < M / 2 ? km : km + (MF - M);
+        U[(size_t)(kx0 + l) * M + km] = cscale(buf[l * MF + kf], a.decy[km]);
+    }
+}
+
+template <int MF>
+static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
+    constexpr int kBandRows = spread_band_rows(MF);
+    size_t sh = (size_t)kBandRows * MF * sizeof(float2);
+    hipError_t e = hipFuncSetAttribute((const void*)k_spread_xfft<MF>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_spread_xfft<MF>, dim3(MF / kBandRows, a.nb), dim3(kSpreadThreads), sh, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s) {
+    switch (a.Mf) {
+        case 32: return spread_impl<32>(a, s);
+        case 64: return spread_impl<64>(a, s);
+        case 128: return spread_impl<128>(a, s);
+        case 256: return spread_impl<256>(a, s);
+        case 512: return spread_impl<512>(a, s);
+        case 1024: return spread_impl<1024>(a, s);
+        case 2048: return spread_impl<2048>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MF>
+static hipError_t finey_impl(const FineYArgs& a, hipStream_t s) {
+    size_t sh = (size_t)kFineYLines * MF * sizeof(float2);
+    hipLaunchKernelGGL(k_fine_y<MF>, dim3(a.M / kFineYLines, a.nb), dim3(kFineYThreads), sh, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s) {
+    switch (a.Mf) {
+        case 32: return finey_impl<32>(a, s);
+        case 64: return finey_impl<64>(a, s);
+        case 128: return finey_impl<128>(a, s);
+        case 256: return finey_impl<256>(a, s);
+        case 512: return finey_impl<512>(a, s);
+        case 1024: return finey_impl<1024>(a, s);
+        case 2048: return finey_impl<2048>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nursd

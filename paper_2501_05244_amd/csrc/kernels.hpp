@@ -1,0 +1,110 @@
+// Kernel parameter blocks and launcher declarations shared by the HIP
+// translation units and the host-side C-ABI implementation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace nursd {
+
+constexpr double kC = 299792458.0;   // speed of light [m/s]
+constexpr int kMaxLog = 13;          // twiddle tables for N = 2^0 .. 2^12
+
+// Binned relay sample, one per (sample or periodic image, band) it touches.
+// In centred fine-grid cells the sample sits at (ix0 + fx, iy0 + fy); its
+// w x w taps are cells ix0 .. ix0 + w - 1 (x) and iy0 .. iy0 + w - 1 (y).
+// Splitting the integer base from the fraction keeps the tap offsets exact
+// to float precision on grids of any size.
+struct SpreadEntry {
+    short ix0, iy0;
+    float fx, fy;
+    int idx;     // relay index into P
+};
+
+// Fine-grid rows per spreading band (one band of one frequency fills LDS).
+constexpr int spread_band_rows(int Mf) { return Mf <= 1024 ? 16 : 8; }
+
+struct TwTables {
+    const float2* t[kMaxLog];   // t[n][m] = e^{-2 pi j m / 2^n}
+};
+
+// ---------------------------------------------------------------- step 1
+struct PhasorArgs {
+    const float* hist;     // [L][T]
+    float2* P;             // [F][L]
+    int L, T, F;
+    const int* bins;       // [F]
+    const float2* wt;      // [F] Gaussian weight * e^{-j 2 pi f t0}
+    const float2* tb;      // [F] e^{-j 2 pi b / T}
+    const float2* tw;      // twiddles of size T/2
+};
+hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- steps 2-3
+struct SpreadArgs {
+    const float2* P;              // [F][L] (frequency-major)
+    const SpreadEntry* ent;       // entries sorted by band, then u
+    const int* band_ptr;          // [nbands + 1]
+    float2* T1;                   // [Fc][M][Mf]: x-transformed bands, kx row-major
+    const float* decx;            // [M] (-1)^kx / (phihat(kx) M^2), FFT order
+    const float2* tw;             // twiddles of size Mf
+    int M, Mf, L, w;
+    float beta, half_w;
+    int b0, nb;                   // frequency range of this launch
+};
+hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s);
+
+struct FineYArgs {
+    const float2* T1;             // [Fc][M][Mf]
+    float2* U;                    // [F][M][M] (kx row, ky column, FFT order)
+    const float* decy;            // [M]
+    const float2* tw;             // size Mf
+    int M, Mf;
+    int b0, nb;
+};
+hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- step 4-7
+// Planes of a chunk: plane p -> frequency b = b0 + p / nz_c, depth iz = z0 + p % nz_c.
+struct ChunkGeom {
+    int b0, nb;         // frequency range
+    int z0, nzc;        // plane range
+    const double* f;    // [F] frequencies [Hz]
+    const double* z;    // [Z] depths [m]
+    const double* pitch_x;  // per-plane kernel pitch (SRSD) or NULL (use dx)
+    const double* pitch_y;
+    double dx, dy;      // kernel sampling pitch
+};
+
+struct P1Args {
+    ChunkGeom g;
+    float2* Bt;         // [planes][M/2+1][BS]
+    int M, BS;
+    const float2* tw;   // size M
+};
+hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s);
+
+struct P2Args {
+    ChunkGeom g;
+    const float2* Bt;   // [planes][M/2+1][BS]
+    const float2* U;    // [F][M][M]
+    float2* Yt;         // [planes][ny][M]
+    int M, BS, ny;
+    const float2* tw;
+};
+hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s);
+
+struct P3Args {
+    ChunkGeom g;
+    const float2* Yt;   // [planes][ny][M]
+    float2* V;          // [Z][ny][nx] (may be NULL for incoherent)
+    float* I;           // [Z][ny][nx] or NULL
+    int M, nx, ny;
+    double xc, yc;      // voxel (ix, iy) at (xc + (ix - nx/2) px, yc + (iy - ny/2) py)
+    double xp0, xp1, xp2;
+    int first, last, coherent;
+    const float2* tw;
+};
+hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s);
+
+}  // namespace nursd
