@@ -34,7 +34,7 @@ import math
 import numpy as np
 
 C_LIGHT = 299_792_458.0
-SUPPORTED_M = (16, 32, 64, 128, 256, 512, 1024)
+SUPPORTED_M = (64, 128, 256, 512, 1024)
 
 
 def centered(n: int) -> np.ndarray:

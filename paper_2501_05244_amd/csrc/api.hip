@@ -29,7 +29,7 @@ int fail(int code, const std::string& msg) {
             return fail(NURSD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-constexpr int kSupportedM[] = {16, 32, 64, 128, 256, 512, 1024};
+constexpr int kSupportedM[] = {64, 128, 256, 512, 1024};
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -109,6 +109,7 @@ struct nursd_plan {
     float* d_decy = nullptr;
     SpreadEntry* d_ent = nullptr;
     int* d_band_ptr = nullptr;
+    int* d_wave_rng = nullptr;
     int nbands = 0, n_ent = 0;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
@@ -202,10 +203,24 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
     }
     for (int b = 0; b < p->nbands; ++b) ptr[b + 1] += ptr[b];
     p->n_ent = (int)out.size();
+    // entry range of each spreading wave: taps of entry e reach columns
+    // ix0 .. ix0 + w - 1, so wave columns [c_lo, c_hi) need ix0 in [c_lo - w + 1, c_hi)
+    std::vector<int> rng((size_t)p->nbands * kSpreadWaves * 2);
+    const int cols = Mf / kSpreadWaves;
+    for (int b = 0; b < p->nbands; ++b) {
+        auto first = ents.begin() + ptr[b], last = ents.begin() + ptr[b + 1];
+        for (int wv = 0; wv < kSpreadWaves; ++wv) {
+            const int lo = wv * cols - w + 1, hi = (wv + 1) * cols;
+            auto a = std::lower_bound(first, last, lo, [](const E& e, int v) { return e.ix0 < v; });
+            auto c = std::lower_bound(first, last, hi, [](const E& e, int v) { return e.ix0 < v; });
+            rng[((size_t)b * kSpreadWaves + wv) * 2] = (int)(a - ents.begin());
+            rng[((size_t)b * kSpreadWaves + wv) * 2 + 1] = (int)(c - ents.begin());
+        }
+    }
     if (p->d_ent) {
         // replace previous lists
         for (auto it = p->owned.begin(); it != p->owned.end();) {
-            if (*it == (void*)p->d_ent || *it == (void*)p->d_band_ptr) {
+            if (*it == (void*)p->d_ent || *it == (void*)p->d_band_ptr || *it == (void*)p->d_wave_rng) {
                 (void)hipFree(*it);
                 it = p->owned.erase(it);
             } else {
@@ -214,9 +229,11 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
         }
         p->d_ent = nullptr;
         p->d_band_ptr = nullptr;
+        p->d_wave_rng = nullptr;
     }
     int rc = upload(p, out, &p->d_ent);
     if (rc) return rc;
+    if ((rc = upload(p, rng, &p->d_wave_rng))) return rc;
     return upload(p, ptr, &p->d_band_ptr);
 }
 
@@ -276,6 +293,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
         sa.P = P;
         sa.ent = p->d_ent;
         sa.band_ptr = p->d_band_ptr;
+        sa.wave_rng = p->d_wave_rng;
         sa.T1 = reinterpret_cast<float2*>(ws + p->off_T1);
         sa.decx = p->d_decx;
         sa.tw = p->tw(p->Mf);
@@ -418,6 +436,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     if (opt->n_relay < 1) return bail(fail(NURSD_ERR_ARG, "n_relay must be >= 1"));
     p->L = opt->n_relay;
     p->pad = opt->pad > 0 ? opt->pad : 2.0;
+    if (p->pad < 1.0) return bail(fail(NURSD_ERR_ARG, "pad must be >= 1"));
     if (opt->sigma_os != 0.0 && opt->sigma_os != 2.0)
         return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "only NUFFT oversampling 2 is supported"));
     const double tol = opt->tol > 0 ? opt->tol : 1e-6;
@@ -479,6 +498,8 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         p->cy = 0.5 * (lo[1] + hi[1]);
     }
     p->M = 0;
+    if (opt->M > 0 && std::find(std::begin(kSupportedM), std::end(kSupportedM), opt->M) == std::end(kSupportedM))
+        return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "M must be a power of two in [64, 1024]"));
     for (int Mc : kSupportedM) {
         if (opt->M > 0 && Mc != opt->M) continue;
         if (Mc >= mmin && frame_fits(Mc, p->dx, p->dy, p->cx, p->cy, rxy, vlo, vhi)) {
@@ -486,14 +507,9 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
             break;
         }
     }
-    if (!p->M) {
-        if (opt->M > 0 && !is_pow2(opt->M)) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "M must be a power of two in [16, 1024]"));
-        return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
-    }
+    if (!p->M) return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
     p->Mf = 2 * p->M;
     p->BS = (p->M / 2 + 1 + 7) / 8 * 8;
-    if (p->nx * 8 > 4096 && p->mode != NURSD_MODE_POINTS)
-        return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "nx must be <= 512"));
 
     // chunking: about 128 planes of 512^2 per propagation chunk
     const long target = std::max(16L, std::min(4096L, 128L * (512L * 512L) / ((long)p->M * p->M)));

@@ -47,39 +47,46 @@ __global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
     for (int i = tid; i < kBandRows * MF; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
-    constexpr int kWaves = kSpreadThreads / 64;
-    constexpr int kCols = MF / kWaves;          // columns owned by one wave
+    constexpr int kCols = MF / kSpreadWaves;          // columns owned by one wave
+    static_assert(kSpreadThreads == kSpreadWaves * 64, "one wave per column range");
     const int wave = tid >> 6, lane = tid & 63;
     const int c_lo = wave * kCols, c_hi = c_lo + kCols;
     const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
     const float hw = a.half_w;
     const int w = a.w;
-    // entries are sorted by ix0 within the band: the wave needs
-    // ix0 in [c_lo - w + 1, c_hi - 1]
-    auto lower = [&](int key) {
-        int lo = e0, hi = e1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((int)a.ent[mid].ix0 < key) lo = mid + 1; else hi = mid;
-        }
-        return lo;
-    };
-    const int s0 = lower(c_lo - w + 1);
-    const int s1 = lower(c_hi);
+    const int s0 = a.wave_rng[(band * kSpreadWaves + wave) * 2];
+    const int s1 = a.wave_rng[(band * kSpreadWaves + wave) * 2 + 1];
     const float2* Pb = a.P + (size_t)b * a.L;
     const bool tap_ok = ti < w && tj < w;
-    for (int e = s0; e < s1; ++e) {
-        const SpreadEntry en = a.ent[e];
-        const int cx = (int)en.ix0 + ti, cy = (int)en.iy0 + tj;
-        const float2 p = Pb[en.idx];
-        if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
-            const float wgt = es_kernel(((float)ti - en.fx) / hw, a.beta) *
-                              es_kernel(((float)tj - en.fy) / hw, a.beta);
-            float2* cell = &tile[(cy - y0) * MF + cx];
-            float2 c = *cell;
-            c.x = fmaf(p.x, wgt, c.x);
-            c.y = fmaf(p.y, wgt, c.y);
-            *cell = c;
+    // 64 entries per round trip: each lane fetches one entry and its phasor,
+    // then the wave walks them in order, broadcasting one per step.
+    for (int base = s0; base < s1; base += 64) {
+        const int e = base + lane;
+        int packed = 0;
+        float efx = 0.f, efy = 0.f;
+        float2 ep = make_float2(0.f, 0.f);
+        if (e < s1) {
+            const SpreadEntry en = a.ent[e];
+            packed = ((int)en.ix0 & 0xffff) | ((int)en.iy0 << 16);
+            efx = en.fx;
+            efy = en.fy;
+            ep = Pb[en.idx];
+        }
+        const int cnt = min(64, s1 - base);
+        for (int j = 0; j < cnt; ++j) {
+            const int pk = __shfl(packed, j);
+            const float fx = __shfl(efx, j), fy = __shfl(efy, j);
+            const float px = __shfl(ep.x, j), py = __shfl(ep.y, j);
+            const int cx = (int)(short)(pk & 0xffff) + ti;
+            const int cy = (pk >> 16) + tj;
+            if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
+                const float wgt = es_kernel(((float)ti - fx) / hw, a.beta) * es_kernel(((float)tj - fy) / hw, a.beta);
+                float2* cell = &tile[(cy - y0) * MF + cx];
+                float2 c = *cell;
+                c.x = fmaf(px, wgt, c.x);
+                c.y = fmaf(py, wgt, c.y);
+                *cell = c;
+            }
         }
     }
     __syncthreads();

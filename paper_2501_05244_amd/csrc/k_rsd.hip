@@ -18,13 +18,11 @@
 //       multiply by the illumination phase e^{+j 2 pi f |x_v - x_p| / c}
 //       (FP64 argument) and accumulate over the chunk's frequencies in
 //       registers before one read-modify-write of the volume.
-#include "fft.hpp"
 #include "kernels.hpp"
+#include "wavefft.hpp"
 
 namespace nursd {
 
-constexpr int kRsdThreads = 512;
-constexpr int kRsdLines = 8;
 
 // e^{+j 2 pi (r f / c)} / r for r = sqrt(r2); the cycle count r f / c is
 // formed in FP64 and reduced to [-1/2, 1/2] before the FP32 sin/cos.
@@ -59,10 +57,16 @@ __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int&
     iz = g.z0 + p % g.nzc;
 }
 
+// P1: one wavefront per kernel row my (LPW rows per wave for M < 512).
+constexpr int kP1Waves = 16;
+
 template <int M>
-__global__ __launch_bounds__(kRsdThreads) void k_kernel_rows(P1Args a) {
-    extern __shared__ float2 sm[];      // [kRsdLines][M]
-    constexpr int H = M / 2;
+__global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = F::SCR + 1;
+    extern __shared__ float2 sm[];      // [kP1Waves][SCRP], then twiddles [M]
+    float2* tws = sm + kP1Waves * SCRP;
+    for (int i = threadIdx.x; i < M; i += kP1Waves * 64) tws[i] = a.tw[i];
     const int p = blockIdx.y;
     int b, iz;
     plane_of(a.g, p, b, iz);
@@ -70,168 +74,223 @@ __global__ __launch_bounds__(kRsdThreads) void k_kernel_rows(P1Args a) {
     const double z = a.g.z[iz];
     const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
-    const int my0 = blockIdx.x * kRsdLines;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int my = my0 + wave;
-    float2* line = sm + wave * M;
-    if (my <= H) {
-        const double ry = my * py;
+    constexpr int LB = kP1Waves * LPW;
+    const int my0 = blockIdx.x * LB;
+    float2 v[F::NV];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int my = my0 + wave * LPW + q;
+        const double ry = (my <= H ? my : 0) * py;
         const double ryz = fma(ry, ry, z * z);
-        for (int n = lane; n <= H; n += 64) {
-            const double rx = n * px;
-            const float2 g = rsd_kernel(fma(rx, rx, ryz), foc);
-            line[n] = g;
-            if (n > 0 && n < H) line[M - n] = g;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int n = lane + 64 * e;
+            v[q * E + e] = make_float2(0.f, 0.f);
+            if (my <= H && n <= H) {
+                const double rx = n * px;
+                v[q * E + e] = rsd_kernel(fma(rx, rx, ryz), foc);
+            }
         }
-    } else {
-        for (int n = lane; n < M; n += 64) line[n] = make_float2(0.f, 0.f);
+        // even extension: x[n] = x[M - n] for n > M/2, taken from the lane
+        // that computed M - n (same wave)
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (64 * e + 63 <= H) continue;             // no slot of this e exceeds H
+            const int n = lane + 64 * e;
+            const float2 src = v[q * E + (E - 1 - e >= 0 ? E - 1 - e : 0)];
+            float2 t;
+            t.x = __shfl(src.x, (64 - lane) & 63);
+            t.y = __shfl(src.y, (64 - lane) & 63);
+            if (n > H) v[q * E + e] = (lane == 0) ? v[q * E + (E - e < E ? E - e : 0)] : t;
+        }
     }
+    float2* scr = sm + wave * SCRP;
     __syncthreads();
-    fft_lines<M, 64, false>(sm, M, kRsdLines, a.tw);
+    F::template nat_to_perm<false>(v, scr, tws, lane);
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            if (k <= H) scr[q * (H + 1) + k] = v[h * 8 + d];
+        }
+    __syncthreads();
     float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
-    for (int i = tid; i < (H + 1) * kRsdLines; i += kRsdThreads) {
-        const int kx = i / kRsdLines, l = i % kRsdLines;
-        if (my0 + l <= H) Bt[(size_t)kx * a.BS + my0 + l] = sm[l * M + kx];
+    for (int i = tid; i < (H + 1) * LB; i += kP1Waves * 64) {
+        const int kx = i / LB, j = i % LB;
+        const int my = my0 + j;
+        if (my <= H) Bt[(size_t)kx * a.BS + my] = sm[(j / LPW) * SCRP + (j % LPW) * (H + 1) + kx];
     }
 }
 
+// P2: one wavefront per kx line (LPW lines for M < 512): Ghat along y,
+// times U[+kx] and U[-kx], inverse along y, window rows -> Yt[p][s][iy].
+constexpr int kP2Waves = 8;
+
 template <int M>
-__global__ __launch_bounds__(kRsdThreads) void k_propagate_cols(P2Args a) {
-    extern __shared__ float2 sm[];      // [2 * kRsdLines][M]: +kx lines, then -kx lines
-    constexpr int H = M / 2;
+__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW;
+    extern __shared__ float2 sm[];      // [kP2Waves][SCR], then twiddles [M]
+    float2* tws = sm + kP2Waves * F::SCR;
+    for (int i = threadIdx.x; i < M; i += kP2Waves * 64) tws[i] = a.tw[i];
+    __syncthreads();
     const int p = blockIdx.y;
     int b, iz;
     plane_of(a.g, p, b, iz);
-    const int kx0 = blockIdx.x * kRsdLines;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kx0 = (blockIdx.x * kP2Waves + wave) * LPW;
+    if (kx0 > H) return;                // wave-uniform; no block barriers below
+    float2* scr = sm + wave * F::SCR;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
-    for (int i = tid; i < kRsdLines * M; i += kRsdThreads) {
-        const int l = i / M, n = i % M;
-        const int kx = kx0 + l;
-        const int d = n <= H ? n : M - n;
-        sm[i] = kx <= H ? Bt[(size_t)kx * a.BS + d] : make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-    fft_lines<M, 64, false>(sm, M, kRsdLines, a.tw);          // Ghat[kx][ky]
-    const float2* Ub = a.U + (size_t)b * M * M;
-    for (int i = tid; i < kRsdLines * M; i += kRsdThreads) {
-        const int l = i / M, ky = i % M;
-        const int kx = kx0 + l;
-        if (kx <= H) {
-            const float2 g = sm[i];
-            const int s2 = (M - kx) & (M - 1);
-            sm[(kRsdLines + l) * M + ky] = s2 != kx ? cmul(Ub[(size_t)s2 * M + ky], g) : make_float2(0.f, 0.f);
-            sm[i] = cmul(Ub[(size_t)kx * M + ky], g);
+    float2 v[F::NV], g[F::NV];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int kx = kx0 + q;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int n = lane + 64 * e;
+            const int dd = n <= H ? n : M - n;
+            v[q * E + e] = kx <= H ? Bt[(size_t)kx * a.BS + dd] : make_float2(0.f, 0.f);
         }
     }
-    __syncthreads();
-    fft_lines<M, kRsdThreads / (2 * kRsdLines), true>(sm, M, 2 * kRsdLines, a.tw);
-    float2* Yt = a.Yt + (size_t)p * a.ny * M;
+    F::template nat_to_perm<false>(v, scr, tws, lane);
+#pragma unroll
+    for (int i = 0; i < F::NV; ++i) g[i] = v[i];
+    const float2* Ub = a.U + (size_t)b * M * M;
+    float2* Yp = a.Yt + (size_t)p * M * a.ny;
     const int half = a.ny / 2;
-    for (int i = tid; i < a.ny * 2 * kRsdLines; i += kRsdThreads) {
-        const int iy = i / (2 * kRsdLines), q = i % (2 * kRsdLines);
-        const int l = q % kRsdLines;
-        const int kx = kx0 + l;
-        if (kx > H) continue;
-        const int s = q < kRsdLines ? kx : ((M - kx) & (M - 1));
-        if (q >= kRsdLines && s == kx) continue;
-        const int my = (iy - half) & (M - 1);
-        Yt[(size_t)iy * M + s] = sm[q * M + my];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                const int kx = kx0 + q;
+                const int s = side ? ((M - kx) & (M - 1)) : kx;
+                v[h * 8 + d] = kx <= H ? cmul(Ub[(size_t)s * M + k], g[h * 8 + d]) : make_float2(0.f, 0.f);
+            }
+        F::template perm_to_nat<true>(v, scr, tws, lane);
+#pragma unroll
+        for (int q = 0; q < LPW; ++q) {
+            const int kx = kx0 + q;
+            const int s = side ? ((M - kx) & (M - 1)) : kx;
+            if (kx > H || (side && s == kx)) continue;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int n = lane + 64 * e;
+                const int iy = (n < H ? n : n - M) + half;
+                if (iy >= 0 && iy < a.ny) Yp[(size_t)s * a.ny + iy] = v[q * E + e];
+            }
+        }
     }
 }
 
-constexpr int kP3MaxVox = 8;   // voxels per thread: kRsdLines * nx / kRsdThreads <= 8 (nx <= 512)
+// P3: LPW output rows per wavefront, RB = waves * LPW rows per block; loops
+// over the chunk's frequencies with per-voxel accumulators in registers.
+template <int M>
+constexpr int p3_waves() { return M >= 1024 ? 8 : 16; }
 
 template <int M>
-__global__ __launch_bounds__(kRsdThreads) void k_propagate_rows(P3Args a) {
-    extern __shared__ float2 sm[];      // [kRsdLines][M]
+__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M>();
+    constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
+    constexpr int RB = NW * LPW;
+    extern __shared__ float2 sm[];      // [NW][SCRP], then twiddles [M]
+    float2* tws = sm + NW * SCRP;
+    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
     const int zl = blockIdx.y;
     const int iz = a.g.z0 + zl;
-    const int iy0 = blockIdx.x * kRsdLines;
-    const int tid = threadIdx.x;
-    const int nx = a.nx;
-    const int nvox = kRsdLines * nx;
+    const int iy0 = blockIdx.x * RB;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nx = a.nx, ny = a.ny;
     const double z = a.g.z[iz];
     const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
-    double d[kP3MaxVox];
-    float2 acc[kP3MaxVox];
-    const size_t plane_off = (size_t)iz * a.ny * nx;
+    const size_t plane_off = (size_t)iz * ny * nx;
+    double dist[F::NV];
+    float2 acc[F::NV];
+    int off[F::NV];                     // output offset within the plane, -1 outside the window
 #pragma unroll
-    for (int k = 0; k < kP3MaxVox; ++k) {
-        const int v = tid + k * kRsdThreads;
-        const int l = v / nx, ix = v % nx;
-        const int iy = iy0 + l;
-        acc[k] = make_float2(0.f, 0.f);
-        d[k] = 0.0;
-        if (v < nvox && iy < a.ny) {
-            const double x = a.xc + (ix - nx / 2) * px;
-            const double y = a.yc + (iy - a.ny / 2) * py;
-            d[k] = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
-            if (!a.first) {
-                const size_t o = plane_off + (size_t)iy * nx + ix;
-                if (a.coherent) acc[k] = a.V[o];
-                else acc[k].x = a.I[o];
-            }
-        }
-    }
-    for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
-        const int p = (b - a.g.b0) * a.g.nzc + zl;
-        const float2* Yt = a.Yt + (size_t)p * a.ny * M;
-        for (int i = tid; i < kRsdLines * M; i += kRsdThreads) {
-            const int l = i / M, c = i % M;
-            sm[i] = (iy0 + l < a.ny) ? Yt[(size_t)(iy0 + l) * M + c] : make_float2(0.f, 0.f);
-        }
-        __syncthreads();
-        fft_lines<M, 64, true>(sm, M, kRsdLines, a.tw);
-        const double foc = a.g.f[b] / kC;
+    for (int h = 0; h < F::GPL; ++h)
 #pragma unroll
-        for (int k = 0; k < kP3MaxVox; ++k) {
-            const int v = tid + k * kRsdThreads;
-            if (v < nvox) {
-                const int l = v / nx, ix = v % nx;
-                const float2 val = sm[l * M + ((ix - nx / 2) & (M - 1))];
-                if (a.coherent) {
-                    const float2 ph = phase_of(d[k], foc);
-                    acc[k] = cadd(acc[k], cmul(ph, val));
-                } else {
-                    acc[k].x += sqrtf(val.x * val.x + val.y * val.y);
+        for (int d = 0; d < 8; ++d) {
+            const int sl = h * 8 + d;
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            const int iy = iy0 + wave * LPW + q;
+            const int ix = (k < H ? k : k - M) + nx / 2;
+            off[sl] = (iy < ny && ix >= 0 && ix < nx) ? iy * nx + ix : -1;
+            acc[sl] = make_float2(0.f, 0.f);
+            dist[sl] = 0.0;
+            if (off[sl] >= 0) {
+                const double x = a.xc + (ix - nx / 2) * px;
+                const double y = a.yc + (iy - ny / 2) * py;
+                dist[sl] = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
+                if (!a.first) {
+                    if (a.coherent) acc[sl] = a.V[plane_off + off[sl]];
+                    else acc[sl].x = a.I[plane_off + off[sl]];
                 }
             }
         }
+    float2* rows = sm + wave * SCRP;
+    for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
+        const int p = (b - a.g.b0) * a.g.nzc + zl;
+        const float2* Yp = a.Yt + (size_t)p * M * ny;
         __syncthreads();
+        for (int i = tid; i < M * RB; i += NW * 64) {
+            const int s = i / RB, j = i % RB;
+            const int iy = iy0 + j;
+            sm[(j / LPW) * SCRP + (j % LPW) * M + s] = iy < ny ? Yp[(size_t)s * ny + iy] : make_float2(0.f, 0.f);
+        }
+        __syncthreads();
+        float2 v[F::NV];
+#pragma unroll
+        for (int q = 0; q < LPW; ++q)
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[q * E + e] = rows[q * M + lane + 64 * e];
+        F::template nat_to_perm<true>(v, rows, tws, lane);
+        const double foc = a.g.f[b] / kC;
+#pragma unroll
+        for (int sl = 0; sl < F::NV; ++sl) {
+            if (off[sl] < 0) continue;
+            if (a.coherent) {
+                acc[sl] = cadd(acc[sl], cmul(phase_of(dist[sl], foc), v[sl]));
+            } else {
+                acc[sl].x += sqrtf(v[sl].x * v[sl].x + v[sl].y * v[sl].y);
+            }
+        }
     }
 #pragma unroll
-    for (int k = 0; k < kP3MaxVox; ++k) {
-        const int v = tid + k * kRsdThreads;
-        const int l = v / nx, ix = v % nx;
-        const int iy = iy0 + l;
-        if (v < nvox && iy < a.ny) {
-            const size_t o = plane_off + (size_t)iy * nx + ix;
-            if (a.coherent) {
-                if (a.V) a.V[o] = acc[k];
-                if (a.last && a.I) a.I[o] = sqrtf(acc[k].x * acc[k].x + acc[k].y * acc[k].y);
-            } else {
-                a.I[o] = acc[k].x;
-            }
+    for (int sl = 0; sl < F::NV; ++sl) {
+        if (off[sl] < 0) continue;
+        const size_t o = plane_off + off[sl];
+        if (a.coherent) {
+            a.V[o] = acc[sl];
+            if (a.last && a.I) a.I[o] = sqrtf(acc[sl].x * acc[sl].x + acc[sl].y * acc[sl].y);
+        } else {
+            a.I[o] = acc[sl].x;
         }
     }
 }
 
-template <int M, typename Args>
-static hipError_t launch_rsd(void (*k)(Args), dim3 grid, size_t sh, hipStream_t s, const Args& a) {
+template <typename Args>
+static hipError_t launch_rsd(void (*k)(Args), dim3 grid, int threads, size_t sh, hipStream_t s, const Args& a) {
     if (sh > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k, grid, dim3(kRsdThreads), sh, s, a);
+    hipLaunchKernelGGL(k, grid, dim3(threads), sh, s, a);
     return hipGetLastError();
 }
 
 #define NURSD_SWITCH_M(M_, CALL)                           \
     switch (M_) {                                          \
-        case 16: { constexpr int MM = 16; CALL; }          \
-        case 32: { constexpr int MM = 32; CALL; }          \
         case 64: { constexpr int MM = 64; CALL; }          \
         case 128: { constexpr int MM = 128; CALL; }        \
         case 256: { constexpr int MM = 256; CALL; }        \
@@ -243,24 +302,34 @@ static hipError_t launch_rsd(void (*k)(Args), dim3 grid, size_t sh, hipStream_t 
 hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s) {
     const int planes = a.g.nb * a.g.nzc;
     NURSD_SWITCH_M(a.M, {
-        dim3 grid((MM / 2 + 1 + kRsdLines - 1) / kRsdLines, planes);
-        return launch_rsd<MM>(k_kernel_rows<MM>, grid, (size_t)kRsdLines * MM * sizeof(float2), s, a);
+        using F = WaveFFT<MM>;
+        constexpr int LB = kP1Waves * F::LPW;
+        dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
+        return launch_rsd(k_kernel_rows<MM>, grid, kP1Waves * 64, (size_t)(kP1Waves * (F::SCR + 1) + MM) * sizeof(float2),
+                          s, a);
     })
 }
 
 hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
     const int planes = a.g.nb * a.g.nzc;
     NURSD_SWITCH_M(a.M, {
-        dim3 grid((MM / 2 + 1 + kRsdLines - 1) / kRsdLines, planes);
-        return launch_rsd<MM>(k_propagate_cols<MM>, grid, (size_t)2 * kRsdLines * MM * sizeof(float2), s, a);
+        using F = WaveFFT<MM>;
+        constexpr int LB = kP2Waves * F::LPW;
+        dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
+        return launch_rsd(k_propagate_cols<MM>, grid, kP2Waves * 64, (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s,
+                          a);
     })
 }
 
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
-    if (a.nx * kRsdLines > kP3MaxVox * kRsdThreads) return hipErrorInvalidValue;
+    if (a.nx > a.M / 2 || a.ny > a.M / 2 + 1) return hipErrorInvalidValue;
     NURSD_SWITCH_M(a.M, {
-        dim3 grid((a.ny + kRsdLines - 1) / kRsdLines, a.g.nzc);
-        return launch_rsd<MM>(k_propagate_rows<MM>, grid, (size_t)kRsdLines * MM * sizeof(float2), s, a);
+        using F = WaveFFT<MM>;
+        constexpr int NW = p3_waves<MM>();
+        constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
+        constexpr int RB = NW * F::LPW;
+        dim3 grid((a.ny + RB - 1) / RB, a.g.nzc);
+        return launch_rsd(k_propagate_rows<MM>, grid, NW * 64, (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
     })
 }
 

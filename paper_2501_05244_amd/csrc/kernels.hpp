@@ -23,6 +23,9 @@ struct SpreadEntry {
 
 // Fine-grid rows per spreading band (one band of one frequency fills LDS).
 constexpr int spread_band_rows(int Mf) { return Mf <= 1024 ? 16 : 8; }
+// Wavefronts per spreading workgroup; wave w owns fine columns
+// [w * Mf / kSpreadWaves, (w + 1) * Mf / kSpreadWaves).
+constexpr int kSpreadWaves = 16;
 
 struct TwTables {
     const float2* t[kMaxLog];   // t[n][m] = e^{-2 pi j m / 2^n}
@@ -45,6 +48,7 @@ struct SpreadArgs {
     const float2* P;              // [F][L] (frequency-major)
     const SpreadEntry* ent;       // entries sorted by band, then u
     const int* band_ptr;          // [nbands + 1]
+    const int* wave_rng;          // [nbands][kSpreadWaves][2]: entry range of each wave's columns
     float2* T1;                   // [Fc][M][Mf]: x-transformed bands, kx row-major
     const float* decx;            // [M] (-1)^kx / (phihat(kx) M^2), FFT order
     const float2* tw;             // twiddles of size Mf

@@ -148,9 +148,14 @@ def test_errors_are_reported(device):
     with pytest.raises(RuntimeError, match="ARG"):
         Plan(xy, lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=3, z=[0.2], bins=[0, 3, 4], x0=-0.19,
              y0=-0.13, dx=0.02, dy=0.02, nx=20, ny=13)
-    with pytest.raises(RuntimeError, match="GEOMETRY"):
+    with pytest.raises(RuntimeError, match="UNSUPPORTED_SIZE"):
         Plan(xy, lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=3, z=[0.2], x0=-0.19, y0=-0.13,
-             dx=0.02, dy=0.02, nx=20, ny=13, M=16)
+             dx=0.02, dy=0.02, nx=20, ny=13, M=96)
+    far = xy.clone()
+    far[0, 0] = 5.0
+    with pytest.raises(RuntimeError, match="GEOMETRY"):
+        Plan(far, lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=3, z=[0.2], x0=-0.19, y0=-0.13,
+             dx=0.02, dy=0.02, nx=20, ny=13, M=64)
 
 
 @pytest.mark.slow
