@@ -1,0 +1,192 @@
+"""Benchmark: NURSD reconstruction throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload: the SPAD-scale reconstruction (65,536 relay samples from a 32x32
+SPAD array at 64 oblique poses over 2x2 m, 4,096 bins at 4 ps, 200 points
+and two patches, 6 cm wavelength with 96 frequencies, 256x256x128 voxels,
+FFT size 512).  One step is one full forward from histograms already
+resident in HBM: temporal phasor transform, type-1 NUFFT, per-depth RSD
+propagation of every (frequency, plane) pair, coherent volume and
+intensity.  The metric is voxel-frequency propagations per second
+(256*256*128*96 per step).
+
+Prints one JSON line.  The roofline object describes the dominant kernel,
+timed live with HIP events inside the timed region; cpu_baseline times the
+FP64 oracle on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Non-packed FP32 vector issue rate of MI355X: 256 CUs x 4 SIMDs x 16 lanes x
+# 2 FLOP per FMA x 2.4 GHz (packed FP32 instructions are not used).
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_HBM_GBS = 8000.0
+
+
+def fft_flops(n: int) -> float:
+    return 5.0 * n * math.log2(n)
+
+
+def stage_work(stage: str, info: dict, w) -> tuple[str, float]:
+    """Algorithmic work of one forward for a stage: ('TFLOP', flops) or ('GB', bytes)."""
+    M, Mf, F, L = info["M"], info["Mf"], info["n_freq"], info["n_relay"]
+    g = w.grid
+    Z, nx, ny = len(g.z), g.nx, g.ny
+    planes = F * Z
+    H = M // 2
+    if stage == "propagate_cols":
+        return "flop", planes * ((H + 1 + M) * fft_flops(M) + 6.0 * M * M)
+    if stage == "propagate_rows":
+        return "flop", planes * (ny * fft_flops(M) + 8.0 * nx * ny)
+    if stage == "kernel_rows":
+        return "flop", planes * (H + 1) * fft_flops(M)
+    if stage == "spread":
+        return "flop", F * (Mf // 2) * fft_flops(Mf)
+    if stage == "phasor":
+        return "byte", float(L * w.wavelet.n_time * 4 + F * L * 8)
+    if stage == "fine_y":
+        return "byte", float(F * M * Mf * 8 + F * M * M * 8)
+    return "flop", 0.0
+
+
+def cpu_baseline(w, hist, threads: int) -> dict:
+    """Oracle (FP64, numpy) on 8 of the 96 frequencies and 8 of the 128 planes,
+    full 256x256 lateral window, phasor transform included."""
+    from oracle import nursd_ref as o
+    from workloads import scenes
+    wl = w.wavelet
+    bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
+    sel_b = np.arange(4, 96, 12)[:8]
+    sel_z = np.arange(0, 128, 16)[:8]
+    g = w.grid
+    sub = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[sel_z])
+    fr = o.frame_for_workload(w)
+    t = time.perf_counter()
+    wts = o.phasor_weights(f[sel_b], wl.lambda_c, wl.sigma_rel, wl.t0)
+    P = o.temporal_phasor(hist, bins[sel_b], wts)
+    o.nursd_grid(P, w.relay_xy.astype(np.float64), f[sel_b], fr, sub, w.xp)
+    dt = time.perf_counter() - t
+    units = g.nx * g.ny * len(sel_z) * len(sel_b)
+    return {"value": units / dt, "unit": "voxel*freq/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sel_b)} of 96 frequencies x {len(sel_z)} of 128 planes, full 256x256 window; "
+                      f"phasor DFT + direct NUDFT-1 + direct 2D DFTs in float64; {dt:.1f} s"}
+
+
+def load_traffic(stage: str):
+    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
+    summary, if one exists for the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{stage}_spad_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the reconstruction would shard "
+              "by depth plane with no exchange); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2501_05244_amd.api import plan_from_workload
+    from workloads import scenes
+
+    dev = torch.device("cuda:0")
+    w = scenes.config_spad()
+    plan = plan_from_workload(w, dev)
+    hist = torch.from_numpy(w.hist).to(dev)
+    g = w.grid
+    shape = (len(g.z), g.ny, g.nx)
+    V = torch.empty(shape, dtype=torch.complex64, device=dev)
+    I = torch.empty(shape, dtype=torch.float32, device=dev)
+    units = g.nx * g.ny * len(g.z) * plan.F
+
+    for _ in range(args.warmup):
+        plan.forward_hist(hist, out_vol=V, out_I=I)
+    # untimed profiled pass: find the dominant kernel
+    torch.cuda.synchronize()
+    plan.profile_begin()
+    plan.forward_hist(hist, out_vol=V, out_I=I)
+    stages = plan.profile_end()
+    dominant = max(stages, key=lambda k: stages[k][0])
+
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    plan.profile_begin([dominant])
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        plan.forward_hist(hist, out_vol=V, out_I=I)
+    e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dom = plan.profile_end()[dominant]
+    ms = e0.elapsed_time(e1) / args.steps
+    wall_ms = (t1 - t0) * 1e3 / args.steps
+
+    kind, work = stage_work(dominant, plan.info, w)
+    launches_per_step = dom[1] / args.steps
+    avg_launch_ms = dom[0] / dom[1]
+    per_launch = work / launches_per_step
+    if kind == "flop":
+        achieved = per_launch / (avg_launch_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_FP32_TFLOPS, 2),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4)}
+    else:
+        achieved = per_launch / (avg_launch_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(achieved / PEAK_HBM_GBS, 4)}
+    roof["traffic"] = load_traffic(dominant)
+    roof["kernel"] = dominant
+    roof["avg_launch_ms"] = round(avg_launch_ms, 4)
+
+    out = {
+        "metric": "NURSD voxel*freq propagations/s at rel-L2<=1e-4",
+        "value": units / (ms * 1e-3),
+        "unit": "voxel*freq/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "wall_ms_per_step": round(wall_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "spad_L65536_T4096_F96_256x256x128_M512", "relay_samples": w.relay_xy.shape[0],
+                   "time_bins": w.wavelet.n_time, "frequencies": plan.F, "voxels": [g.nx, g.ny, len(g.z)],
+                   "fft_size": plan.M, "complex": "c64 data, f64 phase arguments"},
+        "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = cpu_baseline(w, w.hist, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

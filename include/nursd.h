@@ -189,6 +189,26 @@ int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float*
                         void* stream);
 void nursd_batch_destroy(nursd_batch* batch);
 
+/* Per-kernel timing with HIP events, for profiling and roofline reports.
+ * nursd_profile_begin starts recording an event pair around every launch
+ * of the stages selected by stage_mask (bit i = stage i, NURSD_STAGE_*);
+ * nursd_profile_end waits for the recorded events, writes the summed
+ * milliseconds and the launch count per stage (arrays of NURSD_NUM_STAGES)
+ * and stops recording.  Events are recorded on the stream of each call. */
+#define NURSD_STAGE_PHASOR 0
+#define NURSD_STAGE_SPREAD 1
+#define NURSD_STAGE_FINE_Y 2
+#define NURSD_STAGE_KERNEL_ROWS 3
+#define NURSD_STAGE_PROPAGATE_COLS 4
+#define NURSD_STAGE_PROPAGATE_ROWS 5
+#define NURSD_STAGE_CHIRP_ROWS 6
+#define NURSD_STAGE_RELAY_GRID 7
+#define NURSD_STAGE_TYPE2 8
+#define NURSD_STAGE_ADJOINT 9
+#define NURSD_NUM_STAGES 16
+int nursd_profile_begin(nursd_plan* plan, uint32_t stage_mask);
+int nursd_profile_end(nursd_plan* plan, double* ms, int32_t* calls);
+
 const char* nursd_last_error(void);
 
 #ifdef __cplusplus

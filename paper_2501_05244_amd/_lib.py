@@ -22,6 +22,9 @@ ERRORS = {
     -6: "NURSD_ERR_UNIMPLEMENTED",
 }
 MODE_GRID, MODE_POINTS, MODE_SRSD = 0, 1, 2
+STAGES = ["phasor", "spread", "fine_y", "kernel_rows", "propagate_cols", "propagate_rows", "chirp_rows",
+          "relay_grid", "type2", "adjoint"]
+NUM_STAGES = 16
 
 
 class Wavelet(ctypes.Structure):
@@ -73,6 +76,8 @@ SIGNATURES = {
     "nursd_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
     "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     "nursd_batch_destroy": (None, [c_void_p]),
+    "nursd_profile_begin": (c_int32, [c_void_p, ctypes.c_uint32]),
+    "nursd_profile_end": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "nursd_last_error": (c_char_p, []),
 }
 

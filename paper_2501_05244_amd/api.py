@@ -125,6 +125,17 @@ class Plan:
             return (self.info["n_voxels"],)
         return (self.nz, self.ny, self.nx)
 
+    # ------------------------------------------------------------ profiling
+    def profile_begin(self, stages=None):
+        mask = 0xFFFFFFFF if stages is None else sum(1 << _lib.STAGES.index(n) for n in stages)
+        check(self._lib.nursd_profile_begin(self.handle, mask), "nursd_profile_begin")
+
+    def profile_end(self) -> dict:
+        ms = (c_double * _lib.NUM_STAGES)()
+        calls = (c_int32 * _lib.NUM_STAGES)()
+        check(self._lib.nursd_profile_end(self.handle, ms, calls), "nursd_profile_end")
+        return {n: (ms[i], calls[i]) for i, n in enumerate(_lib.STAGES) if calls[i]}
+
     # ------------------------------------------------------------ entry points
     def set_points(self, relay_xy: torch.Tensor, stream=None):
         _need(relay_xy, torch.float32, (self.L, 2), "relay_xy")

@@ -111,11 +111,17 @@ struct nursd_plan {
     int* d_band_ptr = nullptr;
     int* d_wave_rng = nullptr;
     int nbands = 0, n_ent = 0;
+    // per-kernel event timing
+    uint32_t prof_mask = 0;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_stage;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
 
     ~nursd_plan() {
         for (void* p : owned) (void)hipFree(p);
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
     const float2* tw(int n) const { return tw_all + tw_off[__builtin_ctz((unsigned)n)]; }
     int nvox() const {
@@ -124,6 +130,41 @@ struct nursd_plan {
 };
 
 namespace {
+
+// Launch `call` (a hipError_t expression) for `stage`, bracketed by events
+// when that stage is being profiled.
+int timed(nursd_plan* p, int stage, hipStream_t s, hipError_t (*fn)(const void*, hipStream_t), const void* args) {
+    const bool on = (p->prof_mask >> stage) & 1u;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (on) {
+        while (p->ev_pool.size() < p->ev_used + 2) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            p->ev_pool.push_back(e);
+        }
+        e0 = p->ev_pool[p->ev_used];
+        e1 = p->ev_pool[p->ev_used + 1];
+        HIP_TRY(hipEventRecord(e0, s));
+    }
+    HIP_TRY(fn(args, s));
+    if (on) {
+        HIP_TRY(hipEventRecord(e1, s));
+        p->ev_used += 2;
+        p->ev_stage.push_back(stage);
+    }
+    return NURSD_OK;
+}
+
+template <typename A, hipError_t (*L)(const A&, hipStream_t)>
+hipError_t thunk(const void* a, hipStream_t s) {
+    return L(*static_cast<const A*>(a), s);
+}
+
+#define LAUNCH(p, stage, Args, launcher, args, s)                                   \
+    do {                                                                             \
+        int rc_ = timed(p, stage, s, &thunk<Args, launcher>, &(args));               \
+        if (rc_) return rc_;                                                         \
+    } while (0)
 
 template <typename T>
 int upload(nursd_plan* p, const std::vector<T>& v, T** out) {
@@ -305,7 +346,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
         sa.half_w = 0.5f * p->w;
         sa.b0 = b0;
         sa.nb = nb;
-        HIP_TRY(launch_spread_xfft(sa, s));
+        LAUNCH(p, NURSD_STAGE_SPREAD, SpreadArgs, launch_spread_xfft, sa, s);
         FineYArgs fa{};
         fa.T1 = sa.T1;
         fa.U = U;
@@ -315,7 +356,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
         fa.Mf = p->Mf;
         fa.b0 = b0;
         fa.nb = nb;
-        HIP_TRY(launch_fine_y(fa, s));
+        LAUNCH(p, NURSD_STAGE_FINE_Y, FineYArgs, launch_fine_y, fa, s);
     }
     return NURSD_OK;
 }
@@ -329,9 +370,9 @@ int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, ch
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
             P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
-            HIP_TRY(launch_kernel_rows(a1, s));
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
-            HIP_TRY(launch_propagate_cols(a2, s));
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
             P3Args a3{};
             a3.g = g;
             a3.Yt = Yt;
@@ -349,7 +390,7 @@ int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, ch
             a3.last = b0 + nb >= p->F;
             a3.coherent = p->coherent;
             a3.tw = p->tw(p->M);
-            HIP_TRY(launch_propagate_rows(a3, s));
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
         }
     }
     return NURSD_OK;
@@ -629,7 +670,7 @@ int nursd_phasor(nursd_plan* p, const float* hist, void* P, void* stream) {
     a.wt = p->d_wt;
     a.tb = p->d_tb;
     a.tw = p->tw(p->T / 2);
-    HIP_TRY(launch_phasor(a, static_cast<hipStream_t>(stream)));
+    LAUNCH(p, NURSD_STAGE_PHASOR, PhasorArgs, launch_phasor, a, static_cast<hipStream_t>(stream));
     return NURSD_OK;
 }
 
@@ -679,6 +720,33 @@ int nursd_batch_forward(nursd_batch*, const float* const*, float* const*, void*)
 }
 
 void nursd_batch_destroy(nursd_batch*) {}
+
+int nursd_profile_begin(nursd_plan* p, uint32_t mask) {
+    if (!p) return fail(NURSD_ERR_ARG, "NULL plan");
+    p->prof_mask = mask;
+    p->ev_used = 0;
+    p->ev_stage.clear();
+    return NURSD_OK;
+}
+
+int nursd_profile_end(nursd_plan* p, double* ms, int32_t* calls) {
+    if (!p || !ms || !calls) return fail(NURSD_ERR_ARG, "NULL argument");
+    for (int i = 0; i < NURSD_NUM_STAGES; ++i) {
+        ms[i] = 0.0;
+        calls[i] = 0;
+    }
+    for (size_t i = 0; i < p->ev_stage.size(); ++i) {
+        HIP_TRY(hipEventSynchronize(p->ev_pool[2 * i + 1]));
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, p->ev_pool[2 * i], p->ev_pool[2 * i + 1]));
+        ms[p->ev_stage[i]] += t;
+        calls[p->ev_stage[i]] += 1;
+    }
+    p->prof_mask = 0;
+    p->ev_used = 0;
+    p->ev_stage.clear();
+    return NURSD_OK;
+}
 
 const char* nursd_last_error(void) { return g_err.c_str(); }
 
