@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -62,6 +63,27 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& wts) {
     }
 }
 
+// In-place iterative radix-2 FFT in float64 (plan-time tables only).
+void fft64(std::vector<std::complex<double>>& a) {
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        for (size_t i = 0; i < n; i += len)
+            for (size_t k = 0; k < len / 2; ++k) {
+                const double ang = -2.0 * M_PI * (double)k / (double)len;
+                const std::complex<double> w(std::cos(ang), std::sin(ang));
+                const std::complex<double> u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+    }
+}
+
 double es_psi(double z, double beta) {
     double t = 1.0 - z * z;
     return t <= 0.0 ? 0.0 : std::exp(beta * (std::sqrt(t) - 1.0));
@@ -105,6 +127,8 @@ struct nursd_plan {
     double* d_z = nullptr;
     double* d_px = nullptr;   // per-plane pitch (SRSD)
     double* d_py = nullptr;
+    double* d_alpha = nullptr;
+    float2* d_hhat = nullptr; // [Z][2M] chirp spectra (SRSD)
     float* d_decx = nullptr;
     float* d_decy = nullptr;
     SpreadEntry* d_ent = nullptr;
@@ -118,6 +142,7 @@ struct nursd_plan {
     std::vector<int> ev_stage;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
+    size_t off_Tg = 0, off_u = 0, off_S1 = 0;
 
     ~nursd_plan() {
         for (void* p : owned) (void)hipFree(p);
@@ -301,6 +326,14 @@ void layout_workspace(nursd_plan* p) {
     o = align_up(o + planes * p->ny * p->M * c8);
     p->off_V = o;
     o = align_up(o + (size_t)p->nvox() * c8);
+    if (p->mode == NURSD_MODE_SRSD) {
+        p->off_Tg = o;
+        o = align_up(o + (size_t)p->F * p->M * p->nx * c8);
+        p->off_u = o;
+        o = align_up(o + (size_t)p->F * p->nx * p->nx * c8);
+        p->off_S1 = o;
+        o = align_up(o + planes * p->M * p->nx * c8);
+    }
     p->ws_bytes = o;
 }
 
@@ -361,6 +394,8 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
     return NURSD_OK;
 }
 
+P3Args rows_args(const nursd_plan* p, const ChunkGeom& g, const float2* Yt, float2* V, float* I, int b0, int nb);
+
 int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
     float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
     float2* Yt = reinterpret_cast<float2*>(ws + p->off_Yt);
@@ -373,23 +408,72 @@ int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, ch
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
             LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
-            P3Args a3{};
-            a3.g = g;
-            a3.Yt = Yt;
-            a3.V = V;
-            a3.I = I;
-            a3.M = p->M;
-            a3.nx = p->nx;
-            a3.ny = p->ny;
-            a3.xc = p->cx;
-            a3.yc = p->cy;
-            a3.xp0 = p->xp[0];
-            a3.xp1 = p->xp[1];
-            a3.xp2 = p->xp[2];
-            a3.first = b0 == 0;
-            a3.last = b0 + nb >= p->F;
-            a3.coherent = p->coherent;
-            a3.tw = p->tw(p->M);
+            P3Args a3 = rows_args(p, g, Yt, V, I, b0, nb);
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
+        }
+    }
+    return NURSD_OK;
+}
+
+P3Args rows_args(const nursd_plan* p, const ChunkGeom& g, const float2* Yt, float2* V, float* I, int b0, int nb) {
+    P3Args a3{};
+    a3.g = g;
+    a3.Yt = Yt;
+    a3.V = V;
+    a3.I = I;
+    a3.M = p->M;
+    a3.nx = p->nx;
+    a3.ny = p->ny;
+    a3.xc = p->cx;
+    a3.yc = p->cy;
+    a3.xp0 = p->xp[0];
+    a3.xp1 = p->xp[1];
+    a3.xp2 = p->xp[2];
+    a3.first = b0 == 0;
+    a3.last = b0 + nb >= p->F;
+    a3.coherent = p->coherent;
+    a3.tw = p->tw(p->M);
+    return a3;
+}
+
+int run_srsd(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
+    float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
+    float2* Yt = reinterpret_cast<float2*>(ws + p->off_Yt);
+    float2* u = reinterpret_cast<float2*>(ws + p->off_u);
+    RelayGridArgs ra{};
+    ra.U = U;
+    ra.Tg = reinterpret_cast<float2*>(ws + p->off_Tg);
+    ra.u = u;
+    ra.M = p->M;
+    ra.N = p->nx;
+    ra.b0 = 0;
+    ra.nb = p->F;
+    ra.tw_m = p->tw(p->M);
+    LAUNCH(p, NURSD_STAGE_RELAY_GRID, RelayGridArgs, launch_relay_grid, ra, s);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            ChirpArgs ca{};
+            ca.g = g;
+            ca.u = u;
+            ca.S1t = reinterpret_cast<float2*>(ws + p->off_S1);
+            ca.Bt = Bt;
+            ca.Yt = Yt;
+            ca.M = p->M;
+            ca.N = p->nx;
+            ca.BS = p->BS;
+            ca.ny = p->ny;
+            ca.alpha = p->d_alpha;
+            ca.hhat = p->d_hhat;
+            ca.tw_m = p->tw(p->M);
+            ca.tw_lb = p->tw(2 * p->M);
+            LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, ChirpArgs, launch_chirp_cols, ca, s);
+            P3Args a3 = rows_args(p, g, Yt, V, I, b0, nb);
             LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
         }
     }
@@ -397,12 +481,13 @@ int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, ch
 }
 
 int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws, hipStream_t s) {
-    if (p->mode != NURSD_MODE_GRID) return fail(NURSD_ERR_UNIMPLEMENTED, "only GRID mode is implemented");
+    if (p->mode == NURSD_MODE_POINTS) return fail(NURSD_ERR_UNIMPLEMENTED, "POINTS mode is not implemented yet");
     float2* U = reinterpret_cast<float2*>(ws + p->off_U);
     int rc = run_spectrum(p, P, U, ws, s);
     if (rc) return rc;
     float2* V = vol ? static_cast<float2*>(vol) : reinterpret_cast<float2*>(ws + p->off_V);
     if (!p->coherent) V = nullptr;
+    if (p->mode == NURSD_MODE_SRSD) return run_srsd(p, U, V, I, ws, s);
     return run_grid_propagation(p, U, V, I, ws, s);
 }
 
@@ -551,6 +636,10 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     if (!p->M) return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
     p->Mf = 2 * p->M;
     p->BS = (p->M / 2 + 1 + 7) / 8 * 8;
+    if (p->mode == NURSD_MODE_SRSD) {
+        if (p->nx != p->ny) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a square grid (nx == ny)"));
+        if (p->M < 512) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a transform size M >= 512"));
+    }
 
     // chunking: about 128 planes of 512^2 per propagation chunk
     const long target = std::max(16L, std::min(4096L, 128L * (512L * 512L) / ((long)p->M * p->M)));
@@ -597,6 +686,27 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
             }
             if ((rc = upload(p, px, &p->d_px))) return bail(rc);
             if ((rc = upload(p, py, &p->d_py))) return bail(rc);
+            if ((rc = upload(p, p->alpha, &p->d_alpha))) return bail(rc);
+            // spectra of the Bluestein chirps h'[j] = e^{+j pi alpha (j - D)^2 / M},
+            // j in [-(N-1), M-1] at j mod LB, D = M/2 - N/2, divided by LB (inverse
+            // FFT of the convolution) and by M (each of the two passes carries one
+            // factor of the M^-2 of the final inverse transform)
+            const int M = p->M, N = p->nx, LB = 2 * M, D = M / 2 - N / 2;
+            std::vector<float2> hh((size_t)p->nz * LB);
+            std::vector<std::complex<double>> line(LB);
+            for (int iz = 0; iz < p->nz; ++iz) {
+                std::fill(line.begin(), line.end(), std::complex<double>(0, 0));
+                for (int j = -(N - 1); j <= M - 1; ++j) {
+                    const double dd = (double)(j - D);
+                    const double cyc = std::fmod(p->alpha[iz] * dd * dd / (2.0 * M), 1.0);
+                    line[(j + LB) % LB] = std::polar(1.0, 2.0 * M_PI * cyc);
+                }
+                fft64(line);
+                for (int k = 0; k < LB; ++k)
+                    hh[(size_t)iz * LB + k] = make_float2((float)(line[k].real() / ((double)LB * M)),
+                                                          (float)(line[k].imag() / ((double)LB * M)));
+            }
+            if ((rc = upload(p, hh, &p->d_hhat))) return bail(rc);
         }
     }
     {

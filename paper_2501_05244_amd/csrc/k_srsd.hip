@@ -1,0 +1,320 @@
+// Step 6: scaled RSD (eq. SRSD_conv) with the scaled FFT of eq. SFFT and
+// its chirp-z derivation (eq. RSD_scale, eq. RSD_scaleconv).
+//
+// Per frequency, the uniform relay grid u = crop_{N x N}(IDFT_M(U)) is formed
+// from the type-1 NUFFT spectrum (fusion for non-uniform acquisition):
+//   k_relay_grid_rows: inverse FFT along y of each spectrum row, keep the N
+//                      window rows (transposed store [kx][iy]);
+//   k_relay_grid_cols: inverse FFT along x, keep the N window columns.
+// Per (frequency, plane) with scale alpha:
+//   S[k] = sum_{n in I_N^2} u[n] e^{-2 pi j alpha k.n / M},  k in I_M^2,
+// separable, each 1D pass by Bluestein's identity
+//   alpha k n = alpha/2 (k^2 + n^2 - (k - n)^2):
+//   S[k] = e^{-j pi alpha k^2/M} sum_n (u[n] e^{-j pi alpha n^2/M}) e^{+j pi alpha (k-n)^2/M},
+// a linear convolution done with FFTs of length LB = 2M >= M + N - 1 against
+// the precomputed spectrum of the chirp (one table per plane).  Chirp phase
+// arguments are reduced in FP64 before the FP32 sin/cos.
+//   k_chirp_rows: Bluestein along x for each of the N rows; store transposed
+//                 S1t[p][kx][iy].
+//   k_chirp_cols: Bluestein along y for kx and -kx, multiply by the DCT of the
+//                 kernel sampled at pitch d/alpha (finished from k_kernel_rows
+//                 output, even in kx), inverse FFT along y, keep the window.
+// The x pass of the inverse transform and the volume formation are the
+// uniform-grid k_propagate_rows with per-plane voxel pitch d/alpha.
+#include "kernels.hpp"
+#include "wavefft.hpp"
+
+namespace nursd {
+
+// e^{-j pi alpha n^2 / M} (sgn = -1) or e^{+...} (sgn = +1); FP64 reduction.
+__device__ __forceinline__ float2 chirp(int n, double alpha_over_2M, float sgn) {
+    const double cyc = alpha_over_2M * (double)((long long)n * n);
+    const float fr = (float)(cyc - rint(cyc));
+    float s, c;
+    sincospif(2.0f * fr, &s, &c);
+    return make_float2(c, sgn * s);
+}
+
+constexpr int kGridWaves = 8;
+
+// u-pass 1: Tg[b][kx][iy] = sum_ky Us[b][kx][ky] e^{+2 pi j ky (iy - N/2) / M}
+template <int M>
+__global__ __launch_bounds__(kGridWaves * 64) void k_relay_grid_rows(RelayGridArgs a) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW;
+    extern __shared__ float2 sm[];
+    float2* tws = sm + kGridWaves * F::SCR;
+    for (int i = threadIdx.x; i < M; i += kGridWaves * 64) tws[i] = a.tw_m[i];
+    __syncthreads();
+    const int fb = blockIdx.y;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kx0 = (blockIdx.x * kGridWaves + wave) * LPW;
+    if (kx0 >= M) return;
+    const float2* Ub = a.U + (size_t)(a.b0 + fb) * M * M;
+    float2 v[F::NV];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q * E + e] = Ub[(size_t)(kx0 + q) * M + lane + 64 * e];
+    F::template nat_to_perm<true>(v, sm + wave * F::SCR, tws, lane);
+    float2* T = a.Tg + (size_t)fb * M * a.N;
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            const int iy = (k < H ? k : k - M) + a.N / 2;
+            if (iy >= 0 && iy < a.N) T[(size_t)(kx0 + q) * a.N + iy] = v[h * 8 + d];
+        }
+}
+
+// u-pass 2: u[b][iy][ix] = sum_kx Tg[b][kx][iy] e^{+2 pi j kx (ix - N/2) / M}
+template <int M>
+__global__ __launch_bounds__(kGridWaves * 64) void k_relay_grid_cols(RelayGridArgs a) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW;
+    constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
+    constexpr int RB = kGridWaves * LPW;
+    extern __shared__ float2 sm[];
+    float2* tws = sm + kGridWaves * SCRP;
+    for (int i = threadIdx.x; i < M; i += kGridWaves * 64) tws[i] = a.tw_m[i];
+    const int fb = blockIdx.y;
+    const int iy0 = blockIdx.x * RB;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int N = a.N;
+    const float2* T = a.Tg + (size_t)fb * M * N;
+    for (int i = threadIdx.x; i < M * RB; i += kGridWaves * 64) {
+        const int s = i / RB, j = i % RB;
+        const int iy = iy0 + j;
+        sm[(j / LPW) * SCRP + (j % LPW) * M + s] = iy < N ? T[(size_t)s * N + iy] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* rows = sm + wave * SCRP;
+    float2 v[F::NV];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q)
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[q * E + e] = rows[q * M + lane + 64 * e];
+    F::template nat_to_perm<true>(v, rows, tws, lane);
+    float2* u = a.u + (size_t)(a.b0 + fb) * N * N;
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            const int iy = iy0 + wave * LPW + q;
+            const int ix = (k < H ? k : k - M) + N / 2;
+            if (iy < N && ix >= 0 && ix < N) u[(size_t)iy * N + ix] = v[h * 8 + d];
+        }
+}
+
+// Bluestein on one LB-point line held by a wave.  In: natural layout with the
+// pre-chirped input in [0, N).  Out: natural layout of the convolution.
+template <int M>
+__device__ __forceinline__ void bluestein_line(float2* v, float2* scr, const float2* __restrict__ tw_lb,
+                                               const float2* __restrict__ hhat, int lane) {
+    using B = WaveFFT<2 * M>;
+    B::template nat_to_perm<false>(v, scr, tw_lb, lane);
+#pragma unroll
+    for (int h = 0; h < B::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = B::perm_k(lane, h, d, q);
+            v[h * 8 + d] = cmul(v[h * 8 + d], hhat[k]);
+        }
+    B::template perm_to_nat<true>(v, scr, tw_lb, lane);
+}
+
+constexpr int kChirpWaves = 8;
+
+template <int M>
+__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
+    using B = WaveFFT<2 * M>;
+    constexpr int LB = 2 * M, EB = B::E;
+    constexpr int SCRP = B::SCR + 1;
+    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles [LB]
+    float2* tws = sm + kChirpWaves * SCRP;
+    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws[i] = a.tw_lb[i];
+    __syncthreads();
+    const int p = blockIdx.y;
+    const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int N = a.N;
+    const int iy0 = blockIdx.x * kChirpWaves;
+    const int iy = iy0 + wave;
+    const double ahm = a.alpha[iz] / (2.0 * M);
+    const float2* hhat = a.hhat + (size_t)iz * LB;
+    const float2* urow = a.u + ((size_t)b * N + (iy < N ? iy : 0)) * N;
+    float2 v[B::NV];
+#pragma unroll
+    for (int e = 0; e < EB; ++e) {
+        const int n = lane + 64 * e;
+        v[e] = make_float2(0.f, 0.f);
+        if (iy < N && n < N) v[e] = cmul(urow[n], chirp(n - N / 2, ahm, -1.f));
+    }
+    float2* scr = sm + wave * SCRP;
+    bluestein_line<M>(v, scr, tws, hhat, lane);
+    // outputs k' = lane + 64 e < M: S[k] with k = k' - M/2, stored at kx = k mod M
+    NURSD_WAVE_SYNC();
+#pragma unroll
+    for (int e = 0; e < M / 64; ++e) {
+        const int kp = lane + 64 * e;
+        const int k = kp - M / 2;
+        scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+    }
+    __syncthreads();
+    float2* S1 = a.S1t + (size_t)p * M * N;
+    for (int i = threadIdx.x; i < M * kChirpWaves; i += kChirpWaves * 64) {
+        const int kx = i / kChirpWaves, j = i % kChirpWaves;
+        if (iy0 + j < N) S1[(size_t)kx * N + iy0 + j] = sm[j * SCRP + kx];
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_cols(ChirpArgs a) {
+    using F = WaveFFT<M>;
+    using B = WaveFFT<2 * M>;
+    constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E;
+    static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
+    constexpr int SCRP = B::SCR + 1;
+    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles LB, twiddles M
+    float2* tws_lb = sm + kChirpWaves * SCRP;
+    float2* tws_m = tws_lb + LB;
+    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws_lb[i] = a.tw_lb[i];
+    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws_m[i] = a.tw_m[i];
+    __syncthreads();
+    const int p = blockIdx.y;
+    const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
+    (void)b;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kx = blockIdx.x * kChirpWaves + wave;
+    if (kx > H) return;
+    const int N = a.N;
+    const double ahm = a.alpha[iz] / (2.0 * M);
+    const float2* hhat = a.hhat + (size_t)iz * LB;
+    float2* scr = sm + wave * SCRP;
+    // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows
+    const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
+    float2 g[F::NV];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n = lane + 64 * e;
+        g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
+    }
+    F::template nat_to_perm<false>(g, scr, tws_m, lane);
+    const float2* S1 = a.S1t + (size_t)p * M * N;
+    float2* Yp = a.Yt + (size_t)p * M * a.ny;
+    const int half = a.ny / 2;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int s = side ? ((M - kx) & (M - 1)) : kx;
+        if (side && s == kx) break;
+        float2 v[B::NV];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int n = lane + 64 * e;
+            v[e] = make_float2(0.f, 0.f);
+            if (n < N) v[e] = cmul(S1[(size_t)s * N + n], chirp(n - N / 2, ahm, -1.f));
+        }
+        bluestein_line<M>(v, scr, tws_lb, hhat, lane);
+        // scaled spectrum column S[s][ky] (natural), staged to LDS in FFT order
+        NURSD_WAVE_SYNC();
+#pragma unroll
+        for (int e = 0; e < M / 64; ++e) {
+            const int k = lane + 64 * e - M / 2;
+            scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+        }
+        NURSD_WAVE_SYNC();
+        float2 x[F::NV];
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                x[h * 8 + d] = cmul(scr[k], g[h * 8 + d]);
+            }
+        NURSD_WAVE_SYNC();
+        F::template perm_to_nat<true>(x, scr, tws_m, lane);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int n = lane + 64 * e;
+            const int iyo = (n < H ? n : n - M) + half;
+            if (iyo >= 0 && iyo < a.ny) Yp[(size_t)s * a.ny + iyo] = x[e];
+        }
+    }
+}
+
+template <typename Args>
+static hipError_t launch_k(void (*k)(Args), dim3 grid, int threads, size_t sh, hipStream_t s, const Args& a) {
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, grid, dim3(threads), sh, s, a);
+    return hipGetLastError();
+}
+
+#define NURSD_SWITCH_M2(M_, CALL)                          \
+    switch (M_) {                                          \
+        case 64: { constexpr int MM = 64; CALL; }          \
+        case 128: { constexpr int MM = 128; CALL; }        \
+        case 256: { constexpr int MM = 256; CALL; }        \
+        case 512: { constexpr int MM = 512; CALL; }        \
+        case 1024: { constexpr int MM = 1024; CALL; }      \
+        default: return hipErrorInvalidValue;              \
+    }
+
+hipError_t launch_relay_grid(const RelayGridArgs& a, hipStream_t s) {
+    NURSD_SWITCH_M2(a.M, {
+        using F = WaveFFT<MM>;
+        constexpr int LB = kGridWaves * F::LPW;
+        hipError_t e = launch_k(k_relay_grid_rows<MM>, dim3((MM + LB - 1) / LB, a.nb), kGridWaves * 64,
+                                (size_t)(kGridWaves * F::SCR + MM) * sizeof(float2), s, a);
+        if (e != hipSuccess) return e;
+        constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
+        return launch_k(k_relay_grid_cols<MM>, dim3((a.N + LB - 1) / LB, a.nb), kGridWaves * 64,
+                        (size_t)(kGridWaves * SCRP + MM) * sizeof(float2), s, a);
+    })
+}
+
+hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s) {
+    const int planes = a.g.nb * a.g.nzc;
+    switch (a.M) {
+        case 512: {
+            using B = WaveFFT<1024>;
+            return launch_k(k_chirp_rows<512>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024) * sizeof(float2), s, a);
+        }
+        case 1024: {
+            using B = WaveFFT<2048>;
+            return launch_k(k_chirp_rows<1024>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048) * sizeof(float2), s, a);
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
+    const int planes = a.g.nb * a.g.nzc;
+    switch (a.M) {
+        case 512: {
+            using B = WaveFFT<1024>;
+            return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
+                            s, a);
+        }
+        case 1024: {
+            using B = WaveFFT<2048>;
+            return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
+                            s, a);
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nursd

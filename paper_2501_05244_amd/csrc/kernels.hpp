@@ -111,4 +111,30 @@ struct P3Args {
 };
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s);
 
+// ---------------------------------------------------------------- step 6
+struct RelayGridArgs {
+    const float2* U;        // [F][M][M] spectra (scaled by M^-2)
+    float2* Tg;             // [nb][M][N] scratch
+    float2* u;              // [F][N][N] uniform relay grid
+    int M, N;
+    int b0, nb;
+    const float2* tw_m;
+};
+hipError_t launch_relay_grid(const RelayGridArgs& a, hipStream_t s);
+
+struct ChirpArgs {
+    ChunkGeom g;
+    const float2* u;        // [F][N][N]
+    float2* S1t;            // [planes][M][N] row-scaled spectra, transposed
+    const float2* Bt;       // [planes][M/2+1][BS] kernel quadrant rows (pitch d/alpha)
+    float2* Yt;             // [planes][M][ny]
+    int M, N, BS, ny;
+    const double* alpha;    // [Z]
+    const float2* hhat;     // [Z][2M] chirp spectra / (2M * M)
+    const float2* tw_m;     // twiddles of size M
+    const float2* tw_lb;    // twiddles of size 2M
+};
+hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s);
+hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
+
 }  // namespace nursd
