@@ -129,6 +129,10 @@ struct nursd_plan {
     double* d_py = nullptr;
     double* d_alpha = nullptr;
     float2* d_hhat = nullptr; // [Z][2M] chirp spectra (SRSD)
+    int* d_plane_ptr = nullptr;   // POINTS
+    int* d_row_lo = nullptr;
+    int* d_row_hi = nullptr;
+    int max_vox = 0;
     float* d_decx = nullptr;
     float* d_decy = nullptr;
     SpreadEntry* d_ent = nullptr;
@@ -142,7 +146,7 @@ struct nursd_plan {
     std::vector<int> ev_stage;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
-    size_t off_Tg = 0, off_u = 0, off_S1 = 0;
+    size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_G2 = 0;
 
     ~nursd_plan() {
         for (void* p : owned) (void)hipFree(p);
@@ -324,6 +328,12 @@ void layout_workspace(nursd_plan* p) {
     o = align_up(o + planes * (p->M / 2 + 1) * p->BS * c8);
     p->off_Yt = o;
     o = align_up(o + planes * p->ny * p->M * c8);
+    if (p->mode == NURSD_MODE_POINTS) {
+        p->off_T2 = o;
+        o = align_up(o + planes * p->M * p->Mf * c8);
+        p->off_G2 = o;
+        o = align_up(o + planes * p->Mf * p->Mf * c8);
+    }
     p->off_V = o;
     o = align_up(o + (size_t)p->nvox() * c8);
     if (p->mode == NURSD_MODE_SRSD) {
@@ -480,14 +490,58 @@ int run_srsd(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipS
     return NURSD_OK;
 }
 
+int run_points(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
+    float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            Type2Args t{};
+            t.g = g;
+            t.Bt = Bt;
+            t.U = U;
+            t.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
+            t.G2 = reinterpret_cast<float2*>(ws + p->off_G2);
+            t.V = V;
+            t.I = I;
+            t.dec = p->d_decy;
+            t.tw_m = p->tw(p->M);
+            t.tw_f = p->tw(p->Mf);
+            t.M = p->M;
+            t.Mf = p->Mf;
+            t.BS = p->BS;
+            t.w = p->w;
+            t.beta = (float)p->beta;
+            t.cx = p->cx;
+            t.cy = p->cy;
+            t.xp0 = p->xp[0];
+            t.xp1 = p->xp[1];
+            t.xp2 = p->xp[2];
+            t.plane_ptr = p->d_plane_ptr;
+            t.voxel_xy = p->voxel_xy_dev;
+            t.row_lo = p->d_row_lo;
+            t.row_hi = p->d_row_hi;
+            t.max_vox = p->max_vox;
+            t.first = b0 == 0;
+            t.last = b0 + nb >= p->F;
+            t.coherent = p->coherent;
+            LAUNCH(p, NURSD_STAGE_TYPE2, Type2Args, launch_type2, t, s);
+        }
+    }
+    return NURSD_OK;
+}
+
 int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws, hipStream_t s) {
-    if (p->mode == NURSD_MODE_POINTS) return fail(NURSD_ERR_UNIMPLEMENTED, "POINTS mode is not implemented yet");
     float2* U = reinterpret_cast<float2*>(ws + p->off_U);
     int rc = run_spectrum(p, P, U, ws, s);
     if (rc) return rc;
     float2* V = vol ? static_cast<float2*>(vol) : reinterpret_cast<float2*>(ws + p->off_V);
     if (!p->coherent) V = nullptr;
     if (p->mode == NURSD_MODE_SRSD) return run_srsd(p, U, V, I, ws, s);
+    if (p->mode == NURSD_MODE_POINTS) return run_points(p, U, V, I, ws, s);
     return run_grid_propagation(p, U, V, I, ws, s);
 }
 
@@ -576,6 +630,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if (!std::isfinite(v)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite relay position"));
 
     double vlo[2], vhi[2], mmin = 0;
+    std::vector<float> vxy;
     if (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_SRSD) {
         if (p->nx < 1 || p->ny < 1) return bail(fail(NURSD_ERR_ARG, "nx, ny must be >= 1"));
         p->dx = p->vdx;
@@ -602,7 +657,9 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         p->dx = p->vdx;
         p->dy = p->vdy;
         const int V = p->plane_ptr.back();
-        std::vector<float> vxy;
+        for (int i = 0; i < p->nz; ++i)
+            if (p->plane_ptr[i + 1] < p->plane_ptr[i]) return bail(fail(NURSD_ERR_ARG, "plane_ptr must be non-decreasing"));
+        if (p->plane_ptr[0] != 0 || V < 1) return bail(fail(NURSD_ERR_ARG, "plane_ptr must start at 0 and list voxels"));
         rc = read_points(geo->voxel_xy_dev, (size_t)V * 2, vxy, s);
         if (rc) return bail(rc);
         double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
@@ -640,12 +697,42 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if (p->nx != p->ny) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a square grid (nx == ny)"));
         if (p->M < 512) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a transform size M >= 512"));
     }
+    if (p->mode == NURSD_MODE_POINTS) {
+        if (p->M < 512)
+            return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "voxel lists need a transform size M >= 512 (set options.M)"));
+        // fine rows each plane's interpolation can reach (centred fine cells)
+        std::vector<int> lo(p->nz), hi(p->nz);
+        const double hw = 0.5 * p->w;
+        for (int iz = 0; iz < p->nz; ++iz) {
+            int a = 1 << 30, c = -(1 << 30);
+            for (int v = p->plane_ptr[iz]; v < p->plane_ptr[iz + 1]; ++v) {
+                const double ty = ((double)vxy[2 * v + 1] - p->cy) / p->dy * 2.0 + p->Mf / 2;
+                const int iy0 = (int)std::ceil(ty - hw);
+                a = std::min(a, iy0);
+                c = std::max(c, iy0 + p->w - 1);
+            }
+            if (a > c) {          // empty plane
+                a = 0;
+                c = -1;
+            } else if (c - a + 1 >= p->Mf) {
+                a = 0;
+                c = p->Mf - 1;
+            }
+            lo[iz] = a;
+            hi[iz] = c;
+            p->max_vox = std::max(p->max_vox, p->plane_ptr[iz + 1] - p->plane_ptr[iz]);
+        }
+        if ((rc = upload(p, lo, &p->d_row_lo))) return bail(rc);
+        if ((rc = upload(p, hi, &p->d_row_hi))) return bail(rc);
+        if ((rc = upload(p, p->plane_ptr, &p->d_plane_ptr))) return bail(rc);
+    }
 
     // chunking: about 128 planes of 512^2 per propagation chunk
     const long target = std::max(16L, std::min(4096L, 128L * (512L * 512L) / ((long)p->M * p->M)));
     p->FC = opt->freq_chunk > 0 ? opt->freq_chunk : std::min(p->F, 8);
     p->FC = std::min(p->FC, p->F);
     p->ZC = opt->plane_chunk > 0 ? opt->plane_chunk : (int)std::max(1L, target / p->FC);
+    if (p->mode == NURSD_MODE_POINTS && opt->plane_chunk <= 0) p->ZC = std::max(1, 32 / p->FC);
     p->ZC = std::min(p->ZC, p->nz);
     p->FCn = std::min(p->F, 16);
 

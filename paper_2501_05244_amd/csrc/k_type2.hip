@@ -1,0 +1,235 @@
+// Step 5 for arbitrary voxels (eq. NURSD2 / eq. NURSD3): type-2 NUFFT of
+// X = U_b * Ghat_{b,z} at each plane's voxel list,
+//   F(x_v) = M^-2 sum_{k in I_M^2} U_b[k] Ghat[k] e^{+j k.x~_v},
+// by the reverse of the type-1 steps (NUFFT section): deconvolve by the
+// kernel's Fourier coefficients, zero-pad to the oversampled grid, inverse
+// FFT, interpolate with the same exponential-of-semicircle kernel.
+//   k_type2_cols: Ghat along y (cosine transform of the quadrant rows), times
+//                 U[+kx], U[-kx] and the x and y deconvolution factors
+//                 (with the (-1)^k of the centred fine grid), zero-padded
+//                 Mf-point inverse FFT along y -> T2[p][kx][jy].
+//   k_type2_rows: Mf-point inverse FFT along x of the zero-padded rows
+//                 -> fine grid G2[p][jy][jx] (rows no voxel can reach are
+//                 skipped).
+//   k_type2_interp: per voxel, w x w gather from the fine grid of every
+//                 frequency of the chunk, illumination phase, accumulation.
+#include "kernels.hpp"
+#include "wavefft.hpp"
+
+namespace nursd {
+
+__device__ __forceinline__ float es_w(float z, float beta) {
+    const float t = fmaxf(1.0f - z * z, 0.0f);
+    return __expf(beta * (sqrtf(t) - 1.0f));
+}
+
+constexpr int kT2Waves = 8;
+
+template <int M>
+__global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
+    using F = WaveFFT<M>;
+    using G = WaveFFT<2 * M>;
+    constexpr int H = M / 2, MF = 2 * M, E = F::E, EG = G::E;
+    static_assert(F::LPW == 1, "type-2 output needs M >= 512 per wave line");
+    constexpr int SCRP = G::SCR + 1;
+    extern __shared__ float2 sm[];          // [kT2Waves][SCRP], twiddles M, twiddles MF
+    float2* tws_m = sm + kT2Waves * SCRP;
+    float2* tws_f = tws_m + M;
+    for (int i = threadIdx.x; i < M; i += kT2Waves * 64) tws_m[i] = a.tw_m[i];
+    for (int i = threadIdx.x; i < MF; i += kT2Waves * 64) tws_f[i] = a.tw_f[i];
+    __syncthreads();
+    const int p = blockIdx.y;
+    const int b = a.g.b0 + p / a.g.nzc;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kx = blockIdx.x * kT2Waves + wave;
+    if (kx > H) return;
+    float2* scr = sm + wave * SCRP;
+    const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
+    float2 g[F::NV];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n = lane + 64 * e;
+        g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
+    }
+    F::template nat_to_perm<false>(g, scr, tws_m, lane);
+    const float2* Ub = a.U + (size_t)b * M * M;
+    float2* T2 = a.T2 + (size_t)p * M * MF;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int s = side ? ((M - kx) & (M - 1)) : kx;
+        if (side && s == kx) break;
+        const float dx = a.dec[s];
+        // product in FFT order of M, staged into the zero-padded natural MF line
+        NURSD_WAVE_SYNC();
+        for (int i = lane; i < MF; i += 64) scr[i] = make_float2(0.f, 0.f);
+        NURSD_WAVE_SYNC();
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);      // ky mod M
+                const int kf = k < H ? k : k + (MF - M);     // ky mod MF
+                scr[kf] = cscale(cmul(Ub[(size_t)s * M + k], g[h * 8 + d]), dx * a.dec[k]);
+            }
+        NURSD_WAVE_SYNC();
+        float2 v[G::NV];
+#pragma unroll
+        for (int e = 0; e < EG; ++e) v[e] = scr[lane + 64 * e];
+        G::template nat_to_perm<true>(v, scr, tws_f, lane);
+#pragma unroll
+        for (int h = 0; h < G::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int jy = G::perm_k(lane, h, d, q);
+                T2[(size_t)s * MF + jy] = v[h * 8 + d];
+            }
+    }
+}
+
+constexpr int kT2RowWaves = 8;
+
+template <int M>
+__global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
+    using G = WaveFFT<2 * M>;
+    constexpr int H = M / 2, MF = 2 * M, EG = G::E;
+    constexpr int SCRP = (G::SCR > MF ? G::SCR : MF) + 1;
+    constexpr int RB = kT2RowWaves;
+    extern __shared__ float2 sm[];          // [RB][SCRP], twiddles MF
+    float2* tws = sm + RB * SCRP;
+    for (int i = threadIdx.x; i < MF; i += kT2RowWaves * 64) tws[i] = a.tw_f[i];
+    const int p = blockIdx.y;
+    const int iz = a.g.z0 + p % a.g.nzc;
+    const int jy0 = a.row_lo[iz] + blockIdx.x * RB;
+    if (jy0 > a.row_hi[iz]) return;         // block-uniform
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const float2* T2 = a.T2 + (size_t)p * M * MF;
+    for (int i = threadIdx.x; i < M * RB; i += kT2RowWaves * 64) {
+        const int kx = i / RB, j = i % RB;
+        const int jy = (jy0 + j) & (MF - 1);
+        const int kf = kx < H ? kx : kx + (MF - M);
+        sm[j * SCRP + kf] = T2[(size_t)kx * MF + jy];
+    }
+    for (int i = threadIdx.x; i < (MF - M) * RB; i += kT2RowWaves * 64) {
+        const int kk = i / RB, j = i % RB;
+        sm[j * SCRP + H + kk] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    float2* row = sm + wave * SCRP;
+    float2 v[G::NV];
+#pragma unroll
+    for (int e = 0; e < EG; ++e) v[e] = row[lane + 64 * e];
+    G::template nat_to_perm<true>(v, row, tws, lane);
+    const int jy = (jy0 + wave) & (MF - 1);
+    float2* G2 = a.G2 + ((size_t)p * MF + jy) * MF;
+#pragma unroll
+    for (int h = 0; h < G::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int jx = G::perm_k(lane, h, d, q);
+            G2[jx] = v[h * 8 + d];
+        }
+}
+
+__device__ __forceinline__ double dist3d(double x, double y, double z) {
+    const double d2 = x * x + y * y + z * z;
+    const float d0 = sqrtf((float)d2);
+    return (double)d0 + (d2 - (double)d0 * (double)d0) * (double)(0.5f / d0);
+}
+
+constexpr int kInterpThreads = 256;
+
+__global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
+    const int zl = blockIdx.y;
+    const int iz = a.g.z0 + zl;
+    const int v = a.plane_ptr[iz] + blockIdx.x * kInterpThreads + threadIdx.x;
+    if (v >= a.plane_ptr[iz + 1]) return;
+    const int MF = a.Mf;
+    const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
+    const double z = a.g.z[iz];
+    const double hw = 0.5 * a.w;
+    const double tx = (x - a.cx) / a.g.dx * 2.0 + MF / 2;
+    const double ty = (y - a.cy) / a.g.dy * 2.0 + MF / 2;
+    const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
+    const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
+    float wx[8], wy[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        wx[i] = i < a.w ? es_w(((float)i - fx) / (float)hw, a.beta) : 0.f;
+        wy[i] = i < a.w ? es_w(((float)i - fy) / (float)hw, a.beta) : 0.f;
+    }
+    const double dd = dist3d(x - a.xp0, y - a.xp1, z - a.xp2);
+    float2 acc = make_float2(0.f, 0.f);
+    if (!a.first) {
+        if (a.coherent) acc = a.V[v];
+        else acc.x = a.I[v];
+    }
+    for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
+        const int p = (b - a.g.b0) * a.g.nzc + zl;
+        const float2* G2 = a.G2 + (size_t)p * MF * MF;
+        float2 s = make_float2(0.f, 0.f);
+        for (int j = 0; j < a.w; ++j) {
+            const float2* row = G2 + (size_t)((iy0 + j) & (MF - 1)) * MF;
+            float2 r = make_float2(0.f, 0.f);
+            for (int i = 0; i < a.w; ++i) {
+                const float2 gv = row[(ix0 + i) & (MF - 1)];
+                r.x = fmaf(wx[i], gv.x, r.x);
+                r.y = fmaf(wx[i], gv.y, r.y);
+            }
+            s.x = fmaf(wy[j], r.x, s.x);
+            s.y = fmaf(wy[j], r.y, s.y);
+        }
+        if (a.coherent) {
+            const double cyc = dd * (a.g.f[b] / kC);
+            const float fr = (float)(cyc - rint(cyc));
+            float sn, cs;
+            sincospif(2.0f * fr, &sn, &cs);
+            acc = cadd(acc, cmul(make_float2(cs, sn), s));
+        } else {
+            acc.x += sqrtf(s.x * s.x + s.y * s.y);
+        }
+    }
+    if (a.coherent) {
+        a.V[v] = acc;
+        if (a.last && a.I) a.I[v] = sqrtf(acc.x * acc.x + acc.y * acc.y);
+    } else {
+        a.I[v] = acc.x;
+    }
+}
+
+template <typename Args>
+static hipError_t launch_t2(void (*k)(Args), dim3 grid, int threads, size_t sh, hipStream_t s, const Args& a) {
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, grid, dim3(threads), sh, s, a);
+    return hipGetLastError();
+}
+
+template <int M>
+static hipError_t type2_impl(const Type2Args& a, hipStream_t s) {
+    using G = WaveFFT<2 * M>;
+    const int planes = a.g.nb * a.g.nzc;
+    hipError_t e = launch_t2(k_type2_cols<M>, dim3((M / 2 + 1 + kT2Waves - 1) / kT2Waves, planes), kT2Waves * 64,
+                             (size_t)(kT2Waves * (G::SCR + 1) + M + 2 * M) * sizeof(float2), s, a);
+    if (e != hipSuccess) return e;
+    constexpr int SCRP = (G::SCR > 2 * M ? G::SCR : 2 * M) + 1;
+    e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes), kT2RowWaves * 64,
+                  (size_t)(kT2RowWaves * SCRP + 2 * M) * sizeof(float2), s, a);
+    if (e != hipSuccess) return e;
+    return launch_t2(k_type2_interp, dim3((a.max_vox + kInterpThreads - 1) / kInterpThreads, a.g.nzc),
+                     kInterpThreads, 0, s, a);
+}
+
+hipError_t launch_type2(const Type2Args& a, hipStream_t s) {
+    switch (a.M) {
+        case 512: return type2_impl<512>(a, s);
+        case 1024: return type2_impl<1024>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace nursd

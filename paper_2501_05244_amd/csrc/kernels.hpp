@@ -137,4 +137,29 @@ struct ChirpArgs {
 hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s);
 hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- step 5 (voxel lists)
+struct Type2Args {
+    ChunkGeom g;
+    const float2* Bt;        // [planes][M/2+1][BS]
+    const float2* U;         // [F][M][M]
+    float2* T2;              // [planes][M][Mf]
+    float2* G2;              // [planes][Mf][Mf] oversampled fine grids
+    float2* V;               // [V] or NULL
+    float* I;                // [V] or NULL
+    const float* dec;        // [M] (-1)^k / phihat(k), FFT order
+    const float2* tw_m;
+    const float2* tw_f;
+    int M, Mf, BS, w;
+    float beta;
+    double cx, cy;
+    double xp0, xp1, xp2;
+    const int* plane_ptr;    // [Z+1]
+    const float* voxel_xy;   // [V][2]
+    const int* row_lo;       // [Z] first fine row any voxel of the plane reaches (may be < 0)
+    const int* row_hi;       // [Z] last such row
+    int max_vox;             // largest voxel count of a plane
+    int first, last, coherent;
+};
+hipError_t launch_type2(const Type2Args& a, hipStream_t s);
+
 }  // namespace nursd
