@@ -129,6 +129,9 @@ struct nursd_plan {
     double* d_py = nullptr;
     double* d_alpha = nullptr;
     float2* d_hhat = nullptr; // [Z][2M] chirp spectra (SRSD)
+    float* d_relay = nullptr;     // [L][2] plan-owned copy of the relay positions
+    int relay_row_lo = 0, relay_row_hi = -1;
+    int FC3 = 4;                  // frequencies per adjoint type-2 chunk
     int* d_plane_ptr = nullptr;   // POINTS
     int* d_row_lo = nullptr;
     int* d_row_hi = nullptr;
@@ -146,7 +149,7 @@ struct nursd_plan {
     std::vector<int> ev_stage;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
-    size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_G2 = 0;
+    size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_G2 = 0, off_T3 = 0, off_G3 = 0;
 
     ~nursd_plan() {
         for (void* p : owned) (void)hipFree(p);
@@ -301,8 +304,31 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
         p->d_band_ptr = nullptr;
         p->d_wave_rng = nullptr;
     }
-    int rc = upload(p, out, &p->d_ent);
-    if (rc) return rc;
+    // relay fine rows reached by interpolation (adjoint type-2 at relay points)
+    {
+        int lo = 1 << 30, hi = -(1 << 30);
+        for (int l = 0; l < p->L; ++l) {
+            const double v = ((double)rxy[2 * l + 1] - p->cy) / p->dy * 2.0 + Mf / 2;
+            const int iy0 = (int)std::ceil(v - hw);
+            lo = std::min(lo, iy0);
+            hi = std::max(hi, iy0 + w - 1);
+        }
+        if (hi - lo + 1 >= Mf) {
+            lo = 0;
+            hi = Mf - 1;
+        }
+        p->relay_row_lo = lo;
+        p->relay_row_hi = hi;
+    }
+    int rc;
+    if (!p->d_relay) {
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, (size_t)p->L * 2 * sizeof(float)));
+        p->owned.push_back(d);
+        p->d_relay = static_cast<float*>(d);
+    }
+    HIP_TRY(hipMemcpy(p->d_relay, rxy.data(), (size_t)p->L * 2 * sizeof(float), hipMemcpyHostToDevice));
+    if ((rc = upload(p, out, &p->d_ent))) return rc;
     if ((rc = upload(p, rng, &p->d_wave_rng))) return rc;
     return upload(p, ptr, &p->d_band_ptr);
 }
@@ -336,6 +362,12 @@ void layout_workspace(nursd_plan* p) {
     }
     p->off_V = o;
     o = align_up(o + (size_t)p->nvox() * c8);
+    if (p->mode == NURSD_MODE_GRID && p->coherent) {
+        p->off_T3 = o;
+        o = align_up(o + (size_t)p->FC3 * 3 * p->M * p->Mf * c8);
+        p->off_G3 = o;
+        o = align_up(o + (size_t)p->FC3 * 3 * p->Mf * p->Mf * c8);
+    }
     if (p->mode == NURSD_MODE_SRSD) {
         p->off_Tg = o;
         o = align_up(o + (size_t)p->F * p->M * p->nx * c8);
@@ -903,8 +935,69 @@ int nursd_forward_hist(nursd_plan* p, const float* hist, void* vol, float* I, vo
     return forward_from_P(p, P, vol, I, w, static_cast<hipStream_t>(stream));
 }
 
-int nursd_adjoint(nursd_plan*, const void*, const void*, void*, float*, void*, size_t, void*) {
-    return fail(NURSD_ERR_UNIMPLEMENTED, "adjoint not implemented yet");
+int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad_P, float* grad_xy, void* ws,
+                  size_t ws_bytes, void* stream) {
+    if (!p || !grad_vol || !grad_P) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (grad_xy && !P) return fail(NURSD_ERR_ARG, "the position gradient needs P");
+    if (p->mode != NURSD_MODE_GRID || !p->coherent)
+        return fail(NURSD_ERR_UNSUPPORTED_SIZE, "the adjoint is defined for coherent GRID plans");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    AdjArgs a{};
+    a.gV = static_cast<const float2*>(grad_vol);
+    a.Rt = reinterpret_cast<float2*>(w + p->off_Yt);
+    a.Bt = reinterpret_cast<float2*>(w + p->off_Bt);
+    a.St = reinterpret_cast<float2*>(w + p->off_U);
+    a.T3 = reinterpret_cast<float2*>(w + p->off_T3);
+    a.G3 = reinterpret_cast<float2*>(w + p->off_G3);
+    a.P = static_cast<const float2*>(P);
+    a.grad_P = static_cast<float2*>(grad_P);
+    a.grad_xy = grad_xy;
+    a.relay = p->d_relay;
+    a.tw_m = p->tw(p->M);
+    a.tw_f = p->tw(p->Mf);
+    a.dec = p->d_decy;
+    a.M = p->M;
+    a.Mf = p->Mf;
+    a.BS = p->BS;
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.L = p->L;
+    a.w = p->w;
+    a.beta = (float)p->beta;
+    a.kscale_x = (float)(2.0 * M_PI / (p->M * p->dx));
+    a.kscale_y = (float)(2.0 * M_PI / (p->M * p->dy));
+    a.xc = p->cx;
+    a.yc = p->cy;
+    a.cx = p->cx;
+    a.cy = p->cy;
+    a.xp0 = p->xp[0];
+    a.xp1 = p->xp[1];
+    a.xp2 = p->xp[2];
+    a.relay_row_lo = p->relay_row_lo;
+    a.relay_row_hi = p->relay_row_hi;
+    float2* Bt = const_cast<float2*>(a.Bt);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            a.g = g;
+            a.first = z0 == 0;
+            LAUNCH(p, NURSD_STAGE_ADJOINT, AdjArgs, launch_adjoint_planes, a, s);
+        }
+    }
+    for (int b0 = 0; b0 < p->F; b0 += p->FC3) {
+        const int nb = std::min(p->FC3, p->F - b0);
+        a.g = chunk_geom(p, b0, nb, 0, 1);
+        a.first_b = b0 == 0;
+        LAUNCH(p, NURSD_STAGE_TYPE2, AdjArgs, launch_adjoint_type2, a, s);
+    }
+    return NURSD_OK;
 }
 
 int nursd_batch_create(nursd_plan* const*, int32_t, int32_t, void*, nursd_batch** out) {

@@ -162,4 +162,33 @@ struct Type2Args {
 };
 hipError_t launch_type2(const Type2Args& a, hipStream_t s);
 
+// ---------------------------------------------------------------- step 8
+struct AdjArgs {
+    ChunkGeom g;
+    const float2* gV;        // [Z][ny][nx] upstream gradient
+    float2* Rt;              // [planes][M][ny]
+    const float2* Bt;        // [planes][M/2+1][BS]
+    float2* St;              // [F][M][M] adjoint spectra (FFT order)
+    float2* T3;              // [nb][3][M][Mf]
+    float2* G3;              // [nb][3][Mf][Mf]
+    const float2* P;         // [F][L] (for the position gradient)
+    float2* grad_P;          // [F][L]
+    float* grad_xy;          // [L][2] or NULL
+    const float* relay;      // [L][2]
+    const float2* tw_m;
+    const float2* tw_f;
+    const float* dec;        // [M] (-1)^k / phihat(k)
+    int M, Mf, BS, nx, ny, L, w;
+    float beta;
+    float kscale_x, kscale_y;    // 2 pi / (M dx), 2 pi / (M dy)
+    double xc, yc;           // grid point with index 0 (voxel window centre)
+    double cx, cy;           // frame centre (relay rescaling)
+    double xp0, xp1, xp2;
+    int relay_row_lo, relay_row_hi;
+    int first;               // first plane chunk: St is written, else accumulated
+    int first_b;             // first frequency chunk: grad_xy is written, else accumulated
+};
+hipError_t launch_adjoint_planes(const AdjArgs& a, hipStream_t s);
+hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s);
+
 }  // namespace nursd
