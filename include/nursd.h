@@ -179,14 +179,30 @@ int nursd_adjoint(nursd_plan* plan, const void* grad_vol_dev, const void* P_dev,
                   void* grad_P_dev, float* grad_xy_dev, void* ws_dev, size_t ws_bytes,
                   void* stream);
 
-/* Batched serving: n plans (GRID mode, coherent) run as one captured HIP
- * graph of persistent kernels.  inputs[i] = hist_dev of plan i,
- * outputs[i] = I_dev (float) of plan i.  The batch owns its workspace and
- * graph; nursd_batch_forward launches the graph on `stream`. */
+/* Batched serving of many reconstructions of uneven size (the plans may
+ * differ in relay count, grid, frequency count, wavelength and transform
+ * size).  All n plans (coherent GRID mode, T a power of two) run as one HIP
+ * graph of grouped persistent kernels: each launch serves every plan of one
+ * kernel type and size class, pulling work items from a device queue.
+ * nursd_batch_create copies nothing and launches nothing; the plans must
+ * outlive the batch.  With autotune = 1 the first nursd_batch_forward times
+ * candidate propagation chunk budgets (planes per round) on the real inputs
+ * and keeps the fastest; otherwise a default is used.
+ * nursd_batch_forward: hist_dev[i] = [L_i][T_i] histograms of plan i,
+ * I_dev[i] = [nz][ny][nx] intensity of plan i (float).  The first call
+ * builds the workspace (owned by the batch), captures the graph and
+ * synchronises `stream`; later calls with the same pointers launch the graph
+ * only, new pointers re-upload the work tables (one synchronising copy).
+ * The batch workspace holds every plan's intermediates at once. */
 int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream,
                        nursd_batch** out);
 int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev,
                         void* stream);
+/* Chosen budget, number of grouped launches in the graph, the autotuner's
+ * candidates and their times (ms per batch), workspace bytes.  Arrays may be
+ * NULL; tried / tried_ms need room for 8 entries. */
+int nursd_batch_info(const nursd_batch* batch, int32_t* budget, int32_t* launches, int32_t* n_tried,
+                     int32_t* tried, float* tried_ms, size_t* workspace_bytes);
 void nursd_batch_destroy(nursd_batch* batch);
 
 /* Per-kernel timing with HIP events, for profiling and roofline reports.

@@ -76,6 +76,8 @@ SIGNATURES = {
     "nursd_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
     "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     "nursd_batch_destroy": (None, [c_void_p]),
+    "nursd_batch_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
+                                   POINTER(c_float), POINTER(c_size_t)]),
     "nursd_profile_begin": (c_int32, [c_void_p, ctypes.c_uint32]),
     "nursd_profile_end": (c_int32, [c_void_p, POINTER(c_double), POINTER(c_int32)]),
     "nursd_last_error": (c_char_p, []),

@@ -196,6 +196,49 @@ class Plan:
         return gP, gxy
 
 
+class Batch:
+    """Many GRID plans served by one captured graph of grouped persistent
+    kernels (C handle nursd_batch)."""
+
+    def __init__(self, plans: list[Plan], autotune: bool = True, stream=None):
+        self._lib = _lib.load()
+        self.plans = list(plans)
+        arr = (c_void_p * len(plans))(*[p.handle.value for p in plans])
+        h = c_void_p()
+        check(self._lib.nursd_batch_create(arr, len(plans), 1 if autotune else 0, _stream(stream), byref(h)),
+              "nursd_batch_create")
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            self._lib.nursd_batch_destroy(self.handle)
+            self.handle = None
+
+    def forward(self, hists: list[torch.Tensor], outs: list[torch.Tensor] | None = None, stream=None):
+        if len(hists) != len(self.plans):
+            raise ValueError("one histogram tensor per plan")
+        if outs is None:
+            outs = [torch.empty(p.out_shape(), dtype=torch.float32, device=p.device) for p in self.plans]
+        for p, h, o in zip(self.plans, hists, outs):
+            _need(h, torch.float32, (p.L, p.n_time), "hist")
+            _need(o, torch.float32, p.out_shape(), "I")
+        self._keep = (list(hists), list(outs))
+        hp = (c_void_p * len(hists))(*[h.data_ptr() for h in hists])
+        op = (c_void_p * len(outs))(*[o.data_ptr() for o in outs])
+        check(self._lib.nursd_batch_forward(self.handle, hp, op, _stream(stream)), "nursd_batch_forward")
+        return outs
+
+    def info(self) -> dict:
+        b, nl, nt = c_int32(), c_int32(), c_int32()
+        tried = (c_int32 * 8)()
+        tms = (ctypes.c_float * 8)()
+        wsb = c_size_t()
+        check(self._lib.nursd_batch_info(self.handle, byref(b), byref(nl), byref(nt), tried, tms, byref(wsb)),
+              "nursd_batch_info")
+        return {"budget": b.value, "launches": nl.value, "workspace_bytes": wsb.value,
+                "tried": {tried[i]: tms[i] for i in range(nt.value)}}
+
+
 def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) -> Plan:
     """Plan for a workloads.scenes.Workload (relay positions copied to `device`)."""
     wl, g = w.wavelet, w.grid

@@ -579,6 +579,337 @@ int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws
 
 }  // namespace
 
+
+// ============================================================================
+// Batched serving: many GRID plans in one captured graph of grouped
+// persistent launches.
+// ============================================================================
+__global__ void k_zero_counters(int* c, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = 0;
+}
+
+namespace nursd {
+hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_zero_counters, dim3((n + 255) / 256), dim3(256), 0, s, c, n);
+    return hipGetLastError();
+}
+}  // namespace nursd
+
+enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3 };
+
+struct BatchScene {
+    nursd_plan* p = nullptr;
+    size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0;
+    int ZC = 1, rounds = 1;
+};
+
+struct BatchLaunch {
+    int kind = 0, size = 0, fmax = 0;
+    size_t items = 0, prefix = 0, gridx = 0;   // byte offsets in the table buffer
+    int n = 0, total = 0, counter = 0;
+};
+
+struct nursd_batch {
+    std::vector<BatchScene> sc;
+    int autotune = 0;
+    int budget = 0;                 // planes per round at M = 512 (0 = not chosen yet)
+    std::vector<int> tried;         // candidate budgets and their times
+    std::vector<float> tried_ms;
+    char* ws = nullptr;
+    size_t ws_bytes = 0;
+    char* d_tab = nullptr;
+    size_t tab_cap = 0;
+    void* pinned = nullptr;
+    size_t pinned_cap = 0;
+    std::vector<char> tab;
+    int* d_counters = nullptr;
+    int counters_cap = 0;
+    std::vector<BatchLaunch> launches;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<const float*> hist;
+    std::vector<float*> I;
+    ~nursd_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (ws) (void)hipFree(ws);
+        if (d_tab) (void)hipFree(d_tab);
+        if (pinned) (void)hipHostFree(pinned);
+        if (d_counters) (void)hipFree(d_counters);
+    }
+};
+
+namespace {
+
+template <typename T>
+size_t tab_push(std::vector<char>& tab, const std::vector<T>& v) {
+    size_t off = (tab.size() + 15) / 16 * 16;
+    tab.resize(off + v.size() * sizeof(T));
+    std::memcpy(tab.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+}
+
+int batch_zc(const nursd_plan* p, int budget) {
+    const long per_m = std::max(1L, (long)budget * (512L * 512L) / ((long)p->M * p->M));
+    return (int)std::max(1L, std::min((long)p->nz, per_m / p->F));
+}
+
+// Workspace layout, item tables and launch list for `budget`, with the
+// current input / output pointers baked into the items.
+int batch_build(nursd_batch* bt, int budget) {
+    size_t o = 0;
+    const size_t c8 = sizeof(float2);
+    int max_rounds = 0;
+    for (auto& sc : bt->sc) {
+        nursd_plan* p = sc.p;
+        sc.ZC = batch_zc(p, budget);
+        sc.rounds = (p->nz + sc.ZC - 1) / sc.ZC;
+        max_rounds = std::max(max_rounds, sc.rounds);
+        sc.off_P = o;
+        o = align_up(o + (size_t)p->F * p->L * c8);
+        sc.off_T1 = o;
+        o = align_up(o + (size_t)p->F * p->M * p->Mf * c8);
+        sc.off_U = o;
+        o = align_up(o + (size_t)p->F * p->M * p->M * c8);
+        sc.off_Bt = o;
+        o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
+        sc.off_Yt = o;
+        o = align_up(o + (size_t)p->F * sc.ZC * p->ny * p->M * c8);
+        sc.off_V = o;
+        o = align_up(o + (size_t)p->nvox() * c8);
+    }
+    if (o > bt->ws_bytes) {
+        if (bt->ws) HIP_TRY(hipFree(bt->ws));
+        bt->ws = nullptr;
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, o));
+        bt->ws = static_cast<char*>(d);
+        bt->ws_bytes = o;
+    }
+    char* ws = bt->ws;
+    bt->tab.clear();
+    bt->launches.clear();
+    int counter = 0;
+    // one grouped launch per (kind, size class) over the given items
+    auto add = [&](int kind, int size, int fmax, auto& items, std::vector<int>& gx, std::vector<int>& gy) {
+        if (items.empty()) return;
+        BatchLaunch L;
+        L.kind = kind;
+        L.size = size;
+        L.fmax = fmax;
+        L.n = (int)items.size();
+        std::vector<int> prefix(items.size() + 1, 0);
+        for (size_t i = 0; i < items.size(); ++i) prefix[i + 1] = prefix[i] + gx[i] * gy[i];
+        L.total = prefix.back();
+        L.items = tab_push(bt->tab, items);
+        L.prefix = tab_push(bt->tab, prefix);
+        L.gridx = tab_push(bt->tab, gx);
+        L.counter = counter++;
+        bt->launches.push_back(L);
+    };
+    std::vector<int> sizes;
+    auto classes = [&](auto key) {
+        std::vector<int> v;
+        for (auto& sc : bt->sc) v.push_back(key(sc.p));
+        std::sort(v.begin(), v.end());
+        v.erase(std::unique(v.begin(), v.end()), v.end());
+        return v;
+    };
+    // step 1
+    for (int T : classes([](nursd_plan* p) { return p->T; })) {
+        std::vector<PhasorArgs> it;
+        std::vector<int> gx, gy;
+        int fmax = 0;
+        for (size_t i = 0; i < bt->sc.size(); ++i) {
+            nursd_plan* p = bt->sc[i].p;
+            if (p->T != T) continue;
+            PhasorArgs a{};
+            a.hist = bt->hist[i];
+            a.P = reinterpret_cast<float2*>(ws + bt->sc[i].off_P);
+            a.L = p->L;
+            a.T = p->T;
+            a.F = p->F;
+            a.bins = p->d_bins;
+            a.wt = p->d_wt;
+            a.tb = p->d_tb;
+            a.tw = p->tw(p->T / 2);
+            it.push_back(a);
+            gx.push_back((p->L + phasor_group() - 1) / phasor_group());
+            gy.push_back(1);
+            fmax = std::max(fmax, p->F);
+        }
+        add(BK_PHASOR, T, fmax, it, gx, gy);
+    }
+    // steps 2-3
+    for (int Mf : classes([](nursd_plan* p) { return p->Mf; })) {
+        std::vector<SpreadArgs> it;
+        std::vector<FineYArgs> it2;
+        std::vector<int> gx, gy, gx2, gy2;
+        for (auto& sc : bt->sc) {
+            nursd_plan* p = sc.p;
+            if (p->Mf != Mf) continue;
+            SpreadArgs a{};
+            a.P = reinterpret_cast<float2*>(ws + sc.off_P);
+            a.ent = p->d_ent;
+            a.band_ptr = p->d_band_ptr;
+            a.wave_rng = p->d_wave_rng;
+            a.T1 = reinterpret_cast<float2*>(ws + sc.off_T1);
+            a.decx = p->d_decx;
+            a.tw = p->tw(Mf);
+            a.M = p->M;
+            a.Mf = Mf;
+            a.L = p->L;
+            a.w = p->w;
+            a.beta = (float)p->beta;
+            a.half_w = 0.5f * p->w;
+            a.b0 = 0;
+            a.nb = p->F;
+            it.push_back(a);
+            gx.push_back(p->nbands);
+            gy.push_back(p->F);
+            FineYArgs f{};
+            f.T1 = a.T1;
+            f.U = reinterpret_cast<float2*>(ws + sc.off_U);
+            f.decy = p->d_decy;
+            f.tw = p->tw(Mf);
+            f.M = p->M;
+            f.Mf = Mf;
+            f.b0 = 0;
+            f.nb = p->F;
+            it2.push_back(f);
+            gx2.push_back(p->M / fine_y_lines());
+            gy2.push_back(p->F);
+        }
+        add(BK_SPREAD, Mf, 0, it, gx, gy);
+        add(BK_FINEY, Mf, 0, it2, gx2, gy2);
+    }
+    // steps 4-7, round by round
+    const std::vector<int> Ms = classes([](nursd_plan* p) { return p->M; });
+    for (int r = 0; r < max_rounds; ++r) {
+        for (int M : Ms) {
+            std::vector<P1Args> i1;
+            std::vector<P2Args> i2;
+            std::vector<P3Args> i3;
+            std::vector<int> g1x, g1y, g2x, g2y, g3x, g3y;
+            for (size_t i = 0; i < bt->sc.size(); ++i) {
+                BatchScene& sc = bt->sc[i];
+                nursd_plan* p = sc.p;
+                if (p->M != M || r >= sc.rounds) continue;
+                const int z0 = r * sc.ZC, nzc = std::min(sc.ZC, p->nz - z0);
+                const ChunkGeom g = chunk_geom(p, 0, p->F, z0, nzc);
+                float2* Bt = reinterpret_cast<float2*>(ws + sc.off_Bt);
+                float2* Yt = reinterpret_cast<float2*>(ws + sc.off_Yt);
+                const float2* U = reinterpret_cast<const float2*>(ws + sc.off_U);
+                i1.push_back(P1Args{g, Bt, p->M, p->BS, p->tw(p->M)});
+                g1x.push_back(grid_x_kernel_rows(M));
+                g1y.push_back(p->F * nzc);
+                i2.push_back(P2Args{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)});
+                g2x.push_back(grid_x_propagate_cols(M));
+                g2y.push_back(p->F * nzc);
+                P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I[i], 0, p->F);
+                i3.push_back(a3);
+                const int rb = rows_per_block_propagate(M);
+                g3x.push_back((p->ny + rb - 1) / rb);
+                g3y.push_back(nzc);
+            }
+            add(BK_P1, M, 0, i1, g1x, g1y);
+            add(BK_P2, M, 0, i2, g2x, g2y);
+            add(BK_P3, M, 0, i3, g3x, g3y);
+        }
+    }
+    // upload the tables through pinned staging (same device buffer if it fits)
+    const size_t nb = bt->tab.size();
+    if (nb > bt->tab_cap) {
+        if (bt->d_tab) HIP_TRY(hipFree(bt->d_tab));
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, nb));
+        bt->d_tab = static_cast<char*>(d);
+        bt->tab_cap = nb;
+    }
+    if (nb > bt->pinned_cap) {
+        if (bt->pinned) HIP_TRY(hipHostFree(bt->pinned));
+        HIP_TRY(hipHostMalloc(&bt->pinned, nb, hipHostMallocDefault));
+        bt->pinned_cap = nb;
+    }
+    if (counter > bt->counters_cap) {
+        if (bt->d_counters) HIP_TRY(hipFree(bt->d_counters));
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, (size_t)counter * sizeof(int)));
+        bt->d_counters = static_cast<int*>(d);
+        bt->counters_cap = counter;
+    }
+    return NURSD_OK;
+}
+
+int batch_upload(nursd_batch* bt, hipStream_t s) {
+    std::memcpy(bt->pinned, bt->tab.data(), bt->tab.size());
+    HIP_TRY(hipMemcpyAsync(bt->d_tab, bt->pinned, bt->tab.size(), hipMemcpyHostToDevice, s));
+    // the staging buffer is reused by the next upload only after this copy
+    HIP_TRY(hipStreamSynchronize(s));
+    return NURSD_OK;
+}
+
+template <typename A>
+Group<A> group_of(nursd_batch* bt, const BatchLaunch& L) {
+    Group<A> g;
+    g.items = reinterpret_cast<const A*>(bt->d_tab + L.items);
+    g.prefix = reinterpret_cast<const int*>(bt->d_tab + L.prefix);
+    g.gridx = reinterpret_cast<const int*>(bt->d_tab + L.gridx);
+    g.n = L.n;
+    g.total = L.total;
+    g.counter = bt->d_counters + L.counter;
+    return g;
+}
+
+int batch_enqueue(nursd_batch* bt, hipStream_t s) {
+    HIP_TRY(launch_zero_counters(bt->d_counters, (int)bt->launches.size(), s));
+    for (const BatchLaunch& L : bt->launches) {
+        switch (L.kind) {
+            case BK_PHASOR: HIP_TRY(launch_phasor_grouped(L.size, L.fmax, group_of<PhasorArgs>(bt, L), s)); break;
+            case BK_SPREAD: HIP_TRY(launch_spread_xfft_grouped(L.size, group_of<SpreadArgs>(bt, L), s)); break;
+            case BK_FINEY: HIP_TRY(launch_fine_y_grouped(L.size, group_of<FineYArgs>(bt, L), s)); break;
+            case BK_P1: HIP_TRY(launch_kernel_rows_grouped(L.size, group_of<P1Args>(bt, L), s)); break;
+            case BK_P2: HIP_TRY(launch_propagate_cols_grouped(L.size, group_of<P2Args>(bt, L), s)); break;
+            default: HIP_TRY(launch_propagate_rows_grouped(L.size, group_of<P3Args>(bt, L), s)); break;
+        }
+    }
+    return NURSD_OK;
+}
+
+int batch_capture(nursd_batch* bt) {
+    if (bt->exec) HIP_TRY(hipGraphExecDestroy(bt->exec));
+    if (bt->graph) HIP_TRY(hipGraphDestroy(bt->graph));
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    HIP_TRY(hipStreamBeginCapture(bt->cap, hipStreamCaptureModeThreadLocal));
+    int rc = batch_enqueue(bt, bt->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(bt->cap, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(NURSD_ERR_HIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    bt->graph = g;
+    HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+    return NURSD_OK;
+}
+
+// Build, warm up (uncaptured run: sets kernel attributes), capture.
+int batch_prepare(nursd_batch* bt, int budget, hipStream_t s) {
+    int rc = batch_build(bt, budget);
+    if (rc) return rc;
+    if ((rc = batch_upload(bt, s))) return rc;
+    if ((rc = batch_enqueue(bt, s))) return rc;
+    HIP_TRY(hipStreamSynchronize(s));
+    return batch_capture(bt);
+}
+
+}  // namespace
+
 extern "C" {
 
 void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options* opt) {
@@ -1000,16 +1331,106 @@ int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad
     return NURSD_OK;
 }
 
-int nursd_batch_create(nursd_plan* const*, int32_t, int32_t, void*, nursd_batch** out) {
-    if (out) *out = nullptr;
-    return fail(NURSD_ERR_UNIMPLEMENTED, "batched mode not implemented yet");
+int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream, nursd_batch** out) {
+    (void)stream;
+    if (!out) return fail(NURSD_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plans || n < 1) return fail(NURSD_ERR_ARG, "no plans");
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) return fail(NURSD_ERR_ARG, "NULL plan");
+        if (plans[i]->mode != NURSD_MODE_GRID || !plans[i]->coherent)
+            return fail(NURSD_ERR_UNSUPPORTED_SIZE, "batched mode takes coherent GRID plans");
+        if (!is_pow2(plans[i]->T) || plans[i]->T < 256 || plans[i]->T > 8192)
+            return fail(NURSD_ERR_UNSUPPORTED_SIZE, "T must be a power of two in [256, 8192]");
+    }
+    auto bt = new nursd_batch();
+    for (int i = 0; i < n; ++i) {
+        BatchScene sc;
+        sc.p = plans[i];
+        bt->sc.push_back(sc);
+    }
+    bt->autotune = autotune ? 1 : 0;
+    bt->hist.assign(n, nullptr);
+    bt->I.assign(n, nullptr);
+    hipError_t e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        delete bt;
+        return fail(NURSD_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    }
+    *out = bt;
+    return NURSD_OK;
 }
 
-int nursd_batch_forward(nursd_batch*, const float* const*, float* const*, void*) {
-    return fail(NURSD_ERR_UNIMPLEMENTED, "batched mode not implemented yet");
+int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const* I, void* stream) {
+    if (!bt || !hist || !I) return fail(NURSD_ERR_ARG, "NULL argument");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int n = (int)bt->sc.size();
+    bool changed = false;
+    for (int i = 0; i < n; ++i) {
+        if (!hist[i] || !I[i]) return fail(NURSD_ERR_ARG, "NULL histogram or output pointer");
+        if (hist[i] != bt->hist[i] || I[i] != bt->I[i]) changed = true;
+        bt->hist[i] = hist[i];
+        bt->I[i] = I[i];
+    }
+    int rc;
+    if (!bt->budget) {
+        // choose the propagation chunk budget: measured (autotune) or default
+        const int cands_tune[] = {64, 128, 256, 512};
+        if (bt->autotune) {
+            hipEvent_t e0, e1;
+            HIP_TRY(hipEventCreate(&e0));
+            HIP_TRY(hipEventCreate(&e1));
+            float best = 1e30f;
+            int best_b = 128;
+            for (int c : cands_tune) {
+                if ((rc = batch_prepare(bt, c, s))) return rc;
+                HIP_TRY(hipGraphLaunch(bt->exec, s));
+                HIP_TRY(hipEventRecord(e0, s));
+                for (int k = 0; k < 2; ++k) HIP_TRY(hipGraphLaunch(bt->exec, s));
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                bt->tried.push_back(c);
+                bt->tried_ms.push_back(ms / 2);
+                if (ms < best) {
+                    best = ms;
+                    best_b = c;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            bt->budget = best_b;
+        } else {
+            bt->budget = 128;
+        }
+        if ((rc = batch_prepare(bt, bt->budget, s))) return rc;
+        changed = false;
+    }
+    if (changed) {
+        // same layout, new pointers: rebuild and re-upload the item tables
+        if ((rc = batch_build(bt, bt->budget))) return rc;
+        if ((rc = batch_upload(bt, s))) return rc;
+    }
+    HIP_TRY(hipGraphLaunch(bt->exec, s));
+    return NURSD_OK;
 }
 
-void nursd_batch_destroy(nursd_batch*) {}
+int nursd_batch_info(const nursd_batch* bt, int32_t* budget, int32_t* launches, int32_t* n_tried, int32_t* tried,
+                     float* tried_ms, size_t* workspace_bytes) {
+    if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
+    if (budget) *budget = bt->budget;
+    if (launches) *launches = (int32_t)bt->launches.size();
+    if (n_tried) *n_tried = (int32_t)bt->tried.size();
+    for (size_t i = 0; i < bt->tried.size(); ++i) {
+        if (tried) tried[i] = bt->tried[i];
+        if (tried_ms) tried_ms[i] = bt->tried_ms[i];
+    }
+    if (workspace_bytes) *workspace_bytes = bt->ws_bytes;
+    return NURSD_OK;
+}
+
+void nursd_batch_destroy(nursd_batch* bt) { delete bt; }
 
 int nursd_profile_begin(nursd_plan* p, uint32_t mask) {
     if (!p) return fail(NURSD_ERR_ARG, "NULL plan");

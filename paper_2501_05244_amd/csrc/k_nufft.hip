@@ -15,6 +15,7 @@
 // k_fine_y: FFT along y of each kept kx row, keep M modes, deconvolve in y.
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "persistent.hpp"
 
 namespace nursd {
 
@@ -26,16 +27,16 @@ __device__ __forceinline__ float es_kernel(float z, float beta) {
 }
 
 template <int MF>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
+__device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, int by) {
     constexpr int kBandRows = spread_band_rows(MF);
     extern __shared__ float2 tile[];   // [kBandRows][MF]
-    const int band = blockIdx.x;
-    const int b = a.b0 + blockIdx.y;
+    const int band = bx;
+    const int b = a.b0 + by;
     const int tid = threadIdx.x;
     const int e0 = a.band_ptr[band], e1 = a.band_ptr[band + 1];
     const int M = a.M;
     const int y0 = band * kBandRows;
-    float2* T1 = a.T1 + (size_t)blockIdx.y * M * MF;
+    float2* T1 = a.T1 + (size_t)by * M * MF;
     if (e0 == e1) {
         // empty band: its transform is zero
         for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
@@ -104,11 +105,11 @@ constexpr int kFineYThreads = 256;
 constexpr int kFineYLines = 4;
 
 template <int MF>
-__global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
+__device__ __forceinline__ void fine_y_body(const FineYArgs& a, int bx, int by) {
     extern __shared__ float2 buf[];    // [kFineYLines][MF]
     const int M = a.M;
-    const int kx0 = blockIdx.x * kFineYLines;
-    const int fb = blockIdx.y;
+    const int kx0 = bx * kFineYLines;
+    const int fb = by;
     const float2* T1 = a.T1 + (size_t)fb * M * MF;
     float2* U = a.U + (size_t)(a.b0 + fb) * M * M;
     const int tid = threadIdx.x;
@@ -123,6 +124,45 @@ __global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
         const int kf = km < M / 2 ? km : km + (MF - M);
         U[(size_t)(kx0 + l) * M + km] = cscale(buf[l * MF + kf], a.decy[km]);
     }
+}
+
+template <int MF>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
+    spread_xfft_body<MF>(a, blockIdx.x, blockIdx.y);
+}
+template <int MF>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_grouped(Group<SpreadArgs> g) {
+    persistent_loop(g, [](const SpreadArgs& a, int bx, int by) { spread_xfft_body<MF>(a, bx, by); });
+}
+template <int MF>
+__global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
+    fine_y_body<MF>(a, blockIdx.x, blockIdx.y);
+}
+template <int MF>
+__global__ __launch_bounds__(kFineYThreads) void k_fine_y_grouped(Group<FineYArgs> g) {
+    persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_body<MF>(a, bx, by); });
+}
+
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, size_t sh, int total) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, sh) != hipSuccess) per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    const int g = (per_cu > 0 ? per_cu : 1) * cus;
+    return g < total ? g : total;
+}
+
+template <typename K, typename G>
+static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, hipStream_t s) {
+    if (g.total <= 0) return hipSuccess;
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(persistent_grid(kernel, threads, sh, g.total)), dim3(threads), sh, s, g);
+    return hipGetLastError();
 }
 
 template <int MF>
@@ -168,5 +208,28 @@ hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s) {
         default: return hipErrorInvalidValue;
     }
 }
+
+hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStream_t s) {
+    switch (Mf) {
+#define NURSD_SG(n) \
+    case n: return launch_grouped(k_spread_xfft_grouped<n>, g, kSpreadThreads, \
+                                  (size_t)spread_band_rows(n) * n * sizeof(float2), s);
+        NURSD_SG(128) NURSD_SG(256) NURSD_SG(512) NURSD_SG(1024) NURSD_SG(2048)
+#undef NURSD_SG
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fine_y_grouped(int Mf, const Group<FineYArgs>& g, hipStream_t s) {
+    switch (Mf) {
+#define NURSD_FG(n) \
+    case n: return launch_grouped(k_fine_y_grouped<n>, g, kFineYThreads, (size_t)kFineYLines * n * sizeof(float2), s);
+        NURSD_FG(128) NURSD_FG(256) NURSD_FG(512) NURSD_FG(1024) NURSD_FG(2048)
+#undef NURSD_FG
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int fine_y_lines() { return kFineYLines; }
 
 }  // namespace nursd

@@ -10,6 +10,7 @@
 // HBM-bound: each histogram is read once, F values written per sample.
 #include "fft.hpp"
 #include "kernels.hpp"
+#include "persistent.hpp"
 
 namespace nursd {
 
@@ -17,11 +18,11 @@ constexpr int kPhasorThreads = 256;
 constexpr int kPhasorGroup = 16;   // relay samples per workgroup (coalesced P writes)
 
 template <int TH>
-__global__ __launch_bounds__(kPhasorThreads) void k_phasor(PhasorArgs a) {
+__device__ __forceinline__ void phasor_body(const PhasorArgs& a, int bx) {
     extern __shared__ float2 smem[];
     float2* line = smem;             // [TH]
     float2* out = smem + TH;         // [F][kPhasorGroup]
-    const int l0 = blockIdx.x * kPhasorGroup;
+    const int l0 = bx * kPhasorGroup;
     const int tid = threadIdx.x;
     for (int r = 0; r < kPhasorGroup; ++r) {
         const int l = l0 + r;
@@ -49,6 +50,37 @@ __global__ __launch_bounds__(kPhasorThreads) void k_phasor(PhasorArgs a) {
     }
 }
 
+template <int TH>
+__global__ __launch_bounds__(kPhasorThreads) void k_phasor(PhasorArgs a) {
+    phasor_body<TH>(a, blockIdx.x);
+}
+template <int TH>
+__global__ __launch_bounds__(kPhasorThreads) void k_phasor_grouped(Group<PhasorArgs> g) {
+    persistent_loop(g, [](const PhasorArgs& a, int bx, int) { phasor_body<TH>(a, bx); });
+}
+
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, size_t sh, int total) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, sh) != hipSuccess) per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    const int g = (per_cu > 0 ? per_cu : 1) * cus;
+    return g < total ? g : total;
+}
+
+template <typename K, typename G>
+static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, hipStream_t s) {
+    if (g.total <= 0) return hipSuccess;
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(persistent_grid(kernel, threads, sh, g.total)), dim3(threads), sh, s, g);
+    return hipGetLastError();
+}
+
 hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s) {
     const int TH = a.T / 2;
     dim3 grid((a.L + kPhasorGroup - 1) / kPhasorGroup);
@@ -69,5 +101,18 @@ hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s) {
     }
     return hipGetLastError();
 }
+
+hipError_t launch_phasor_grouped(int T, int F_max, const Group<PhasorArgs>& g, hipStream_t s) {
+    const size_t sh = (size_t)(T / 2 + F_max * kPhasorGroup) * sizeof(float2);
+    switch (T / 2) {
+#define NURSD_PG(n) \
+    case n: return launch_grouped(k_phasor_grouped<n>, g, kPhasorThreads, sh, s);
+        NURSD_PG(128) NURSD_PG(256) NURSD_PG(512) NURSD_PG(1024) NURSD_PG(2048) NURSD_PG(4096)
+#undef NURSD_PG
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int phasor_group() { return kPhasorGroup; }
 
 }  // namespace nursd

@@ -19,6 +19,7 @@
 //       (FP64 argument) and accumulate over the chunk's frequencies in
 //       registers before one read-modify-write of the volume.
 #include "kernels.hpp"
+#include "persistent.hpp"
 #include "wavefft.hpp"
 
 namespace nursd {
@@ -61,13 +62,13 @@ __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int&
 constexpr int kP1Waves = 16;
 
 template <int M>
-__global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
+__device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = F::SCR + 1;
     extern __shared__ float2 sm[];      // [kP1Waves][SCRP], then twiddles [M]
     float2* tws = sm + kP1Waves * SCRP;
     for (int i = threadIdx.x; i < M; i += kP1Waves * 64) tws[i] = a.tw[i];
-    const int p = blockIdx.y;
+    const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
     const double foc = a.g.f[b] / kC;
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int LB = kP1Waves * LPW;
-    const int my0 = blockIdx.x * LB;
+    const int my0 = bx * LB;
     float2 v[F::NV];
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
@@ -130,18 +131,18 @@ __global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
 constexpr int kP2Waves = 8;
 
 template <int M>
-__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
+__device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
     extern __shared__ float2 sm[];      // [kP2Waves][SCR], then twiddles [M]
     float2* tws = sm + kP2Waves * F::SCR;
     for (int i = threadIdx.x; i < M; i += kP2Waves * 64) tws[i] = a.tw[i];
     __syncthreads();
-    const int p = blockIdx.y;
+    const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int kx0 = (blockIdx.x * kP2Waves + wave) * LPW;
+    const int kx0 = (bx * kP2Waves + wave) * LPW;
     if (kx0 > H) return;                // wave-uniform; no block barriers below
     float2* scr = sm + wave * F::SCR;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
@@ -196,7 +197,7 @@ template <int M>
 constexpr int p3_waves() { return M >= 1024 ? 8 : 16; }
 
 template <int M>
-__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a) {
+__device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M>();
     constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
@@ -204,9 +205,9 @@ __global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a)
     extern __shared__ float2 sm[];      // [NW][SCRP], then twiddles [M]
     float2* tws = sm + NW * SCRP;
     for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
-    const int zl = blockIdx.y;
+    const int zl = by;
     const int iz = a.g.z0 + zl;
-    const int iy0 = blockIdx.x * RB;
+    const int iy0 = bx * RB;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int nx = a.nx, ny = a.ny;
     const double z = a.g.z[iz];
@@ -279,6 +280,32 @@ __global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a)
     }
 }
 
+
+template <int M>
+__global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
+    kernel_rows_body<M>(a, blockIdx.x, blockIdx.y);
+}
+template <int M>
+__global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows_grouped(Group<P1Args> g) {
+    persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M>(a, bx, by); });
+}
+template <int M>
+__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
+    propagate_cols_body<M>(a, blockIdx.x, blockIdx.y);
+}
+template <int M>
+__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
+    persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M>(a, bx, by); });
+}
+template <int M>
+__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a) {
+    propagate_rows_body<M>(a, blockIdx.x, blockIdx.y);
+}
+template <int M>
+__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
+    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M>(a, bx, by); });
+}
+
 template <typename Args>
 static hipError_t launch_rsd(void (*k)(Args), dim3 grid, int threads, size_t sh, hipStream_t s, const Args& a) {
     if (sh > 65536) {
@@ -286,6 +313,28 @@ static hipError_t launch_rsd(void (*k)(Args), dim3 grid, int threads, size_t sh,
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k, grid, dim3(threads), sh, s, a);
+    return hipGetLastError();
+}
+
+
+template <typename K>
+static int persistent_grid(K kernel, int threads, size_t sh, int total) {
+    int per_cu = 0, dev = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, sh) != hipSuccess) per_cu = 1;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    const int g = (per_cu > 0 ? per_cu : 1) * cus;
+    return g < total ? g : total;
+}
+
+template <typename K, typename G>
+static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, hipStream_t s) {
+    if (g.total <= 0) return hipSuccess;
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, dim3(persistent_grid(kernel, threads, sh, g.total)), dim3(threads), sh, s, g);
     return hipGetLastError();
 }
 
@@ -331,6 +380,49 @@ hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
         dim3 grid((a.ny + RB - 1) / RB, a.g.nzc);
         return launch_rsd(k_propagate_rows<MM>, grid, NW * 64, (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
     })
+}
+
+hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, {
+        using F = WaveFFT<MM>;
+        return launch_grouped(k_kernel_rows_grouped<MM>, g, kP1Waves * 64,
+                              (size_t)(kP1Waves * (F::SCR + 1) + MM) * sizeof(float2), s);
+    })
+}
+
+hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, {
+        using F = WaveFFT<MM>;
+        return launch_grouped(k_propagate_cols_grouped<MM>, g, kP2Waves * 64,
+                              (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s);
+    })
+}
+
+hipError_t launch_propagate_rows_grouped(int M, const Group<P3Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, {
+        using F = WaveFFT<MM>;
+        constexpr int NW = p3_waves<MM>();
+        constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
+        return launch_grouped(k_propagate_rows_grouped<MM>, g, NW * 64, (size_t)(NW * SCRP + MM) * sizeof(float2), s);
+    })
+}
+
+int grid_x_kernel_rows(int M) {
+    switch (M) {
+        case 64: return (33 + kP1Waves * 8 - 1) / (kP1Waves * 8);
+        case 128: return (65 + kP1Waves * 4 - 1) / (kP1Waves * 4);
+        case 256: return (129 + kP1Waves * 2 - 1) / (kP1Waves * 2);
+        case 512: return (257 + kP1Waves - 1) / kP1Waves;
+        default: return (513 + kP1Waves - 1) / kP1Waves;
+    }
+}
+int grid_x_propagate_cols(int M) {
+    const int lpw = M >= 512 ? 1 : 512 / M;
+    return (M / 2 + 1 + kP2Waves * lpw - 1) / (kP2Waves * lpw);
+}
+int rows_per_block_propagate(int M) {
+    const int lpw = M >= 512 ? 1 : 512 / M;
+    return (M >= 1024 ? 8 : 16) * lpw;
 }
 
 }  // namespace nursd

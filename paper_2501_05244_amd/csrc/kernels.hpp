@@ -2,6 +2,7 @@
 // translation units and the host-side C-ABI implementation.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "persistent.hpp"
 #include <cstddef>
 #include <cstdint>
 
@@ -190,5 +191,19 @@ struct AdjArgs {
 };
 hipError_t launch_adjoint_planes(const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- grouped launches
+hipError_t launch_phasor_grouped(int T, int F_max, const Group<PhasorArgs>& g, hipStream_t s);
+hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStream_t s);
+hipError_t launch_fine_y_grouped(int Mf, const Group<FineYArgs>& g, hipStream_t s);
+hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t s);
+hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStream_t s);
+hipError_t launch_propagate_rows_grouped(int M, const Group<P3Args>& g, hipStream_t s);
+int grid_x_kernel_rows(int M);
+int grid_x_propagate_cols(int M);
+int rows_per_block_propagate(int M);
+int fine_y_lines();
+int phasor_group();
+hipError_t launch_zero_counters(int* c, int n, hipStream_t s);
 
 }  // namespace nursd

@@ -1,0 +1,83 @@
+"""Batched serving (one captured graph of grouped persistent kernels) against
+the plain per-scene loop (<= 1e-5) and the FP64 oracle (<= 1e-4)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nursd_ref as o
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def small_scenes():
+    """Six scenes of uneven size: N in {32, 48, 64, 96, 128, 20}, transform
+    sizes 64..256, relay counts 300..3000, 3..9 frequencies, 2..5 planes."""
+    out = []
+    rng = np.random.default_rng(77)
+    dx = 0.0078125
+    for s, (n, L, F, Z, lam) in enumerate([(32, 300, 3, 2, 0.05), (48, 1200, 5, 3, 0.06), (64, 800, 4, 4, 0.07),
+                                           (96, 3000, 9, 2, 0.045), (128, 2500, 6, 5, 0.06), (20, 400, 7, 3, 0.08)]):
+        half = n * dx / 2
+        relay = scenes.relay_uniform(L, half * 0.98, seed=100 + s)
+        scat, alb = scenes.scatter_points(3, 0.8 * half, 0.3, 0.3 + n * dx, seed=200 + s)
+        wl = scenes.Wavelet(lambda_c=lam, n_time=2048, dt=4e-12, t0=0.0, n_freq=F)
+        g = scenes.Grid(x0=-half + dx / 2, y0=-half + dx / 2, dx=dx, dy=dx, nx=n, ny=n,
+                        z=scenes.cell_centres(0.3, 0.3 + n * dx, Z))
+        w = scenes.Workload(f"s{s}", relay, np.zeros(3), wl, g, scatterers=scat, albedo=alb)
+        w.hist = scenes.render_transients(relay, scat, alb, w.xp, 2048, 4e-12, 0.0)
+        out.append(w)
+    return out
+
+
+def run_both(ws, device, autotune):
+    from paper_2501_05244_amd.api import Batch, plan_from_workload
+    plans = [plan_from_workload(w, device) for w in ws]
+    hists = [torch.from_numpy(w.hist).to(device) for w in ws]
+    plain = [p.forward_hist(h, vol=False)[1] for p, h in zip(plans, hists)]
+    batch = Batch(plans, autotune=autotune)
+    outs = batch.forward(hists)
+    torch.cuda.synchronize()
+    return plans, hists, plain, batch, outs
+
+
+@pytest.mark.parametrize("autotune", [False, True])
+def test_batch_matches_plain_loop(device, autotune):
+    print("case: batch small autotune", autotune, flush=True)
+    ws = small_scenes()
+    plans, hists, plain, batch, outs = run_both(ws, device, autotune)
+    for a, b in zip(outs, plain):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+    info = batch.info()
+    assert info["budget"] in (64, 128, 256, 512)
+    if autotune:
+        assert len(info["tried"]) == 4
+    # new output buffers: tables are re-uploaded, results unchanged
+    outs2 = batch.forward(hists, [torch.zeros_like(x) for x in outs])
+    for a, b in zip(outs2, plain):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
+
+
+def test_batch_matches_oracle(device):
+    ws = small_scenes()
+    plans, hists, plain, batch, outs = run_both(ws, device, False)
+    for w, I in zip(ws[:2] + ws[5:], outs[:2] + outs[5:]):
+        P, f = o.phasors_from_workload(w)
+        ref = o.nursd_grid(P, w.relay_xy.astype(np.float64), f, o.frame_for_workload(w), w.grid, w.xp,
+                           intensity=True)
+        assert rel(I.cpu().numpy(), ref) < 1e-4
+
+
+@pytest.mark.slow
+def test_batch_64_uneven_scenes(device):
+    """The 64-scene serving workload (relays 2k-64k, grids 64^2x32 to
+    256^2x128, 16-128 frequencies, 4-8 cm wavelengths): batched == plain."""
+    print("case: batch 64 scenes", flush=True)
+    ws = scenes.config_batch()
+    plans, hists, plain, batch, outs = run_both(ws, device, True)
+    for a, b in zip(outs, plain):
+        assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
