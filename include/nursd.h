@@ -185,9 +185,17 @@ int nursd_adjoint(nursd_plan* plan, const void* grad_vol_dev, const void* P_dev,
  * graph of grouped persistent kernels: each launch serves every plan of one
  * kernel type and size class, pulling work items from a device queue.
  * nursd_batch_create copies nothing and launches nothing; the plans must
- * outlive the batch.  With autotune = 1 the first nursd_batch_forward times
- * candidate propagation chunk budgets (planes per round) on the real inputs
- * and keeps the fastest; otherwise a default is used.
+ * outlive the batch.  The temporal transform, spreading and fine-grid
+ * passes of all plans are grouped launches; plans with a transform size
+ * below a threshold are also propagated by grouped launches, in R rounds
+ * each covering about 1/R of every such plan's planes, while larger plans
+ * are propagated chunk by chunk with ordinary launches inside the graph.
+ * Grouped launches run in one of three schedules: persistent workgroups fed
+ * by a device work queue, persistent workgroups with a static stride, or
+ * one workgroup per work block.  With autotune = 1 the first
+ * nursd_batch_forward times (threshold, schedule, R) candidates on the real
+ * inputs and keeps the fastest; otherwise the work-queue schedule, threshold
+ * 512 and the smallest R whose scratch fits 24 GiB are used.
  * nursd_batch_forward: hist_dev[i] = [L_i][T_i] histograms of plan i,
  * I_dev[i] = [nz][ny][nx] intensity of plan i (float).  The first call
  * builds the workspace (owned by the batch), captures the graph and
@@ -198,9 +206,12 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
                        nursd_batch** out);
 int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev,
                         void* stream);
-/* Chosen budget, number of grouped launches in the graph, the autotuner's
- * candidates and their times (ms per batch), workspace bytes.  Arrays may be
- * NULL; tried / tried_ms need room for 8 entries. */
+/* Chosen configuration (R + 1000 * schedule + 10000 * threshold code;
+ * schedule 0 = work queue, 1 = static stride, 2 = one workgroup per block;
+ * threshold code 0 = none chunk by chunk, 1 = M >= 256, 2 = M >= 512),
+ * number of launch records in the graph, the autotuner's candidates (same
+ * encoding) and their times (ms per batch), workspace bytes.  Arrays may be
+ * NULL; tried / tried_ms need room for 16 entries. */
 int nursd_batch_info(const nursd_batch* batch, int32_t* budget, int32_t* launches, int32_t* n_tried,
                      int32_t* tried, float* tried_ms, size_t* workspace_bytes);
 void nursd_batch_destroy(nursd_batch* batch);

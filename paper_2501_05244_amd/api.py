@@ -230,13 +230,19 @@ class Batch:
 
     def info(self) -> dict:
         b, nl, nt = c_int32(), c_int32(), c_int32()
-        tried = (c_int32 * 8)()
-        tms = (ctypes.c_float * 8)()
+        tried = (c_int32 * 16)()
+        tms = (ctypes.c_float * 16)()
         wsb = c_size_t()
         check(self._lib.nursd_batch_info(self.handle, byref(b), byref(nl), byref(nt), tried, tms, byref(wsb)),
               "nursd_batch_info")
-        return {"budget": b.value, "launches": nl.value, "workspace_bytes": wsb.value,
-                "tried": {tried[i]: tms[i] for i in range(nt.value)}}
+        names = {0: "queue", 1: "static", 2: "flat"}
+        serial = {0: "none", 1: "M>=256", 2: "M>=512"}
+
+        def label(t):
+            return f"{names[(t // 1000) % 10]}/R{t % 1000}/serial:{serial[t // 10000]}"
+        return {"rounds": b.value % 1000, "schedule": names[(b.value // 1000) % 10],
+                "serial": serial[b.value // 10000], "launches": nl.value, "workspace_bytes": wsb.value,
+                "tried": {label(t): tms[i] for i, t in enumerate(tried[:nt.value])}}
 
 
 def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) -> Plan:

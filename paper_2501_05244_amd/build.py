@@ -34,7 +34,7 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-result",
-]
+] + os.environ.get("NURSD_EXTRA_FLAGS", "").split()
 
 
 def _compile(src: str) -> str:

@@ -596,24 +596,30 @@ hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
 }
 }  // namespace nursd
 
-enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3 };
+enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL };
 
 struct BatchScene {
     nursd_plan* p = nullptr;
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0;
     int ZC = 1, rounds = 1;
+    bool serial = false;     // propagated chunk by chunk with ordinary launches
 };
 
 struct BatchLaunch {
     int kind = 0, size = 0, fmax = 0;
-    size_t items = 0, prefix = 0, gridx = 0;   // byte offsets in the table buffer
+    int half = 0;                                    // row pass: every window within M/2
+    int scene = -1;                                  // BK_SERIAL: scene propagated with ordinary launches
+    size_t items = 0, prefix = 0, gridx = 0, item_of = 0;   // byte offsets in the table buffer
     int n = 0, total = 0, counter = 0;
 };
 
 struct nursd_batch {
     std::vector<BatchScene> sc;
     int autotune = 0;
-    int budget = 0;                 // planes per round at M = 512 (0 = not chosen yet)
+    int budget = 0;                 // propagation rounds R (0 = not chosen yet)
+    int sched = kFlat;              // grouped-launch schedule (kQueue, kStatic, kFlat)
+    int serial_min_m = 512;         // scenes with M >= this are propagated chunk by chunk
+    size_t off_serial_Bt = 0, off_serial_Yt = 0;
     std::vector<int> tried;         // candidate budgets and their times
     std::vector<float> tried_ms;
     char* ws = nullptr;
@@ -652,9 +658,21 @@ size_t tab_push(std::vector<char>& tab, const std::vector<T>& v) {
     return off;
 }
 
-int batch_zc(const nursd_plan* p, int budget) {
-    const long per_m = std::max(1L, (long)budget * (512L * 512L) / ((long)p->M * p->M));
-    return (int)std::max(1L, std::min((long)p->nz, per_m / p->F));
+// Every scene is split into the same number of rounds so each round carries
+// about 1/R of every scene's planes.
+int batch_zc(const nursd_plan* p, int rounds) { return std::max(1, (p->nz + rounds - 1) / rounds); }
+
+constexpr size_t kBatchScratchCap = 96ull << 30;      // propagation scratch limit for candidates
+constexpr size_t kBatchScratchDefault = 24ull << 30;  // default without autotuning
+
+size_t batch_scratch_bytes(const nursd_batch* bt, int rounds) {
+    size_t t = 0;
+    for (const auto& sc : bt->sc) {
+        const nursd_plan* p = sc.p;
+        const size_t zc = (size_t)batch_zc(p, rounds);
+        t += (size_t)p->F * zc * ((size_t)(p->M / 2 + 1) * p->BS + (size_t)p->ny * p->M) * sizeof(float2);
+    }
+    return t;
 }
 
 // Workspace layout, item tables and launch list for `budget`, with the
@@ -663,10 +681,16 @@ int batch_build(nursd_batch* bt, int budget) {
     size_t o = 0;
     const size_t c8 = sizeof(float2);
     int max_rounds = 0;
+    size_t serial_bt = 0, serial_yt = 0;
     for (auto& sc : bt->sc) {
         nursd_plan* p = sc.p;
+        sc.serial = p->M >= bt->serial_min_m;
+        if (sc.serial) {
+            serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
+            serial_yt = std::max(serial_yt, (size_t)p->FC * p->ZC * p->ny * p->M * c8);
+        }
         sc.ZC = batch_zc(p, budget);
-        sc.rounds = (p->nz + sc.ZC - 1) / sc.ZC;
+        sc.rounds = sc.serial ? 0 : (p->nz + sc.ZC - 1) / sc.ZC;
         max_rounds = std::max(max_rounds, sc.rounds);
         sc.off_P = o;
         o = align_up(o + (size_t)p->F * p->L * c8);
@@ -674,13 +698,19 @@ int batch_build(nursd_batch* bt, int budget) {
         o = align_up(o + (size_t)p->F * p->M * p->Mf * c8);
         sc.off_U = o;
         o = align_up(o + (size_t)p->F * p->M * p->M * c8);
-        sc.off_Bt = o;
-        o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
-        sc.off_Yt = o;
-        o = align_up(o + (size_t)p->F * sc.ZC * p->ny * p->M * c8);
+        if (!sc.serial) {
+            sc.off_Bt = o;
+            o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
+            sc.off_Yt = o;
+            o = align_up(o + (size_t)p->F * sc.ZC * p->ny * p->M * c8);
+        }
         sc.off_V = o;
         o = align_up(o + (size_t)p->nvox() * c8);
     }
+    bt->off_serial_Bt = o;
+    o = align_up(o + serial_bt);
+    bt->off_serial_Yt = o;
+    o = align_up(o + serial_yt);
     if (o > bt->ws_bytes) {
         if (bt->ws) HIP_TRY(hipFree(bt->ws));
         bt->ws = nullptr;
@@ -694,8 +724,21 @@ int batch_build(nursd_batch* bt, int budget) {
     bt->launches.clear();
     int counter = 0;
     // one grouped launch per (kind, size class) over the given items
-    auto add = [&](int kind, int size, int fmax, auto& items, std::vector<int>& gx, std::vector<int>& gy) {
-        if (items.empty()) return;
+    // one grouped launch per (kind, size class); items are ordered by
+    // descending work so the largest are dequeued first
+    auto add = [&](int kind, int size, int fmax, auto& items_in, std::vector<int>& gx_in, std::vector<int>& gy_in,
+                   const std::vector<double>& work) {
+        if (items_in.empty()) return;
+        std::vector<size_t> ord(items_in.size());
+        for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return work[a] > work[b]; });
+        auto items = items_in;
+        std::vector<int> gx(gx_in.size()), gy(gy_in.size());
+        for (size_t i = 0; i < ord.size(); ++i) {
+            items[i] = items_in[ord[i]];
+            gx[i] = gx_in[ord[i]];
+            gy[i] = gy_in[ord[i]];
+        }
         BatchLaunch L;
         L.kind = kind;
         L.size = size;
@@ -704,9 +747,13 @@ int batch_build(nursd_batch* bt, int budget) {
         std::vector<int> prefix(items.size() + 1, 0);
         for (size_t i = 0; i < items.size(); ++i) prefix[i + 1] = prefix[i] + gx[i] * gy[i];
         L.total = prefix.back();
+        std::vector<int> item_of(L.total);
+        for (size_t i = 0; i < items.size(); ++i)
+            for (int v = prefix[i]; v < prefix[i + 1]; ++v) item_of[v] = (int)i;
         L.items = tab_push(bt->tab, items);
         L.prefix = tab_push(bt->tab, prefix);
         L.gridx = tab_push(bt->tab, gx);
+        L.item_of = tab_push(bt->tab, item_of);
         L.counter = counter++;
         bt->launches.push_back(L);
     };
@@ -722,6 +769,7 @@ int batch_build(nursd_batch* bt, int budget) {
     for (int T : classes([](nursd_plan* p) { return p->T; })) {
         std::vector<PhasorArgs> it;
         std::vector<int> gx, gy;
+        std::vector<double> wk;
         int fmax = 0;
         for (size_t i = 0; i < bt->sc.size(); ++i) {
             nursd_plan* p = bt->sc[i].p;
@@ -739,15 +787,17 @@ int batch_build(nursd_batch* bt, int budget) {
             it.push_back(a);
             gx.push_back((p->L + phasor_group() - 1) / phasor_group());
             gy.push_back(1);
+            wk.push_back((double)p->L);
             fmax = std::max(fmax, p->F);
         }
-        add(BK_PHASOR, T, fmax, it, gx, gy);
+        add(BK_PHASOR, T, fmax, it, gx, gy, wk);
     }
     // steps 2-3
     for (int Mf : classes([](nursd_plan* p) { return p->Mf; })) {
         std::vector<SpreadArgs> it;
         std::vector<FineYArgs> it2;
         std::vector<int> gx, gy, gx2, gy2;
+        std::vector<double> wk;
         for (auto& sc : bt->sc) {
             nursd_plan* p = sc.p;
             if (p->Mf != Mf) continue;
@@ -782,9 +832,10 @@ int batch_build(nursd_batch* bt, int budget) {
             it2.push_back(f);
             gx2.push_back(p->M / fine_y_lines());
             gy2.push_back(p->F);
+            wk.push_back((double)p->F * p->L);
         }
-        add(BK_SPREAD, Mf, 0, it, gx, gy);
-        add(BK_FINEY, Mf, 0, it2, gx2, gy2);
+        add(BK_SPREAD, Mf, 0, it, gx, gy, wk);
+        add(BK_FINEY, Mf, 0, it2, gx2, gy2, wk);
     }
     // steps 4-7, round by round
     const std::vector<int> Ms = classes([](nursd_plan* p) { return p->M; });
@@ -794,6 +845,7 @@ int batch_build(nursd_batch* bt, int budget) {
             std::vector<P2Args> i2;
             std::vector<P3Args> i3;
             std::vector<int> g1x, g1y, g2x, g2y, g3x, g3y;
+            std::vector<double> w12, w3;
             for (size_t i = 0; i < bt->sc.size(); ++i) {
                 BatchScene& sc = bt->sc[i];
                 nursd_plan* p = sc.p;
@@ -814,10 +866,33 @@ int batch_build(nursd_batch* bt, int budget) {
                 const int rb = rows_per_block_propagate(M);
                 g3x.push_back((p->ny + rb - 1) / rb);
                 g3y.push_back(nzc);
+                w12.push_back((double)p->F * nzc);
+                w3.push_back((double)p->F);      // per block: one pass per frequency
             }
-            add(BK_P1, M, 0, i1, g1x, g1y);
-            add(BK_P2, M, 0, i2, g2x, g2y);
-            add(BK_P3, M, 0, i3, g3x, g3y);
+            add(BK_P1, M, 0, i1, g1x, g1y, w12);
+            add(BK_P2, M, 0, i2, g2x, g2y, w12);
+            add(BK_P3, M, 0, i3, g3x, g3y, w3);
+            if (!i3.empty()) {
+                bool half = true;
+                for (const P3Args& a3 : i3) half = half && 2 * a3.nx <= a3.M;
+                bt->launches.back().half = half ? 1 : 0;
+            }
+        }
+    }
+    // large-transform scenes: ordinary chunked launches, largest first
+    {
+        std::vector<int> order;
+        for (size_t i = 0; i < bt->sc.size(); ++i)
+            if (bt->sc[i].serial) order.push_back((int)i);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const nursd_plan *pa = bt->sc[a].p, *pb = bt->sc[b].p;
+            return (double)pa->F * pa->nz * pa->M * pa->M > (double)pb->F * pb->nz * pb->M * pb->M;
+        });
+        for (int i : order) {
+            BatchLaunch L;
+            L.kind = BK_SERIAL;
+            L.scene = i;
+            bt->launches.push_back(L);
         }
     }
     // upload the tables through pinned staging (same device buffer if it fits)
@@ -858,22 +933,44 @@ Group<A> group_of(nursd_batch* bt, const BatchLaunch& L) {
     g.items = reinterpret_cast<const A*>(bt->d_tab + L.items);
     g.prefix = reinterpret_cast<const int*>(bt->d_tab + L.prefix);
     g.gridx = reinterpret_cast<const int*>(bt->d_tab + L.gridx);
+    g.item_of = reinterpret_cast<const int*>(bt->d_tab + L.item_of);
     g.n = L.n;
     g.total = L.total;
     g.counter = bt->d_counters + L.counter;
+    g.mode = bt->sched;
     return g;
 }
 
 int batch_enqueue(nursd_batch* bt, hipStream_t s) {
     HIP_TRY(launch_zero_counters(bt->d_counters, (int)bt->launches.size(), s));
     for (const BatchLaunch& L : bt->launches) {
+        if (L.kind == BK_SERIAL) {
+            const BatchScene& sc = bt->sc[L.scene];
+            nursd_plan* p = sc.p;
+            char* ws = bt->ws;
+            float2* Bt = reinterpret_cast<float2*>(ws + bt->off_serial_Bt);
+            float2* Yt = reinterpret_cast<float2*>(ws + bt->off_serial_Yt);
+            const float2* U = reinterpret_cast<const float2*>(ws + sc.off_U);
+            float2* V = reinterpret_cast<float2*>(ws + sc.off_V);
+            for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+                const int nb = std::min(p->FC, p->F - b0);
+                for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+                    const int nzc = std::min(p->ZC, p->nz - z0);
+                    const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+                    HIP_TRY(launch_kernel_rows(P1Args{g, Bt, p->M, p->BS, p->tw(p->M)}, s));
+                    HIP_TRY(launch_propagate_cols(P2Args{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)}, s));
+                    HIP_TRY(launch_propagate_rows(rows_args(p, g, Yt, V, bt->I[L.scene], b0, nb), s));
+                }
+            }
+            continue;
+        }
         switch (L.kind) {
             case BK_PHASOR: HIP_TRY(launch_phasor_grouped(L.size, L.fmax, group_of<PhasorArgs>(bt, L), s)); break;
             case BK_SPREAD: HIP_TRY(launch_spread_xfft_grouped(L.size, group_of<SpreadArgs>(bt, L), s)); break;
             case BK_FINEY: HIP_TRY(launch_fine_y_grouped(L.size, group_of<FineYArgs>(bt, L), s)); break;
             case BK_P1: HIP_TRY(launch_kernel_rows_grouped(L.size, group_of<P1Args>(bt, L), s)); break;
             case BK_P2: HIP_TRY(launch_propagate_cols_grouped(L.size, group_of<P2Args>(bt, L), s)); break;
-            default: HIP_TRY(launch_propagate_rows_grouped(L.size, group_of<P3Args>(bt, L), s)); break;
+            default: HIP_TRY(launch_propagate_rows_grouped(L.size, L.half != 0, group_of<P3Args>(bt, L), s)); break;
         }
     }
     return NURSD_OK;
@@ -899,7 +996,8 @@ int batch_capture(nursd_batch* bt) {
 }
 
 // Build, warm up (uncaptured run: sets kernel attributes), capture.
-int batch_prepare(nursd_batch* bt, int budget, hipStream_t s) {
+int batch_prepare(nursd_batch* bt, int budget, int sched, hipStream_t s) {
+    bt->sched = sched;
     int rc = batch_build(bt, budget);
     if (rc) return rc;
     if ((rc = batch_upload(bt, s))) return rc;
@@ -1374,16 +1472,25 @@ int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const*
     }
     int rc;
     if (!bt->budget) {
-        // choose the propagation chunk budget: measured (autotune) or default
-        const int cands_tune[] = {64, 128, 256, 512};
+        // choose the number of propagation rounds: measured (autotune) or
+        // the smallest whose scratch fits the default budget
+        std::vector<int> cands_tune;
+        for (int r : {4, 8, 16, 32, 64})
+            if (batch_scratch_bytes(bt, r) <= kBatchScratchCap) cands_tune.push_back(r);
+        if (cands_tune.empty()) cands_tune.push_back(128);
         if (bt->autotune) {
             hipEvent_t e0, e1;
             HIP_TRY(hipEventCreate(&e0));
             HIP_TRY(hipEventCreate(&e1));
             float best = 1e30f;
-            int best_b = 128;
+            int best_b = cands_tune.back(), best_s = kFlat;
+            if (cands_tune.size() > 2) cands_tune.resize(2);
+            int best_m = 512;
+            for (int mth : {256, 512, 1 << 20})
+            for (int sc : {kFlat, kQueue})
             for (int c : cands_tune) {
-                if ((rc = batch_prepare(bt, c, s))) return rc;
+                bt->serial_min_m = mth;
+                if ((rc = batch_prepare(bt, c, sc, s))) return rc;
                 HIP_TRY(hipGraphLaunch(bt->exec, s));
                 HIP_TRY(hipEventRecord(e0, s));
                 for (int k = 0; k < 2; ++k) HIP_TRY(hipGraphLaunch(bt->exec, s));
@@ -1391,26 +1498,39 @@ int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const*
                 HIP_TRY(hipEventSynchronize(e1));
                 float ms = 0.f;
                 HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                bt->tried.push_back(c);
+                bt->tried.push_back(c + 1000 * sc + 10000 * (mth == 256 ? 1 : mth == 512 ? 2 : 0));
                 bt->tried_ms.push_back(ms / 2);
                 if (ms < best) {
                     best = ms;
                     best_b = c;
+                    best_s = sc;
+                    best_m = mth;
                 }
             }
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             bt->budget = best_b;
+            bt->sched = best_s;
+            bt->serial_min_m = best_m;
         } else {
-            bt->budget = 128;
+            bt->sched = kQueue;
+            bt->serial_min_m = 512;
+            bt->budget = cands_tune.front();
+            for (int r : cands_tune)
+                if (batch_scratch_bytes(bt, r) <= kBatchScratchDefault) {
+                    bt->budget = r;
+                    break;
+                }
         }
-        if ((rc = batch_prepare(bt, bt->budget, s))) return rc;
+        if ((rc = batch_prepare(bt, bt->budget, bt->sched, s))) return rc;
         changed = false;
     }
     if (changed) {
-        // same layout, new pointers: rebuild and re-upload the item tables
+        // same layout, new pointers: rebuild the item tables and re-capture
+        // (ordinary launches carry the output pointers as kernel arguments)
         if ((rc = batch_build(bt, bt->budget))) return rc;
         if ((rc = batch_upload(bt, s))) return rc;
+        if ((rc = batch_capture(bt))) return rc;
     }
     HIP_TRY(hipGraphLaunch(bt->exec, s));
     return NURSD_OK;
@@ -1419,7 +1539,9 @@ int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const*
 int nursd_batch_info(const nursd_batch* bt, int32_t* budget, int32_t* launches, int32_t* n_tried, int32_t* tried,
                      float* tried_ms, size_t* workspace_bytes) {
     if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
-    if (budget) *budget = bt->budget;
+    if (budget)
+        *budget = bt->budget + 1000 * bt->sched +
+                  10000 * (bt->serial_min_m == 256 ? 1 : bt->serial_min_m == 512 ? 2 : 0);
     if (launches) *launches = (int32_t)bt->launches.size();
     if (n_tried) *n_tried = (int32_t)bt->tried.size();
     for (size_t i = 0; i < bt->tried.size(); ++i) {

@@ -161,7 +161,8 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
         hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, dim3(persistent_grid(kernel, threads, sh, g.total)), dim3(threads), sh, s, g);
+    const int grid = g.mode == kFlat ? g.total : persistent_grid(kernel, threads, sh, g.total);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), sh, s, g);
     return hipGetLastError();
 }
 

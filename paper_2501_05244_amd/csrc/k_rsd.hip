@@ -193,10 +193,16 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
 
 // P3: LPW output rows per wavefront, RB = waves * LPW rows per block; loops
 // over the chunk's frequencies with per-voxel accumulators in registers.
+#ifndef NURSD_P3_WAVES
+#define NURSD_P3_WAVES 16
+#endif
 template <int M>
-constexpr int p3_waves() { return M >= 1024 ? 8 : 16; }
+constexpr int p3_waves() { return M >= 1024 ? 8 : NURSD_P3_WAVES; }
 
-template <int M>
+// With nx <= M/2 (zero padding >= 2) only permuted slots d in {0, 1, 6, 7}
+// of each 8-point group can fall inside the window (|m'| < M/4); HALF keeps
+// per-voxel state for those four slots only.
+template <int M, bool HALF>
 __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M>();
@@ -214,14 +220,17 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
     const size_t plane_off = (size_t)iz * ny * nx;
-    double dist[F::NV];
-    float2 acc[F::NV];
-    int off[F::NV];                     // output offset within the plane, -1 outside the window
+    constexpr int SPG = HALF ? 4 : 8;                   // kept slots per 8-point group
+    constexpr int NS = F::GPL * SPG;
+    double dist[NS];
+    float2 acc[NS];
+    int off[NS];                        // output offset within the plane, -1 outside the window
 #pragma unroll
     for (int h = 0; h < F::GPL; ++h)
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            const int sl = h * 8 + d;
+        for (int j = 0; j < SPG; ++j) {
+            const int d = HALF ? (j < 2 ? j : j + 4) : j;
+            const int sl = h * SPG + j;
             int q;
             const int k = F::perm_k(lane, h, d, q);
             const int iy = iy0 + wave * LPW + q;
@@ -258,17 +267,22 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
         F::template nat_to_perm<true>(v, rows, tws, lane);
         const double foc = a.g.f[b] / kC;
 #pragma unroll
-        for (int sl = 0; sl < F::NV; ++sl) {
-            if (off[sl] < 0) continue;
-            if (a.coherent) {
-                acc[sl] = cadd(acc[sl], cmul(phase_of(dist[sl], foc), v[sl]));
-            } else {
-                acc[sl].x += sqrtf(v[sl].x * v[sl].x + v[sl].y * v[sl].y);
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int j = 0; j < SPG; ++j) {
+                const int d = HALF ? (j < 2 ? j : j + 4) : j;
+                const int sl = h * SPG + j;
+                const float2 val = v[h * 8 + d];
+                if (off[sl] < 0) continue;
+                if (a.coherent) {
+                    acc[sl] = cadd(acc[sl], cmul(phase_of(dist[sl], foc), val));
+                } else {
+                    acc[sl].x += sqrtf(val.x * val.x + val.y * val.y);
+                }
             }
-        }
     }
 #pragma unroll
-    for (int sl = 0; sl < F::NV; ++sl) {
+    for (int sl = 0; sl < NS; ++sl) {
         if (off[sl] < 0) continue;
         const size_t o = plane_off + off[sl];
         if (a.coherent) {
@@ -280,13 +294,12 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     }
 }
 
-
 template <int M>
 __global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
     kernel_rows_body<M>(a, blockIdx.x, blockIdx.y);
 }
 template <int M>
-__global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows_grouped(Group<P1Args> g) {
+__global__ __launch_bounds__(kP1Waves * 64, 8) void k_kernel_rows_grouped(Group<P1Args> g) {
     persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M>(a, bx, by); });
 }
 template <int M>
@@ -294,16 +307,16 @@ __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
     propagate_cols_body<M>(a, blockIdx.x, blockIdx.y);
 }
 template <int M>
-__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
+__global__ __launch_bounds__(kP2Waves * 64, 6) void k_propagate_cols_grouped(Group<P2Args> g) {
     persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M>(a, bx, by); });
 }
-template <int M>
+template <int M, bool HALF>
 __global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a) {
-    propagate_rows_body<M>(a, blockIdx.x, blockIdx.y);
+    propagate_rows_body<M, HALF>(a, blockIdx.x, blockIdx.y);
 }
-template <int M>
+template <int M, bool HALF>
 __global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
-    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M>(a, bx, by); });
+    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF>(a, bx, by); });
 }
 
 template <typename Args>
@@ -334,7 +347,8 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
         hipError_t e = hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kernel, dim3(persistent_grid(kernel, threads, sh, g.total)), dim3(threads), sh, s, g);
+    const int grid = g.mode == kFlat ? g.total : persistent_grid(kernel, threads, sh, g.total);
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(threads), sh, s, g);
     return hipGetLastError();
 }
 
@@ -371,14 +385,16 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
 }
 
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
-    if (a.nx > a.M / 2 || a.ny > a.M / 2 + 1) return hipErrorInvalidValue;
+    const bool half = 2 * a.nx <= a.M;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
         constexpr int NW = p3_waves<MM>();
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
         constexpr int RB = NW * F::LPW;
         dim3 grid((a.ny + RB - 1) / RB, a.g.nzc);
-        return launch_rsd(k_propagate_rows<MM>, grid, NW * 64, (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
+        const size_t sh = (size_t)(NW * SCRP + MM) * sizeof(float2);
+        if (half) return launch_rsd(k_propagate_rows<MM, true>, grid, NW * 64, sh, s, a);
+        return launch_rsd(k_propagate_rows<MM, false>, grid, NW * 64, sh, s, a);
     })
 }
 
@@ -398,12 +414,14 @@ hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStrea
     })
 }
 
-hipError_t launch_propagate_rows_grouped(int M, const Group<P3Args>& g, hipStream_t s) {
+hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s) {
     NURSD_SWITCH_M(M, {
         using F = WaveFFT<MM>;
         constexpr int NW = p3_waves<MM>();
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
-        return launch_grouped(k_propagate_rows_grouped<MM>, g, NW * 64, (size_t)(NW * SCRP + MM) * sizeof(float2), s);
+        const size_t sh = (size_t)(NW * SCRP + MM) * sizeof(float2);
+        if (half) return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64, sh, s);
+        return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64, sh, s);
     })
 }
 
@@ -422,7 +440,7 @@ int grid_x_propagate_cols(int M) {
 }
 int rows_per_block_propagate(int M) {
     const int lpw = M >= 512 ? 1 : 512 / M;
-    return (M >= 1024 ? 8 : 16) * lpw;
+    return (M >= 1024 ? 8 : NURSD_P3_WAVES) * lpw;
 }
 
 }  // namespace nursd

@@ -198,7 +198,7 @@ hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStr
 hipError_t launch_fine_y_grouped(int Mf, const Group<FineYArgs>& g, hipStream_t s);
 hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t s);
 hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStream_t s);
-hipError_t launch_propagate_rows_grouped(int M, const Group<P3Args>& g, hipStream_t s);
+hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s);
 int grid_x_kernel_rows(int M);
 int grid_x_propagate_cols(int M);
 int rows_per_block_propagate(int M);

@@ -13,27 +13,42 @@ struct Group {
     const Args* items;     // [n] argument blocks
     const int* prefix;     // [n + 1] first virtual block of each item
     const int* gridx;      // [n] blocks along x of each item
+    const int* item_of;    // [total] item of each virtual block
     int n;                 // items
     int total;             // virtual blocks
     int* counter;          // work queue, zeroed before the launch
+    int mode;              // kQueue, kStatic or kFlat
 };
 
+constexpr int kQueue = 0;   // persistent workgroups dequeue virtual blocks from the counter
+constexpr int kStatic = 1;  // persistent workgroups take every gridDim-th virtual block
+constexpr int kFlat = 2;    // one workgroup per virtual block (hardware dispatcher)
+
 // Runs body(args, bx, by) for every virtual block of the group.  Every
-// workgroup exits once the counter passes the last virtual block.
+// workgroup exits once the counter (or its stride) passes the last virtual
+// block.
 template <typename Args, typename Body>
 __device__ __forceinline__ void persistent_loop(const Group<Args>& g, Body body) {
+    if (g.mode != kQueue) {
+        const int step = g.mode == kFlat ? g.total : (int)gridDim.x;
+        for (int vb = blockIdx.x; vb < g.total; vb += step) {
+            const int lo = __builtin_amdgcn_readfirstlane(g.item_of[vb]);
+            const Args a = g.items[lo];
+            const int local = vb - g.prefix[lo];
+            const int gx = g.gridx[lo];
+            body(a, local % gx, local / gx);
+            if (g.mode == kStatic) __syncthreads();
+        }
+        return;
+    }
     __shared__ int s_vb;
     for (;;) {
         if (threadIdx.x == 0) s_vb = atomicAdd(g.counter, 1);
         __syncthreads();
-        const int vb = s_vb;
+        const int vb = __builtin_amdgcn_readfirstlane(s_vb);
         __syncthreads();
         if (vb >= g.total) break;
-        int lo = 0, hi = g.n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (g.prefix[mid] <= vb) lo = mid; else hi = mid - 1;
-        }
+        const int lo = __builtin_amdgcn_readfirstlane(g.item_of[vb]);
         const Args a = g.items[lo];
         const int local = vb - g.prefix[lo];
         const int gx = g.gridx[lo];

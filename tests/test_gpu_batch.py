@@ -53,9 +53,11 @@ def test_batch_matches_plain_loop(device, autotune):
     for a, b in zip(outs, plain):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
     info = batch.info()
-    assert info["budget"] in (64, 128, 256, 512)
+    assert info["rounds"] in (4, 8, 16, 32, 64)
+    assert info["schedule"] in ("queue", "static", "flat")
+    assert info["serial"] in ("none", "M>=256", "M>=512")
     if autotune:
-        assert len(info["tried"]) == 4
+        assert len(info["tried"]) >= 3
     # new output buffers: tables are re-uploaded, results unchanged
     outs2 = batch.forward(hists, [torch.zeros_like(x) for x in outs])
     for a, b in zip(outs2, plain):
