@@ -84,6 +84,87 @@ def cpu_baseline(w, hist, threads: int) -> dict:
                       f"phasor DFT + direct NUDFT-1 + direct 2D DFTs in float64; {dt:.1f} s"}
 
 
+def time_ms(fn, reps: int) -> float:
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def secondary(w_spad, dev) -> dict:
+    """The other hot-path rows on their own workloads: scaled RSD frustum,
+    NURSD-3 voxel lists, forward + adjoint, and batched vs plain serving."""
+    import torch
+    from paper_2501_05244_amd.api import Batch, plan_from_workload
+    from paper_2501_05244_amd.autograd import nursd
+    from workloads import scenes
+    out = {}
+    hist = torch.from_numpy(w_spad.hist).to(dev)
+    # scaled RSD: 256x256 samples on 128 planes over [1,4] m, 96 frequencies
+    w = scenes.config_srsd(render=False)
+    plan = plan_from_workload(w, dev)
+    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
+    ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 5)
+    out["srsd"] = {"workload": "srsd_L65536_F96_256x256x128_frustum_1-4m", "ms": round(ms, 3),
+                   "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
+    del plan
+    # NURSD-3: 1,048,576 jittered frustum voxels on 64 planes, 96 frequencies
+    w = scenes.config_frustum_points(render=False)
+    plan = plan_from_workload(w, dev)
+    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
+    ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 3)
+    out["nursd3_points"] = {"workload": "points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
+                            "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
+    del plan
+    # differentiation: forward + adjoint (grad P and grad xy) through autograd
+    w = scenes.config_diff()
+    plan = plan_from_workload(w, dev)
+    P = plan.phasor(torch.from_numpy(w.hist).to(dev))
+    xy = torch.from_numpy(w.relay_xy).to(dev)
+    tgt = torch.zeros(plan.out_shape(), dtype=torch.complex64, device=dev)
+
+    def step():
+        Pg = P.detach().requires_grad_(True)
+        xg = xy.detach().requires_grad_(True)
+        loss = (nursd(Pg, xg, plan) - tgt).abs().pow(2).sum()
+        loss.backward()
+    ms = time_ms(step, 5)
+    out["forward_adjoint"] = {"workload": "diff_L16384_F48_128x128x64", "ms": round(ms, 3),
+                              "voxel*freq/s (forward+adjoint)": scenes.work_units(w) / (ms * 1e-3)}
+    del plan
+    # batched serving of 64 uneven scenes vs the plain per-scene loop
+    ws = scenes.config_batch()
+    plans = [plan_from_workload(x, dev) for x in ws]
+    hists = [torch.from_numpy(x.hist).to(dev) for x in ws]
+    outs = [torch.empty(p.out_shape(), dtype=torch.float32, device=dev) for p in plans]
+    units = sum(scenes.work_units(x) for x in ws)
+
+    def plain():
+        for p, h, o in zip(plans, hists, outs):
+            p.forward_hist(h, vol=False, out_I=o)
+    t_plain = time_ms(plain, 3)
+    ref = [o.clone() for o in outs]
+    b = Batch(plans, autotune=True)
+    bouts = [torch.empty_like(o) for o in outs]
+    b.forward(hists, bouts)
+    t_batch = time_ms(lambda: b.forward(hists, bouts), 5)
+    err = max(float((x - y).norm() / y.norm()) for x, y in zip(bouts, ref))
+    info = b.info()
+    out["batched"] = {"workload": "64 scenes: relays 2k-64k, grids 64^2x32..256^2x128, F 16-128, 4-8 cm",
+                      "plain_ms": round(t_plain, 3), "batched_ms": round(t_batch, 3),
+                      "speedup": round(t_plain / t_batch, 4), "max_rel_l2_batched_vs_plain": err,
+                      "voxel*freq/s": units / (t_batch * 1e-3),
+                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial")}}
+    return out
+
+
 def load_traffic(stage: str):
     """HBM bytes per launch of `stage` from the committed rocprofv3 counter
     summary, if one exists for the current kernel source (else None)."""
@@ -103,6 +184,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-secondary", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the reconstruction would shard "
@@ -163,7 +245,7 @@ def main():
     roof["avg_launch_ms"] = round(avg_launch_ms, 4)
 
     out = {
-        "metric": "NURSD voxel*freq propagations/s at rel-L2<=1e-4",
+        "metric": "NURSD voxel*freq propagations/s at rel-L2<=1e-4; batched vs plain speedup",
         "value": units / (ms * 1e-3),
         "unit": "voxel*freq/s",
         "n_gpus": 1,
@@ -182,6 +264,12 @@ def main():
         "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
     }
+    if not args.no_secondary:
+        del V, I
+        torch.cuda.empty_cache()
+        sec = secondary(w, dev)
+        out["batched_vs_plain_speedup"] = sec["batched"]["speedup"]
+        out["secondary"] = sec
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = cpu_baseline(w, w.hist, threads)
