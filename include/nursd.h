@@ -122,6 +122,8 @@ typedef struct {
     double cx, cy;        /* frame centre                                      */
     double beta;          /* ES shape parameter                                */
     size_t workspace_bytes;
+    int32_t freq_chunk;   /* frequencies per propagation launch               */
+    int32_t plane_chunk;  /* depth planes per propagation launch              */
 } nursd_plan_info_t;
 
 /* Fill the structs with defaults (pad 2, sigma_os 2, tol 1e-6, coherent,

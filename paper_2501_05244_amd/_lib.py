@@ -55,6 +55,7 @@ class PlanInfo(ctypes.Structure):
         ("M", c_int32), ("Mf", c_int32), ("n_freq", c_int32), ("n_relay", c_int32),
         ("kernel_width", c_int32), ("n_voxels", c_int32), ("dx", c_double), ("dy", c_double),
         ("cx", c_double), ("cy", c_double), ("beta", c_double), ("workspace_bytes", c_size_t),
+        ("freq_chunk", c_int32), ("plane_chunk", c_int32),
     ]
 
 

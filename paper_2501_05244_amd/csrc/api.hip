@@ -1303,6 +1303,8 @@ int nursd_plan_info(const nursd_plan* p, nursd_plan_info_t* info) {
     info->cy = p->cy;
     info->beta = p->beta;
     info->workspace_bytes = p->ws_bytes;
+    info->freq_chunk = p->FC;
+    info->plane_chunk = p->ZC;
     return NURSD_OK;
 }
 
