@@ -309,182 +309,6 @@ def main():
     path = {"model_bytes_per_step": model, "effective_GBs": round(model / (ms * 1e-3) / 1e9, 1),
             "frac_of_hbm": round(model / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
 
-    out = {}
-    hist = torch.from_numpy(w_spad.hist).to(dev)
-    # scaled RSD: 256x256 samples on 128 planes over [1,4] m, 96 frequencies
-    w = scenes.config_srsd(render=False)
-    plan = plan_from_workload(w, dev)
-    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
-    ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 5)
-    out["srsd"] = {"workload": "srsd_L65536_F96_256x256x128_frustum_1-4m", "ms": round(ms, 3),
-                   "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
-    del plan
-    # NURSD-3: 1,048,576 jittered frustum voxels on 64 planes, 96 frequencies
-    w = scenes.config_frustum_points(render=False)
-    plan = plan_from_workload(w, dev)
-    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
-    ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 3)
-    out["nursd3_points"] = {"workload": "points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
-                            "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
-    del plan
-    # differentiation: forward + adjoint (grad P and grad xy) through autograd
-    w = scenes.config_diff()
-    plan = plan_from_workload(w, dev)
-    P = plan.phasor(torch.from_numpy(w.hist).to(dev))
-    xy = torch.from_numpy(w.relay_xy).to(dev)
-    tgt = torch.zeros(plan.out_shape(), dtype=torch.complex64, device=dev)
-
-    def step():
-        Pg = P.detach().requires_grad_(True)
-        xg = xy.detach().requires_grad_(True)
-        loss = (nursd(Pg, xg, plan) - tgt).abs().pow(2).sum()
-        loss.backward()
-    ms = time_ms(step, 5)
-    out["forward_adjoint"] = {"workload": "diff_L16384_F48_128x128x64", "ms": round(ms, 3),
-                              "voxel*freq/s (forward+adjoint)": scenes.work_units(w) / (ms * 1e-3)}
-    del plan
-    # batched serving of 64 uneven scenes vs the plain per-scene loop
-    ws = scenes.config_batch()
-    plans = [plan_from_workload(x, dev) for x in ws]
-    hists = [torch.from_numpy(x.hist).to(dev) for x in ws]
-    outs = [torch.empty(p.out_shape(), dtype=torch.float32, device=dev) for p in plans]
-    units = sum(scenes.work_units(x) for x in ws)
-
-    def plain():
-        for p, h, o in zip(plans, hists, outs):
-            p.forward_hist(h, vol=False, out_I=o)
-    t_plain = time_ms(plain, 3)
-    ref = [o.clone() for o in outs]
-    b = Batch(plans, autotune=True)
-    bouts = [torch.empty_like(o) for o in outs]
-    b.forward(hists, bouts)
-    t_batch = time_ms(lambda: b.forward(hists, bouts), 5)
-    err = max(float((x - y).norm() / y.norm()) for x, y in zip(bouts, ref))
-    info = b.info()
-    out["batched"] = {"workload": "64 scenes: relays 2k-64k, grids 64^2x32..256^2x128, F 16-128, 4-8 cm",
-                      "plain_ms": round(t_plain, 3), "batched_ms": round(t_batch, 3),
-                      "speedup": round(t_plain / t_batch, 4), "max_rel_l2_batched_vs_plain": err,
-                      "voxel*freq/s": units / (t_batch * 1e-3),
-                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial")}}
-    return out
-
-
-KERNEL_SOURCES = ("k_rsd.hip", "k_nufft.hip", "k_phasor.hip", "kernels.hpp", "wavefft.hpp", "persistent.hpp")
-
-
-def kernel_source_hash() -> str:
-    """SHA-256 over the sources of the forward kernels; a counter summary
-    taken on other sources no longer describes the kernels that run."""
-    import hashlib
-    h = hashlib.sha256()
-    for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2501_05244_amd", "csrc", name), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
-
-
-def load_traffic(stage: str):
-    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
-    summary, if one exists and was taken on the current kernel sources
-    (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{stage}_spad_counters.json")
-    if not os.path.exists(path):
-        return None
-    try:
-        with open(path) as fh:
-            d = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if d.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
-
-
-def copy_calibration(dev) -> None:
-    """A plain device-to-device copy of 256 MiB, five times: the reference
-    whose FETCH_SIZE / WRITE_SIZE readings scale the counters of the hot
-    kernels to bytes (each dispatch reads and writes exactly 256 MiB)."""
-    import torch
-    n = 256 << 20
-    src = torch.ones(n // 4, dtype=torch.float32, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(5):
-        dst.copy_(src)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_per_dispatch": n, "dispatches": 5}), flush=True)
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-secondary", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run the plain copy used to scale rocprofv3 byte counters")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the reconstruction would shard "
-              "by depth plane with no exchange); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    from paper_2501_05244_amd.api import plan_from_workload
-    from workloads import scenes
-
-    dev = torch.device("cuda:0")
-    if args.copy_calibration:
-        copy_calibration(dev)
-        return
-    w = scenes.config_spad()
-    plan = plan_from_workload(w, dev)
-    hist = torch.from_numpy(w.hist).to(dev)
-    g = w.grid
-    shape = (len(g.z), g.ny, g.nx)
-    V = torch.empty(shape, dtype=torch.complex64, device=dev)
-    I = torch.empty(shape, dtype=torch.float32, device=dev)
-    units = g.nx * g.ny * len(g.z) * plan.F
-
-    for _ in range(args.warmup):
-        plan.forward_hist(hist, out_vol=V, out_I=I)
-    # untimed profiled pass: find the dominant kernel
-    torch.cuda.synchronize()
-    plan.profile_begin()
-    plan.forward_hist(hist, out_vol=V, out_I=I)
-    stages = plan.profile_end()
-    dominant = max(stages, key=lambda k: stages[k][0])
-
-    torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    plan.profile_begin([dominant])
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        plan.forward_hist(hist, out_vol=V, out_I=I)
-    e1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dom = plan.profile_end()[dominant]
-    ms = e0.elapsed_time(e1) / args.steps
-    wall_ms = (t1 - t0) * 1e3 / args.steps
-
-    kind, work = stage_work(dominant, plan.info, w)
-    launches_per_step = dom[1] / args.steps
-    avg_launch_ms = dom[0] / dom[1]
-    per_launch = work / launches_per_step
-    if kind == "flop":
-        achieved = per_launch / (avg_launch_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 2), "peak": round(PEAK_FP32_TFLOPS, 2),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4)}
-    else:
-        achieved = per_launch / (avg_launch_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4)}
-    roof["traffic"] = load_traffic(dominant)
-    roof["kernel"] = dominant
-    roof["avg_launch_ms"] = round(avg_launch_ms, 4)
-
     out = {
         "metric": "NURSD voxel*freq propagations/s at rel-L2<=1e-4; batched vs plain speedup",
         "value": units / (ms * 1e-3),

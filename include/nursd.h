@@ -183,7 +183,8 @@ int nursd_adjoint(nursd_plan* plan, const void* grad_vol_dev, const void* P_dev,
 
 /* Batched serving of many reconstructions of uneven size (the plans may
  * differ in relay count, grid, frequency count, wavelength and transform
- * size).  All n plans (coherent GRID mode, T a power of two) run as one HIP
+ * size).  All n plans (coherent GRID mode, T a power of two, evenly spaced
+ * frequency bins) run as one HIP
  * graph of grouped persistent kernels: each launch serves every plan of one
  * kernel type and size class, pulling work items from a device queue.
  * nursd_batch_create copies nothing and launches nothing; the plans must

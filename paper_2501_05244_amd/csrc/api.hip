@@ -387,6 +387,12 @@ int check_ws(const nursd_plan* p, void* ws, size_t bytes) {
     return NURSD_OK;
 }
 
+bool even_bins(const nursd_plan* p) {
+    for (int b = 2; b < p->F; ++b)
+        if (p->bins[b] - p->bins[b - 1] != p->bins[1] - p->bins[0]) return false;
+    return true;
+}
+
 ChunkGeom chunk_geom(const nursd_plan* p, int b0, int nb, int z0, int nzc) {
     ChunkGeom g;
     g.b0 = b0;
@@ -399,6 +405,16 @@ ChunkGeom chunk_geom(const nursd_plan* p, int b0, int nb, int z0, int nzc) {
     g.pitch_y = p->d_py;
     g.dx = p->dx;
     g.dy = p->dy;
+    // Evenly spaced bins let the kernels advance phases by a per-point step
+    // factor from one frequency to the next instead of evaluating each.
+    g.uni = 1;
+    g.df = 0.0;
+    if (nb > 1) {
+        const int step = p->bins[b0 + 1] - p->bins[b0];
+        for (int b = b0 + 1; b < b0 + nb; ++b)
+            if (p->bins[b] - p->bins[b - 1] != step) g.uni = 0;
+        g.df = g.uni ? p->freqs[b0 + 1] - p->freqs[b0] : 0.0;
+    }
     return g;
 }
 
@@ -846,6 +862,9 @@ int batch_build(nursd_batch* bt, int budget) {
             std::vector<P3Args> i3;
             std::vector<int> g1x, g1y, g2x, g2y, g3x, g3y;
             std::vector<double> w12, w3;
+            bool half = true;       // one row-pass variant per launch: every window within M/2
+            for (const BatchScene& sc : bt->sc)
+                if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx <= M;
             for (size_t i = 0; i < bt->sc.size(); ++i) {
                 BatchScene& sc = bt->sc[i];
                 nursd_plan* p = sc.p;
@@ -863,7 +882,7 @@ int batch_build(nursd_batch* bt, int budget) {
                 g2y.push_back(p->F * nzc);
                 P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I[i], 0, p->F);
                 i3.push_back(a3);
-                const int rb = rows_per_block_propagate(M);
+                const int rb = rows_per_block_propagate(M, half);
                 g3x.push_back((p->ny + rb - 1) / rb);
                 g3y.push_back(nzc);
                 w12.push_back((double)p->F * nzc);
@@ -872,11 +891,7 @@ int batch_build(nursd_batch* bt, int budget) {
             add(BK_P1, M, 0, i1, g1x, g1y, w12);
             add(BK_P2, M, 0, i2, g2x, g2y, w12);
             add(BK_P3, M, 0, i3, g3x, g3y, w3);
-            if (!i3.empty()) {
-                bool half = true;
-                for (const P3Args& a3 : i3) half = half && 2 * a3.nx <= a3.M;
-                bt->launches.back().half = half ? 1 : 0;
-            }
+            if (!i3.empty()) bt->launches.back().half = half ? 1 : 0;
         }
     }
     // large-transform scenes: ordinary chunked launches, largest first
@@ -1192,6 +1207,9 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     const long target = std::max(16L, std::min(4096L, 128L * (512L * 512L) / ((long)p->M * p->M)));
     p->FC = opt->freq_chunk > 0 ? opt->freq_chunk : std::min(p->F, 8);
     p->FC = std::min(p->FC, p->F);
+    // the propagation kernels step phases from one frequency to the next by a
+    // fixed factor: uneven bin lists run one frequency per chunk
+    if (!even_bins(p)) p->FC = 1;
     p->ZC = opt->plane_chunk > 0 ? opt->plane_chunk : (int)std::max(1L, target / p->FC);
     if (p->mode == NURSD_MODE_POINTS && opt->plane_chunk <= 0) p->ZC = std::max(1, 32 / p->FC);
     p->ZC = std::min(p->ZC, p->nz);
@@ -1442,6 +1460,8 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
             return fail(NURSD_ERR_UNSUPPORTED_SIZE, "batched mode takes coherent GRID plans");
         if (!is_pow2(plans[i]->T) || plans[i]->T < 256 || plans[i]->T > 8192)
             return fail(NURSD_ERR_UNSUPPORTED_SIZE, "T must be a power of two in [256, 8192]");
+        if (!even_bins(plans[i]))
+            return fail(NURSD_ERR_UNSUPPORTED_SIZE, "batched mode needs evenly spaced frequency bins");
     }
     auto bt = new nursd_batch();
     for (int i = 0; i < n; ++i) {

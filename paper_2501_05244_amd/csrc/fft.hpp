@@ -26,6 +26,14 @@ __device__ __forceinline__ float2 cmulc(float2 a, float2 b) {
     return make_float2(fmaf(a.x, b.x, a.y * b.y), fmaf(a.y, b.x, -a.x * b.y));
 }
 __device__ __forceinline__ float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// sin and cos of 2 pi x for x in [-1/2, 1/2] (a phase already reduced to a
+// fraction of a cycle in FP64) on the transcendental unit, whose argument is
+// in revolutions: one instruction each, absolute error about 1.3e-7 on this
+// range against float64 (a float32 library sincos is about 5e-8).
+__device__ __forceinline__ void sincos_cycles(float x, float* s, float* c) {
+    *s = __builtin_amdgcn_sinf(x);
+    *c = __builtin_amdgcn_cosf(x);
+}
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 // multiply by -j (forward) or +j (inverse)
 template <bool INV>

@@ -37,7 +37,7 @@ __device__ __forceinline__ float2 adj_phase(double d, double foc) {
     const double cyc = d * foc;
     const float fr = (float)(cyc - rint(cyc));
     float s, c;
-    sincospif(2.0f * fr, &s, &c);
+    sincos_cycles(fr, &s, &c);
     return make_float2(c, s);
 }
 

@@ -33,7 +33,7 @@ __device__ __forceinline__ float2 rsd_kernel(double r2, double f_over_c) {
     const double cyc = r * f_over_c;
     const float fr = (float)(cyc - rint(cyc));
     float s, c;
-    sincospif(2.0f * fr, &s, &c);
+    sincos_cycles(fr, &s, &c);
     const float ir = 1.0f / (float)r;
     return make_float2(c * ir, s * ir);
 }
@@ -43,7 +43,7 @@ __device__ __forceinline__ float2 phase_of(double d, double f_over_c) {
     const double cyc = d * f_over_c;
     const float fr = (float)(cyc - rint(cyc));
     float s, c;
-    sincospif(2.0f * fr, &s, &c);
+    sincos_cycles(fr, &s, &c);
     return make_float2(c, s);
 }
 
@@ -193,11 +193,19 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
 
 // P3: LPW output rows per wavefront, RB = waves * LPW rows per block; loops
 // over the chunk's frequencies with per-voxel accumulators in registers.
+// The block's column tile of the next frequency is loaded into registers
+// while the current one is transformed, so that HBM reads overlap the FFT.
+// The chunk's frequencies are evenly spaced (the host splits uneven bin
+// lists into single-frequency chunks), so the illumination phase of each
+// voxel is advanced by a step factor e^{+j 2 pi df d / c} (both factors from
+// FP64 arguments) instead of being evaluated per frequency.
 #ifndef NURSD_P3_WAVES
 #define NURSD_P3_WAVES 16
 #endif
-template <int M>
-constexpr int p3_waves() { return M >= 1024 ? 8 : NURSD_P3_WAVES; }
+// The full-window variant keeps twice the per-voxel state and runs 8 waves
+// per block so that it fits the register file without spilling.
+template <int M, bool HALF>
+constexpr int p3_waves() { return (M >= 1024 || !HALF) ? 8 : NURSD_P3_WAVES; }
 
 // With nx <= M/2 (zero padding >= 2) only permuted slots d in {0, 1, 6, 7}
 // of each 8-point group can fall inside the window (|m'| < M/4); HALF keeps
@@ -205,9 +213,11 @@ constexpr int p3_waves() { return M >= 1024 ? 8 : NURSD_P3_WAVES; }
 template <int M, bool HALF>
 __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
     using F = WaveFFT<M>;
-    constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M>();
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M, HALF>();
     constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
     constexpr int RB = NW * LPW;
+    constexpr int NPRE = M * RB / (NW * 64);     // tile values per thread
+    static_assert(M * RB % (NW * 64) == 0, "tile must divide over the block");
     extern __shared__ float2 sm[];      // [NW][SCRP], then twiddles [M]
     float2* tws = sm + NW * SCRP;
     for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
@@ -220,10 +230,10 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
     const size_t plane_off = (size_t)iz * ny * nx;
+    const int b_end = a.g.b0 + a.g.nb;
     constexpr int SPG = HALF ? 4 : 8;                   // kept slots per 8-point group
     constexpr int NS = F::GPL * SPG;
-    double dist[NS];
-    float2 acc[NS];
+    float2 acc[NS], ph[NS], st[NS];
     int off[NS];                        // output offset within the plane, -1 outside the window
 #pragma unroll
     for (int h = 0; h < F::GPL; ++h)
@@ -237,35 +247,56 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
             const int ix = (k < H ? k : k - M) + nx / 2;
             off[sl] = (iy < ny && ix >= 0 && ix < nx) ? iy * nx + ix : -1;
             acc[sl] = make_float2(0.f, 0.f);
-            dist[sl] = 0.0;
+            ph[sl] = make_float2(1.f, 0.f);
+            st[sl] = make_float2(1.f, 0.f);
             if (off[sl] >= 0) {
                 const double x = a.xc + (ix - nx / 2) * px;
                 const double y = a.yc + (iy - ny / 2) * py;
-                dist[sl] = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
+                const double dd = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
+                ph[sl] = phase_of(dd, a.g.f[a.g.b0] / kC);
+                st[sl] = phase_of(dd, a.g.df / kC);
                 if (!a.first) {
                     if (a.coherent) acc[sl] = a.V[plane_off + off[sl]];
                     else acc[sl].x = a.I[plane_off + off[sl]];
                 }
             }
         }
+    // This thread's share of the block's column tile: entry i = tid + r * NW * 64
+    // holds column s = i / RB of output row iy0 + i % RB.
+    float2 pre[NPRE];
+    const float2* Yb = a.Yt + (size_t)zl * M * ny;
+    const size_t fstride = (size_t)a.g.nzc * M * ny;  // next frequency, same plane
+#pragma unroll
+    for (int r = 0; r < NPRE; ++r) {
+        const int i = tid + r * NW * 64;
+        const int iy = iy0 + i % RB;
+        pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
+    }
     float2* rows = sm + wave * SCRP;
-    for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
-        const int p = (b - a.g.b0) * a.g.nzc + zl;
-        const float2* Yp = a.Yt + (size_t)p * M * ny;
+    for (int b = a.g.b0; b < b_end; ++b) {
         __syncthreads();
-        for (int i = tid; i < M * RB; i += NW * 64) {
+#pragma unroll
+        for (int r = 0; r < NPRE; ++r) {
+            const int i = tid + r * NW * 64;
             const int s = i / RB, j = i % RB;
-            const int iy = iy0 + j;
-            sm[(j / LPW) * SCRP + (j % LPW) * M + s] = iy < ny ? Yp[(size_t)s * ny + iy] : make_float2(0.f, 0.f);
+            sm[(j / LPW) * SCRP + (j % LPW) * M + s] = pre[r];
         }
         __syncthreads();
+        if (b + 1 < b_end) {
+            Yb += fstride;
+#pragma unroll
+            for (int r = 0; r < NPRE; ++r) {
+                const int i = tid + r * NW * 64;
+                const int iy = iy0 + i % RB;
+                pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
+            }
+        }
         float2 v[F::NV];
 #pragma unroll
         for (int q = 0; q < LPW; ++q)
 #pragma unroll
             for (int e = 0; e < E; ++e) v[q * E + e] = rows[q * M + lane + 64 * e];
         F::template nat_to_perm<true>(v, rows, tws, lane);
-        const double foc = a.g.f[b] / kC;
 #pragma unroll
         for (int h = 0; h < F::GPL; ++h)
 #pragma unroll
@@ -275,7 +306,8 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
                 const float2 val = v[h * 8 + d];
                 if (off[sl] < 0) continue;
                 if (a.coherent) {
-                    acc[sl] = cadd(acc[sl], cmul(phase_of(dist[sl], foc), val));
+                    acc[sl] = cadd(acc[sl], cmul(ph[sl], val));
+                    ph[sl] = cmul(ph[sl], st[sl]);
                 } else {
                     acc[sl].x += sqrtf(val.x * val.x + val.y * val.y);
                 }
@@ -311,11 +343,11 @@ __global__ __launch_bounds__(kP2Waves * 64, 6) void k_propagate_cols_grouped(Gro
     persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M>(a, bx, by); });
 }
 template <int M, bool HALF>
-__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows(P3Args a) {
+__global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
     propagate_rows_body<M, HALF>(a, blockIdx.x, blockIdx.y);
 }
 template <int M, bool HALF>
-__global__ __launch_bounds__(p3_waves<M>() * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
+__global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows_grouped(Group<P3Args> g) {
     persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF>(a, bx, by); });
 }
 
@@ -385,16 +417,21 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
 }
 
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
+    if (!a.g.uni) return hipErrorInvalidValue;     // phases advance by a fixed step
     const bool half = 2 * a.nx <= a.M;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
-        constexpr int NW = p3_waves<MM>();
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
+        if (half) {
+            constexpr int NW = (p3_waves<MM, true>());
+            constexpr int RB = NW * F::LPW;
+            return launch_rsd((k_propagate_rows<MM, true>), dim3((a.ny + RB - 1) / RB, a.g.nzc), NW * 64,
+                              (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
+        }
+        constexpr int NW = (p3_waves<MM, false>());
         constexpr int RB = NW * F::LPW;
-        dim3 grid((a.ny + RB - 1) / RB, a.g.nzc);
-        const size_t sh = (size_t)(NW * SCRP + MM) * sizeof(float2);
-        if (half) return launch_rsd(k_propagate_rows<MM, true>, grid, NW * 64, sh, s, a);
-        return launch_rsd(k_propagate_rows<MM, false>, grid, NW * 64, sh, s, a);
+        return launch_rsd((k_propagate_rows<MM, false>), dim3((a.ny + RB - 1) / RB, a.g.nzc), NW * 64,
+                          (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
     })
 }
 
@@ -417,11 +454,15 @@ hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStrea
 hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s) {
     NURSD_SWITCH_M(M, {
         using F = WaveFFT<MM>;
-        constexpr int NW = p3_waves<MM>();
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
-        const size_t sh = (size_t)(NW * SCRP + MM) * sizeof(float2);
-        if (half) return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64, sh, s);
-        return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64, sh, s);
+        if (half) {
+            constexpr int NW = (p3_waves<MM, true>());
+            return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64,
+                                  (size_t)(NW * SCRP + MM) * sizeof(float2), s);
+        }
+        constexpr int NW = (p3_waves<MM, false>());
+        return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64,
+                              (size_t)(NW * SCRP + MM) * sizeof(float2), s);
     })
 }
 
@@ -438,9 +479,9 @@ int grid_x_propagate_cols(int M) {
     const int lpw = M >= 512 ? 1 : 512 / M;
     return (M / 2 + 1 + kP2Waves * lpw - 1) / (kP2Waves * lpw);
 }
-int rows_per_block_propagate(int M) {
+int rows_per_block_propagate(int M, bool half) {
     const int lpw = M >= 512 ? 1 : 512 / M;
-    return (M >= 1024 ? 8 : NURSD_P3_WAVES) * lpw;
+    return ((M >= 1024 || !half) ? 8 : NURSD_P3_WAVES) * lpw;
 }
 
 }  // namespace nursd

@@ -31,7 +31,7 @@ __device__ __forceinline__ float2 chirp(int n, double alpha_over_2M, float sgn) 
     const double cyc = alpha_over_2M * (double)((long long)n * n);
     const float fr = (float)(cyc - rint(cyc));
     float s, c;
-    sincospif(2.0f * fr, &s, &c);
+    sincos_cycles(fr, &s, &c);
     return make_float2(c, sgn * s);
 }
 

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
             const double cyc = dd * (a.g.f[b] / kC);
             const float fr = (float)(cyc - rint(cyc));
             float sn, cs;
-            sincospif(2.0f * fr, &sn, &cs);
+            sincos_cycles(fr, &sn, &cs);
             acc = cadd(acc, cmul(make_float2(cs, sn), s));
         } else {
             acc.x += sqrtf(s.x * s.x + s.y * s.y);

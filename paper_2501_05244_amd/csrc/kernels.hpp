@@ -79,6 +79,8 @@ struct ChunkGeom {
     const double* pitch_x;  // per-plane kernel pitch (SRSD) or NULL (use dx)
     const double* pitch_y;
     double dx, dy;      // kernel sampling pitch
+    int uni;            // 1: f[b0 + i] = f[b0] + i * df for the whole chunk
+    double df;          // frequency step of the chunk when uni = 1
 };
 
 struct P1Args {
@@ -201,7 +203,7 @@ hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStrea
 hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s);
 int grid_x_kernel_rows(int M);
 int grid_x_propagate_cols(int M);
-int rows_per_block_propagate(int M);
+int rows_per_block_propagate(int M, bool half);
 int fine_y_lines();
 int phasor_group();
 hipError_t launch_zero_counters(int* c, int n, hipStream_t s);
