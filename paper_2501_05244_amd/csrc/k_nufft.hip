@@ -20,16 +20,27 @@
 namespace nursd {
 
 constexpr int kSpreadThreads = 1024;
+// LDS row stride of a band: 8 cells of padding put the 8 tap rows of one
+// sample on different banks.
+template <int MF>
+constexpr int spread_row_stride() { return MF + 8; }
 
-__device__ __forceinline__ float es_kernel(float z, float beta) {
+// psi(z) = exp(beta (sqrt(1 - z^2) - 1)) with the hardware square root and
+// base-2 exponential (beta_log2e = beta / ln 2).
+__device__ __forceinline__ float es_kernel(float z, float beta_log2e) {
     const float t = fmaxf(1.0f - z * z, 0.0f);
-    return __expf(beta * (sqrtf(t) - 1.0f));
+    return __builtin_amdgcn_exp2f(beta_log2e * (__builtin_amdgcn_sqrtf(t) - 1.0f));
+}
+
+__device__ __forceinline__ float lane_f(float v, int j) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
 
 template <int MF>
 __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, int by) {
     constexpr int kBandRows = spread_band_rows(MF);
-    extern __shared__ float2 tile[];   // [kBandRows][MF]
+    constexpr int LDT = spread_row_stride<MF>();
+    extern __shared__ float2 tile[];   // [kBandRows][LDT]
     const int band = bx;
     const int b = a.b0 + by;
     const int tid = threadIdx.x;
@@ -45,7 +56,7 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
         }
         return;
     }
-    for (int i = tid; i < kBandRows * MF; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
+    for (int i = tid; i < kBandRows * LDT; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
     constexpr int kCols = MF / kSpreadWaves;          // columns owned by one wave
@@ -53,7 +64,8 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     const int wave = tid >> 6, lane = tid & 63;
     const int c_lo = wave * kCols, c_hi = c_lo + kCols;
     const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
-    const float hw = a.half_w;
+    const float inv_hw = 1.0f / a.half_w;
+    const float bl2e = a.beta * 1.4426950408889634f;
     const int w = a.w;
     const int s0 = a.wave_rng[(band * kSpreadWaves + wave) * 2];
     const int s1 = a.wave_rng[(band * kSpreadWaves + wave) * 2 + 1];
@@ -75,14 +87,15 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
         }
         const int cnt = min(64, s1 - base);
         for (int j = 0; j < cnt; ++j) {
-            const int pk = __shfl(packed, j);
-            const float fx = __shfl(efx, j), fy = __shfl(efy, j);
-            const float px = __shfl(ep.x, j), py = __shfl(ep.y, j);
+            // entry j of the batch, broadcast through scalar registers
+            const int pk = __builtin_amdgcn_readlane(packed, j);
+            const float fx = lane_f(efx, j), fy = lane_f(efy, j);
+            const float px = lane_f(ep.x, j), py = lane_f(ep.y, j);
             const int cx = (int)(short)(pk & 0xffff) + ti;
             const int cy = (pk >> 16) + tj;
             if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
-                const float wgt = es_kernel(((float)ti - fx) / hw, a.beta) * es_kernel(((float)tj - fy) / hw, a.beta);
-                float2* cell = &tile[(cy - y0) * MF + cx];
+                const float wgt = es_kernel(((float)ti - fx) * inv_hw, bl2e) * es_kernel(((float)tj - fy) * inv_hw, bl2e);
+                float2* cell = &tile[(cy - y0) * LDT + cx];
                 float2 c = *cell;
                 c.x = fmaf(px, wgt, c.x);
                 c.y = fmaf(py, wgt, c.y);
@@ -91,12 +104,12 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
         }
     }
     __syncthreads();
-    fft_lines<MF, kSpreadThreads / kBandRows, false>(tile, MF, kBandRows, a.tw);
+    fft_lines<MF, kSpreadThreads / kBandRows, false>(tile, LDT, kBandRows, a.tw);
     // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
     for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
         const int km = i / kBandRows, r = i % kBandRows;      // km = kx mod M
         const int kf = km < M / 2 ? km : km + (MF - M);       // kx mod MF
-        const float2 v = tile[r * MF + kf];
+        const float2 v = tile[r * LDT + kf];
         T1[(size_t)km * MF + y0 + r] = cscale(v, a.decx[km]);
     }
 }
@@ -169,7 +182,7 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
 template <int MF>
 static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
     constexpr int kBandRows = spread_band_rows(MF);
-    size_t sh = (size_t)kBandRows * MF * sizeof(float2);
+    size_t sh = (size_t)kBandRows * spread_row_stride<MF>() * sizeof(float2);
     hipError_t e = hipFuncSetAttribute((const void*)k_spread_xfft<MF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
@@ -214,7 +227,7 @@ hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStr
     switch (Mf) {
 #define NURSD_SG(n) \
     case n: return launch_grouped(k_spread_xfft_grouped<n>, g, kSpreadThreads, \
-                                  (size_t)spread_band_rows(n) * n * sizeof(float2), s);
+                                  (size_t)spread_band_rows(n) * spread_row_stride<n>() * sizeof(float2), s);
         NURSD_SG(128) NURSD_SG(256) NURSD_SG(512) NURSD_SG(1024) NURSD_SG(2048)
 #undef NURSD_SG
         default: return hipErrorInvalidValue;

@@ -331,7 +331,7 @@ __global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
     kernel_rows_body<M>(a, blockIdx.x, blockIdx.y);
 }
 template <int M>
-__global__ __launch_bounds__(kP1Waves * 64, 8) void k_kernel_rows_grouped(Group<P1Args> g) {
+__global__ __launch_bounds__(kP1Waves * 64, (M >= 1024 ? 4 : 8)) void k_kernel_rows_grouped(Group<P1Args> g) {
     persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M>(a, bx, by); });
 }
 template <int M>
