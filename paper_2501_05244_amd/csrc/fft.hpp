@@ -34,6 +34,15 @@ __device__ __forceinline__ void sincos_cycles(float x, float* s, float* c) {
     *s = __builtin_amdgcn_sinf(x);
     *c = __builtin_amdgcn_cosf(x);
 }
+// sqrt(d2) to FP64 accuracy: hardware FP32 square root and reciprocal as the
+// estimate d0, then one Newton step d0 + (d2 - d0^2) / (2 d0) in FP64.  The
+// reciprocal of the estimate is returned in *inv (relative error ~1e-7).
+__device__ __forceinline__ double sqrt_f64(double d2, float* inv) {
+    const float d0 = __builtin_amdgcn_sqrtf((float)d2);
+    const float i0 = __builtin_amdgcn_rcpf(d0);
+    *inv = i0;
+    return (double)d0 + (d2 - (double)d0 * (double)d0) * (double)(0.5f * i0);
+}
 __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
 // multiply by -j (forward) or +j (inverse)
 template <bool INV>

@@ -29,8 +29,8 @@ namespace nursd {
 
 __device__ __forceinline__ double adj_dist(double x, double y, double z) {
     const double d2 = x * x + y * y + z * z;
-    const float d0 = sqrtf((float)d2);
-    return (double)d0 + (d2 - (double)d0 * (double)d0) * (double)(0.5f / d0);
+    float inv;
+    return sqrt_f64(d2, &inv);
 }
 
 __device__ __forceinline__ float2 adj_phase(double d, double foc) {

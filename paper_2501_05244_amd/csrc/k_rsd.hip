@@ -28,13 +28,12 @@ namespace nursd {
 // e^{+j 2 pi (r f / c)} / r for r = sqrt(r2); the cycle count r f / c is
 // formed in FP64 and reduced to [-1/2, 1/2] before the FP32 sin/cos.
 __device__ __forceinline__ float2 rsd_kernel(double r2, double f_over_c) {
-    const float r0 = sqrtf((float)r2);
-    const double r = (double)r0 + (r2 - (double)r0 * (double)r0) * (double)(0.5f / r0);
+    float ir;
+    const double r = sqrt_f64(r2, &ir);
     const double cyc = r * f_over_c;
     const float fr = (float)(cyc - rint(cyc));
     float s, c;
     sincos_cycles(fr, &s, &c);
-    const float ir = 1.0f / (float)r;
     return make_float2(c * ir, s * ir);
 }
 
@@ -49,8 +48,8 @@ __device__ __forceinline__ float2 phase_of(double d, double f_over_c) {
 
 __device__ __forceinline__ double dist3(double x, double y, double z) {
     const double d2 = x * x + y * y + z * z;
-    const float d0 = sqrtf((float)d2);
-    return (double)d0 + (d2 - (double)d0 * (double)d0) * (double)(0.5f / d0);
+    float inv;
+    return sqrt_f64(d2, &inv);
 }
 
 __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int& iz) {

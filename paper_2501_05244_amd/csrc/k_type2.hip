@@ -135,8 +135,8 @@ __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
 
 __device__ __forceinline__ double dist3d(double x, double y, double z) {
     const double d2 = x * x + y * y + z * z;
-    const float d0 = sqrtf((float)d2);
-    return (double)d0 + (d2 - (double)d0 * (double)d0) * (double)(0.5f / d0);
+    float inv;
+    return sqrt_f64(d2, &inv);
 }
 
 constexpr int kInterpThreads = 256;
