@@ -313,6 +313,35 @@ def srsd(P, relay_xy, f, frame: Frame, grid, xp, alphas):
     return out
 
 
+def srsd_points(P, relay_xy, f, frame: Frame, N, z, alphas, plane_ptr, voxel_xy, xp):
+    """Fusion of the scaled RSD with NURSD-2 (eq. NURSD2_SRSD): per plane, the
+    scaled spectrum S of the uniform relay grid u (as in srsd) times the DFT
+    of G sampled at pitch dx / alpha, evaluated at the plane's voxel list by a
+    direct NUDFT-2 in the scaled frame (period M dx / alpha around the frame
+    centre).  Returns V complex [V]."""
+    xt = rescale(relay_xy[:, 0], frame.cx, frame.Lx)
+    yt = rescale(relay_xy[:, 1], frame.cy, frame.Ly)
+    vx = np.asarray(voxel_xy[:, 0], dtype=np.float64)
+    vy = np.asarray(voxel_xy[:, 1], dtype=np.float64)
+    M = frame.M
+    z = np.asarray(z, dtype=np.float64)
+    out = np.zeros(len(vx), dtype=np.complex128)
+    for b, fb in enumerate(f):
+        U = nudft1(P[b], xt, yt, M)
+        u = relay_grid(U, N)                         # [nx][ny]
+        for iz, zz in enumerate(z):
+            a0, e0 = int(plane_ptr[iz]), int(plane_ptr[iz + 1])
+            if a0 == e0:
+                continue
+            a = float(alphas[iz])
+            S = scaled_dft(scaled_dft(u, a, M).T, a, M).T
+            Gh = dft2(kernel_samples(fb, zz, M, frame.dx / a, frame.dy / a))
+            vals = nudft2(S * Gh, rescale(vx[a0:e0], frame.cx, frame.Lx / a),
+                          rescale(vy[a0:e0], frame.cy, frame.Ly / a)) / (M * M)
+            out[a0:e0] += illumination_phase(fb, vx[a0:e0], vy[a0:e0], zz, xp) * vals
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Step 8: adjoint of the uniform-grid operator and the loss gradients.
 # ---------------------------------------------------------------------------

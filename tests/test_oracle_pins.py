@@ -286,6 +286,52 @@ def test_srsd_equals_nursd_in_stretched_frame():
     assert rel(Vs, V2) < 1e-11
 
 
+def test_srsd_points_at_scaled_grid_voxels_equals_srsd():
+    # Voxel lists placed on each plane's scaled grid c + m dx / alpha must
+    # reproduce the uniform scaled RSD there (planes with different alpha).
+    rng = np.random.default_rng(21)
+    grid, xy, frame, f, P = _on_grid_case(rng, M=32, n=8, L=20)
+    xy = xy + rng.uniform(-0.006, 0.006, size=xy.shape)        # off grid
+    xp = np.array([0.01, -0.02, 0.0])
+    alphas = np.array([0.8, 0.45])
+    Vs = o.srsd(P, xy, f, frame, grid, xp, alphas)               # [Z][ny][nx]
+    m = np.arange(grid.nx) - grid.nx // 2
+    pick = [rng.choice(grid.nx * grid.ny, 11, replace=False), rng.choice(grid.nx * grid.ny, 7, replace=False)]
+    vox, ref = [], []
+    for iz, a in enumerate(alphas):
+        iy, ix = np.divmod(pick[iz], grid.nx)
+        vox.append(np.stack([frame.cx + m[ix] * grid.dx / a, frame.cy + m[iy] * grid.dy / a], 1))
+        ref.append(Vs[iz, iy, ix])
+    ptr = np.array([0, len(pick[0]), len(pick[0]) + len(pick[1])])
+    V = o.srsd_points(P, xy, f, frame, grid.nx, grid.z, alphas, ptr, np.concatenate(vox), xp)
+    assert rel(V, np.concatenate(ref)) < 1e-11
+
+
+def test_srsd_points_equals_nursd_points_in_stretched_frame():
+    # Independent route at arbitrary voxels: NURSD-3 in a frame of pitch
+    # dx / alpha, fed with the uniform relay grid u at its physical positions.
+    rng = np.random.default_rng(22)
+    grid, xy, frame, f, P = _on_grid_case(rng, M=32, n=8, L=20, zs=(0.2,))
+    xy = xy + rng.uniform(-0.006, 0.006, size=xy.shape)
+    alpha = 0.6
+    xp = np.array([0.0, 0.01, 0.0])
+    n = grid.nx
+    half = 0.5 * frame.M * grid.dx / alpha
+    vox = rng.uniform(-0.45 * half, 0.45 * half, size=(13, 2))
+    ptr = np.array([0, len(vox)])
+    V = o.srsd_points(P, xy, f, frame, n, grid.z, np.array([alpha]), ptr, vox, xp)
+    m = np.arange(n) - n // 2
+    u = [o.relay_grid(o.nudft1(P[b], o.rescale(xy[:, 0], 0, frame.Lx),
+                                o.rescale(xy[:, 1], 0, frame.Ly), frame.M), n) for b in range(len(f))]
+    X, Y = np.meshgrid(m * grid.dx, m * grid.dx, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], 1)
+    Pu = np.stack([ub.ravel() for ub in u])
+    d2 = grid.dx / alpha
+    fr2 = o.Frame(frame.M, d2, d2, 0.0, 0.0)
+    ref = o.nursd_points(Pu, pts, f, fr2, grid.z, ptr, vox, xp)
+    assert rel(V, ref) < 1e-11
+
+
 # ------------------------------------------------------------------ step 8
 def _adj_case(rng):
     grid, xy, frame, f, P = _on_grid_case(rng, M=16, n=6, L=12, zs=(0.12, 0.2))
