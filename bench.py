@@ -124,7 +124,8 @@ def time_ms(fn, reps: int) -> float:
 
 def secondary(w_spad, dev) -> dict:
     """The other hot-path rows on their own workloads: scaled RSD frustum,
-    NURSD-3 voxel lists, forward + adjoint, and batched vs plain serving."""
+    NURSD-3 voxel lists, scaled RSD at voxel lists, forward + adjoint, and
+    batched vs plain serving."""
     import torch
     from paper_2501_05244_amd.api import Batch, plan_from_workload
     from paper_2501_05244_amd.autograd import nursd
@@ -146,6 +147,14 @@ def secondary(w_spad, dev) -> dict:
     ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 3)
     out["nursd3_points"] = {"workload": "points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
                             "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
+    del plan
+    # scaled RSD at voxel lists: the same 1,048,576 frustum voxels on 64 scaled planes
+    w = scenes.config_srsd_points(render=False)
+    plan = plan_from_workload(w, dev)
+    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
+    ms = time_ms(lambda: plan.forward_hist(hist, vol=False, out_I=I), 3)
+    out["srsd_points"] = {"workload": "srsd_points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
+                          "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
     del plan
     # differentiation: forward + adjoint (grad P and grad xy) through autograd
     w = scenes.config_diff()

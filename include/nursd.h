@@ -52,6 +52,8 @@ extern "C" {
 #define NURSD_MODE_GRID 0   /* uniform voxel grid, NURSD-1                  */
 #define NURSD_MODE_POINTS 1 /* per-plane voxel lists, NURSD-3 (or NURSD-2)  */
 #define NURSD_MODE_SRSD 2   /* scaled RSD frustum                           */
+#define NURSD_MODE_SRSD_POINTS 3 /* scaled RSD at per-plane voxel lists
+                                    (eq. NURSD2_SRSD)                       */
 
 /* Phasor-field wavelet and temporal sampling (eq. PF_Response,
  * eq. PFPacket_Omega_Supp).  The F frequencies are DFT bins b of the T-bin
@@ -80,7 +82,12 @@ typedef struct {
  *         (dx, dy) / alpha_iz, alpha_iz = alpha[iz] if alpha != NULL else
  *         zref / z[iz]; voxel (ix, iy) of plane iz lies at
  *         c + ((ix - nx/2) dx, (iy - ny/2) dy) / alpha_iz with
- *         c = (x0 + (nx/2) dx, y0 + (ny/2) dy).  Requires 0 < alpha <= 1. */
+ *         c = (x0 + (nx/2) dx, y0 + (ny/2) dy).  Requires 0 < alpha <= 1.
+ * SRSD_POINTS: the SRSD relay grid and scales, evaluated at per-plane voxel
+ *         lists (plane_ptr, voxel_xy_dev as in POINTS) by a type-2 NUFFT in
+ *         each plane's scaled frame (period M dx / alpha_iz around c), the
+ *         fusion of the scaled RSD with NURSD-2 (eq. NURSD2_SRSD); outputs
+ *         are [V].  Requires nx == ny and a transform size M >= 512. */
 typedef struct {
     int32_t mode;
     double x0, y0;
@@ -88,10 +95,10 @@ typedef struct {
     int32_t nx, ny;
     int32_t nz;
     const double* z;            /* host [nz], each > 0                          */
-    const int32_t* plane_ptr;   /* host [nz+1] (POINTS)                         */
-    const float* voxel_xy_dev;  /* device [V][2] (POINTS)                       */
-    double zref;                /* SRSD                                         */
-    const double* alpha;        /* host [nz] (SRSD) or NULL                     */
+    const int32_t* plane_ptr;   /* host [nz+1] (POINTS, SRSD_POINTS)            */
+    const float* voxel_xy_dev;  /* device [V][2] (POINTS, SRSD_POINTS)          */
+    double zref;                /* SRSD, SRSD_POINTS                            */
+    const double* alpha;        /* host [nz] (SRSD, SRSD_POINTS) or NULL        */
     double xp[3];               /* illumination point x_p                       */
 } nursd_geometry;
 

@@ -21,7 +21,7 @@ ERRORS = {
     -5: "NURSD_ERR_HIP",
     -6: "NURSD_ERR_UNIMPLEMENTED",
 }
-MODE_GRID, MODE_POINTS, MODE_SRSD = 0, 1, 2
+MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS = 0, 1, 2, 3
 STAGES = ["phasor", "spread", "fine_y", "kernel_rows", "propagate_cols", "propagate_rows", "chirp_rows",
           "relay_grid", "type2", "adjoint"]
 NUM_STAGES = 16
@@ -114,4 +114,4 @@ def c_float_p(v) -> c_void_p:
 
 
 __all__ = ["load", "check", "Wavelet", "Geometry", "Options", "PlanInfo", "SIGNATURES",
-           "MODE_GRID", "MODE_POINTS", "MODE_SRSD", "c_float"]
+           "MODE_GRID", "MODE_POINTS", "MODE_SRSD", "MODE_SRSD_POINTS", "c_float"]

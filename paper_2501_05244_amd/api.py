@@ -13,7 +13,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import MODE_GRID, MODE_POINTS, MODE_SRSD, Geometry, Options, PlanInfo, Wavelet, check
+from ._lib import MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS, Geometry, Options, PlanInfo, Wavelet, check
 
 
 def _stream(stream=None) -> c_void_p:
@@ -121,7 +121,7 @@ class Plan:
         return c_void_p(p), c_size_t(int(self.info["workspace_bytes"]))
 
     def out_shape(self):
-        if self.mode == MODE_POINTS:
+        if self.mode in (MODE_POINTS, MODE_SRSD_POINTS):
             return (self.info["n_voxels"],)
         return (self.nz, self.ny, self.nx)
 
@@ -250,12 +250,12 @@ def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) ->
     wl, g = w.wavelet, w.grid
     if relay_xy is None:
         relay_xy = torch.from_numpy(np.ascontiguousarray(w.relay_xy)).to(device)
-    mode = {"grid": MODE_GRID, "points": MODE_POINTS, "srsd": MODE_SRSD}[w.mode]
+    mode = {"grid": MODE_GRID, "points": MODE_POINTS, "srsd": MODE_SRSD, "srsd_points": MODE_SRSD_POINTS}[w.mode]
     extra = {}
-    if w.mode == "points":
+    if w.mode in ("points", "srsd_points"):
         extra["plane_ptr"] = w.plane_ptr
         extra["voxel_xy"] = torch.from_numpy(np.ascontiguousarray(w.voxel_xy)).to(device)
-    if w.mode == "srsd":
+    if w.mode in ("srsd", "srsd_points"):
         extra["zref"] = w.zref
     args = dict(lambda_c=wl.lambda_c, n_time=wl.n_time, dt=wl.dt, t0=wl.t0, n_freq=wl.n_freq, z=g.z,
                 mode=mode, x0=g.x0, y0=g.y0, dx=g.dx, dy=g.dy, nx=g.nx, ny=g.ny, bins=wl.bins,

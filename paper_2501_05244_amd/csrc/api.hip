@@ -155,9 +155,11 @@ struct nursd_plan {
         for (void* p : owned) (void)hipFree(p);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     }
+    bool has_lists() const { return mode == NURSD_MODE_POINTS || mode == NURSD_MODE_SRSD_POINTS; }
+    bool scaled() const { return mode == NURSD_MODE_SRSD || mode == NURSD_MODE_SRSD_POINTS; }
     const float2* tw(int n) const { return tw_all + tw_off[__builtin_ctz((unsigned)n)]; }
     int nvox() const {
-        return mode == NURSD_MODE_POINTS ? (plane_ptr.empty() ? 0 : plane_ptr.back()) : nx * ny * nz;
+        return has_lists() ? (plane_ptr.empty() ? 0 : plane_ptr.back()) : nx * ny * nz;
     }
 };
 
@@ -354,7 +356,7 @@ void layout_workspace(nursd_plan* p) {
     o = align_up(o + planes * (p->M / 2 + 1) * p->BS * c8);
     p->off_Yt = o;
     o = align_up(o + planes * p->ny * p->M * c8);
-    if (p->mode == NURSD_MODE_POINTS) {
+    if (p->has_lists()) {
         p->off_T2 = o;
         o = align_up(o + planes * p->M * p->Mf * c8);
         p->off_G2 = o;
@@ -368,7 +370,7 @@ void layout_workspace(nursd_plan* p) {
         p->off_G3 = o;
         o = align_up(o + (size_t)p->FC3 * 3 * p->Mf * p->Mf * c8);
     }
-    if (p->mode == NURSD_MODE_SRSD) {
+    if (p->scaled()) {
         p->off_Tg = o;
         o = align_up(o + (size_t)p->F * p->M * p->nx * c8);
         p->off_u = o;
@@ -385,6 +387,17 @@ int check_ws(const nursd_plan* p, void* ws, size_t bytes) {
     if (bytes < p->ws_bytes)
         return fail(NURSD_ERR_WORKSPACE, "workspace too small: need " + std::to_string(p->ws_bytes) + " bytes");
     return NURSD_OK;
+}
+
+// Copies the CSR plane pointers and reads the voxel positions to the host.
+int read_voxel_lists(nursd_plan* p, const nursd_geometry* geo, std::vector<float>& vxy, hipStream_t s) {
+    p->plane_ptr.assign(geo->plane_ptr, geo->plane_ptr + p->nz + 1);
+    p->voxel_xy_dev = geo->voxel_xy_dev;
+    const int V = p->plane_ptr.back();
+    for (int i = 0; i < p->nz; ++i)
+        if (p->plane_ptr[i + 1] < p->plane_ptr[i]) return fail(NURSD_ERR_ARG, "plane_ptr must be non-decreasing");
+    if (p->plane_ptr[0] != 0 || V < 1) return fail(NURSD_ERR_ARG, "plane_ptr must start at 0 and list voxels");
+    return read_points(geo->voxel_xy_dev, (size_t)V * 2, vxy, s);
 }
 
 bool even_bins(const nursd_plan* p) {
@@ -538,6 +551,9 @@ int run_srsd(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipS
     return NURSD_OK;
 }
 
+Type2Args type2_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, const float2* U, float2* V, float* I,
+                     char* ws, int b0, int nb);
+
 int run_points(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
     float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
     for (int b0 = 0; b0 < p->F; b0 += p->FC) {
@@ -547,36 +563,89 @@ int run_points(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hi
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
             P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
-            Type2Args t{};
-            t.g = g;
-            t.Bt = Bt;
-            t.U = U;
-            t.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
-            t.G2 = reinterpret_cast<float2*>(ws + p->off_G2);
-            t.V = V;
-            t.I = I;
-            t.dec = p->d_decy;
-            t.tw_m = p->tw(p->M);
-            t.tw_f = p->tw(p->Mf);
-            t.M = p->M;
-            t.Mf = p->Mf;
-            t.BS = p->BS;
-            t.w = p->w;
-            t.beta = (float)p->beta;
-            t.cx = p->cx;
-            t.cy = p->cy;
-            t.xp0 = p->xp[0];
-            t.xp1 = p->xp[1];
-            t.xp2 = p->xp[2];
-            t.plane_ptr = p->d_plane_ptr;
-            t.voxel_xy = p->voxel_xy_dev;
-            t.row_lo = p->d_row_lo;
-            t.row_hi = p->d_row_hi;
-            t.max_vox = p->max_vox;
-            t.first = b0 == 0;
-            t.last = b0 + nb >= p->F;
-            t.coherent = p->coherent;
+            Type2Args t = type2_args(p, g, Bt, U, V, I, ws, b0, nb);
             LAUNCH(p, NURSD_STAGE_TYPE2, Type2Args, launch_type2, t, s);
+        }
+    }
+    return NURSD_OK;
+}
+
+Type2Args type2_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, const float2* U, float2* V, float* I,
+                     char* ws, int b0, int nb) {
+    Type2Args t{};
+    t.g = g;
+    t.Bt = Bt;
+    t.U = U;
+    t.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
+    t.G2 = reinterpret_cast<float2*>(ws + p->off_G2);
+    t.V = V;
+    t.I = I;
+    t.dec = p->d_decy;
+    t.tw_m = p->tw(p->M);
+    t.tw_f = p->tw(p->Mf);
+    t.M = p->M;
+    t.Mf = p->Mf;
+    t.BS = p->BS;
+    t.w = p->w;
+    t.beta = (float)p->beta;
+    t.cx = p->cx;
+    t.cy = p->cy;
+    t.xp0 = p->xp[0];
+    t.xp1 = p->xp[1];
+    t.xp2 = p->xp[2];
+    t.plane_ptr = p->d_plane_ptr;
+    t.voxel_xy = p->voxel_xy_dev;
+    t.row_lo = p->d_row_lo;
+    t.row_hi = p->d_row_hi;
+    t.max_vox = p->max_vox;
+    t.first = b0 == 0;
+    t.last = b0 + nb >= p->F;
+    t.coherent = p->coherent;
+    return t;
+}
+
+// Scaled RSD evaluated at per-plane voxel lists (eq. NURSD2_SRSD): relay
+// grid, kernel rows at pitch d/alpha, Bluestein rows, then per column the
+// scaled spectrum times the kernel spectrum handed to the type-2 steps.
+int run_srsd_points(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipStream_t s) {
+    float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
+    float2* u = reinterpret_cast<float2*>(ws + p->off_u);
+    RelayGridArgs ra{};
+    ra.U = U;
+    ra.Tg = reinterpret_cast<float2*>(ws + p->off_Tg);
+    ra.u = u;
+    ra.M = p->M;
+    ra.N = p->nx;
+    ra.b0 = 0;
+    ra.nb = p->F;
+    ra.tw_m = p->tw(p->M);
+    LAUNCH(p, NURSD_STAGE_RELAY_GRID, RelayGridArgs, launch_relay_grid, ra, s);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            ChirpArgs ca{};
+            ca.g = g;
+            ca.u = u;
+            ca.S1t = reinterpret_cast<float2*>(ws + p->off_S1);
+            ca.Bt = Bt;
+            ca.M = p->M;
+            ca.N = p->nx;
+            ca.BS = p->BS;
+            ca.ny = p->ny;
+            ca.alpha = p->d_alpha;
+            ca.hhat = p->d_hhat;
+            ca.tw_m = p->tw(p->M);
+            ca.tw_lb = p->tw(2 * p->M);
+            ca.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
+            ca.dec = p->d_decy;
+            LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, ChirpArgs, launch_chirp_type2_cols, ca, s);
+            Type2Args t = type2_args(p, g, Bt, U, V, I, ws, b0, nb);
+            LAUNCH(p, NURSD_STAGE_TYPE2, Type2Args, launch_type2_fine, t, s);
         }
     }
     return NURSD_OK;
@@ -590,6 +659,7 @@ int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws
     if (!p->coherent) V = nullptr;
     if (p->mode == NURSD_MODE_SRSD) return run_srsd(p, U, V, I, ws, s);
     if (p->mode == NURSD_MODE_POINTS) return run_points(p, U, V, I, ws, s);
+    if (p->mode == NURSD_MODE_SRSD_POINTS) return run_srsd_points(p, U, V, I, ws, s);
     return run_grid_propagation(p, U, V, I, ws, s);
 }
 
@@ -1074,7 +1144,8 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     for (int b : p->bins) p->freqs.push_back(b * df);
     // geometry
     p->mode = geo->mode;
-    if (p->mode != NURSD_MODE_GRID && p->mode != NURSD_MODE_POINTS && p->mode != NURSD_MODE_SRSD)
+    if (p->mode != NURSD_MODE_GRID && p->mode != NURSD_MODE_POINTS && p->mode != NURSD_MODE_SRSD &&
+        p->mode != NURSD_MODE_SRSD_POINTS)
         return bail(fail(NURSD_ERR_ARG, "unknown mode"));
     if (geo->nz < 1 || !geo->z) return bail(fail(NURSD_ERR_ARG, "no planes"));
     p->nz = geo->nz;
@@ -1107,7 +1178,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
 
     double vlo[2], vhi[2], mmin = 0;
     std::vector<float> vxy;
-    if (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_SRSD) {
+    if (p->mode == NURSD_MODE_GRID || p->scaled()) {
         if (p->nx < 1 || p->ny < 1) return bail(fail(NURSD_ERR_ARG, "nx, ny must be >= 1"));
         p->dx = p->vdx;
         p->dy = p->vdy;
@@ -1118,7 +1189,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         vhi[0] = p->x0 + (p->nx - 1) * p->dx;
         vhi[1] = p->y0 + (p->ny - 1) * p->dy;
         mmin = p->pad * std::max(p->nx, p->ny);
-        if (p->mode == NURSD_MODE_SRSD) {
+        if (p->scaled()) {
             p->zref = geo->zref;
             for (int i = 0; i < p->nz; ++i) {
                 const double a = geo->alpha ? geo->alpha[i] : geo->zref / p->z[i];
@@ -1126,18 +1197,17 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
                 p->alpha.push_back(a);
             }
         }
+        if (p->mode == NURSD_MODE_SRSD_POINTS) {
+            if (!geo->plane_ptr || !geo->voxel_xy_dev)
+                return bail(fail(NURSD_ERR_ARG, "SRSD_POINTS mode needs plane_ptr and voxel_xy_dev"));
+            if ((rc = read_voxel_lists(p, geo, vxy, s))) return bail(rc);
+        }
     } else {
         if (!geo->plane_ptr || !geo->voxel_xy_dev) return bail(fail(NURSD_ERR_ARG, "POINTS mode needs plane_ptr and voxel_xy_dev"));
-        p->plane_ptr.assign(geo->plane_ptr, geo->plane_ptr + p->nz + 1);
-        p->voxel_xy_dev = geo->voxel_xy_dev;
         p->dx = p->vdx;
         p->dy = p->vdy;
+        if ((rc = read_voxel_lists(p, geo, vxy, s))) return bail(rc);
         const int V = p->plane_ptr.back();
-        for (int i = 0; i < p->nz; ++i)
-            if (p->plane_ptr[i + 1] < p->plane_ptr[i]) return bail(fail(NURSD_ERR_ARG, "plane_ptr must be non-decreasing"));
-        if (p->plane_ptr[0] != 0 || V < 1) return bail(fail(NURSD_ERR_ARG, "plane_ptr must start at 0 and list voxels"));
-        rc = read_points(geo->voxel_xy_dev, (size_t)V * 2, vxy, s);
-        if (rc) return bail(rc);
         double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
         for (int i = 0; i < V; ++i)
             for (int a = 0; a < 2; ++a) {
@@ -1169,20 +1239,22 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     if (!p->M) return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
     p->Mf = 2 * p->M;
     p->BS = (p->M / 2 + 1 + 7) / 8 * 8;
-    if (p->mode == NURSD_MODE_SRSD) {
+    if (p->scaled()) {
         if (p->nx != p->ny) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a square grid (nx == ny)"));
         if (p->M < 512) return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "SRSD needs a transform size M >= 512"));
     }
-    if (p->mode == NURSD_MODE_POINTS) {
+    if (p->has_lists()) {
         if (p->M < 512)
             return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "voxel lists need a transform size M >= 512 (set options.M)"));
-        // fine rows each plane's interpolation can reach (centred fine cells)
+        // fine rows each plane's interpolation can reach (centred fine cells;
+        // a scaled plane has pitch dy / alpha)
         std::vector<int> lo(p->nz), hi(p->nz);
         const double hw = 0.5 * p->w;
         for (int iz = 0; iz < p->nz; ++iz) {
             int a = 1 << 30, c = -(1 << 30);
+            const double pitch = p->mode == NURSD_MODE_SRSD_POINTS ? p->dy / p->alpha[iz] : p->dy;
             for (int v = p->plane_ptr[iz]; v < p->plane_ptr[iz + 1]; ++v) {
-                const double ty = ((double)vxy[2 * v + 1] - p->cy) / p->dy * 2.0 + p->Mf / 2;
+                const double ty = ((double)vxy[2 * v + 1] - p->cy) / pitch * 2.0 + p->Mf / 2;
                 const int iy0 = (int)std::ceil(ty - hw);
                 a = std::min(a, iy0);
                 c = std::max(c, iy0 + p->w - 1);
@@ -1211,7 +1283,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     // fixed factor: uneven bin lists run one frequency per chunk
     if (!even_bins(p)) p->FC = 1;
     p->ZC = opt->plane_chunk > 0 ? opt->plane_chunk : (int)std::max(1L, target / p->FC);
-    if (p->mode == NURSD_MODE_POINTS && opt->plane_chunk <= 0) p->ZC = std::max(1, 32 / p->FC);
+    if (p->has_lists() && opt->plane_chunk <= 0) p->ZC = std::max(1, 32 / p->FC);
     p->ZC = std::min(p->ZC, p->nz);
     p->FCn = std::min(p->F, 16);
 
@@ -1244,7 +1316,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if ((rc = upload(p, tb, &p->d_tb))) return bail(rc);
         if ((rc = upload(p, p->freqs, &p->d_f))) return bail(rc);
         if ((rc = upload(p, p->z, &p->d_z))) return bail(rc);
-        if (p->mode == NURSD_MODE_SRSD) {
+        if (p->scaled()) {
             std::vector<double> px, py;
             for (double a : p->alpha) {
                 px.push_back(p->dx / a);

@@ -248,6 +248,102 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_cols(ChirpArgs a) {
     }
 }
 
+// Voxel-list output on the scaled planes (eq. NURSD2_SRSD): as k_chirp_cols
+// up to the product S[s][ky] Ghat'[kx][ky]; then the type-2 steps of the
+// NUFFT section along y: deconvolve by the kernel's Fourier coefficients in
+// x and y, zero-pad to the 2M-point oversampled line, inverse FFT
+// -> T2[p][s][jy].  The oversampled line has the Bluestein length 2M, so it
+// shares that transform's twiddles and scratch.
+template <int M>
+__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
+    using F = WaveFFT<M>;
+    using B = WaveFFT<2 * M>;
+    constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E, MF = 2 * M;
+    static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
+    constexpr int SCRP = B::SCR + 1;
+    static_assert(SCRP >= MF, "oversampled line must fit the scratch");
+    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles LB, twiddles M
+    float2* tws_lb = sm + kChirpWaves * SCRP;
+    float2* tws_m = tws_lb + LB;
+    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws_lb[i] = a.tw_lb[i];
+    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws_m[i] = a.tw_m[i];
+    __syncthreads();
+    const int p = blockIdx.y;
+    const int iz = a.g.z0 + p % a.g.nzc;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kx = blockIdx.x * kChirpWaves + wave;
+    if (kx > H) return;                      // wave-uniform; no block barriers below
+    const int N = a.N;
+    const double ahm = a.alpha[iz] / (2.0 * M);
+    const float2* hhat = a.hhat + (size_t)iz * LB;
+    float2* scr = sm + wave * SCRP;
+    const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
+    float2 g[F::NV];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int n = lane + 64 * e;
+        g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
+    }
+    F::template nat_to_perm<false>(g, scr, tws_m, lane);
+    const float2* S1 = a.S1t + (size_t)p * M * N;
+    float2* T2 = a.T2 + (size_t)p * M * MF;
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+        const int s = side ? ((M - kx) & (M - 1)) : kx;
+        if (side && s == kx) break;
+        float2 v[B::NV];
+#pragma unroll
+        for (int e = 0; e < EB; ++e) {
+            const int n = lane + 64 * e;
+            v[e] = make_float2(0.f, 0.f);
+            if (n < N) v[e] = cmul(S1[(size_t)s * N + n], chirp(n - N / 2, ahm, -1.f));
+        }
+        bluestein_line<M>(v, scr, tws_lb, hhat, lane);
+        // scaled spectrum column S[s][ky] (natural), staged to LDS in FFT order
+        NURSD_WAVE_SYNC();
+#pragma unroll
+        for (int e = 0; e < M / 64; ++e) {
+            const int k = lane + 64 * e - M / 2;
+            scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+        }
+        NURSD_WAVE_SYNC();
+        const float dxs = a.dec[s];
+        float2 x[F::NV];
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                x[h * 8 + d] = cscale(cmul(scr[k], g[h * 8 + d]), dxs * a.dec[k]);
+            }
+        // zero-padded natural oversampled line
+        NURSD_WAVE_SYNC();
+        for (int i = lane; i < MF; i += 64) scr[i] = make_float2(0.f, 0.f);
+        NURSD_WAVE_SYNC();
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);        // ky mod M
+                scr[k < H ? k : k + (MF - M)] = x[h * 8 + d];  // ky mod MF
+            }
+        NURSD_WAVE_SYNC();
+#pragma unroll
+        for (int e = 0; e < EB; ++e) v[e] = scr[lane + 64 * e];
+        B::template nat_to_perm<true>(v, scr, tws_lb, lane);
+#pragma unroll
+        for (int h = 0; h < B::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int jy = B::perm_k(lane, h, d, q);
+                T2[(size_t)s * MF + jy] = v[h * 8 + d];
+            }
+    }
+}
+
 template <typename Args>
 static hipError_t launch_k(void (*k)(Args), dim3 grid, int threads, size_t sh, hipStream_t s, const Args& a) {
     if (sh > 65536) {
@@ -310,6 +406,25 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
         case 1024: {
             using B = WaveFFT<2048>;
             return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
+                            s, a);
+        }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s) {
+    const int planes = a.g.nb * a.g.nzc;
+    switch (a.M) {
+        case 512: {
+            using B = WaveFFT<1024>;
+            return launch_k(k_chirp_type2_cols<512>, dim3((512 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
+                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
+                            s, a);
+        }
+        case 1024: {
+            using B = WaveFFT<2048>;
+            return launch_k(k_chirp_type2_cols<1024>, dim3((1024 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
                             kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
                             s, a);
         }

@@ -150,8 +150,11 @@ __global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
     const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
     const double z = a.g.z[iz];
     const double hw = 0.5 * a.w;
-    const double tx = (x - a.cx) / a.g.dx * 2.0 + MF / 2;
-    const double ty = (y - a.cy) / a.g.dy * 2.0 + MF / 2;
+    // plane pitch: the frame pitch, or dx / alpha on a scaled plane
+    const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
+    const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
+    const double tx = (x - a.cx) / px * 2.0 + MF / 2;
+    const double ty = (y - a.cy) / py * 2.0 + MF / 2;
     const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
     const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
     float wx[8], wy[8];
@@ -210,24 +213,39 @@ static hipError_t launch_t2(void (*k)(Args), dim3 grid, int threads, size_t sh, 
 }
 
 template <int M>
+static hipError_t type2_fine_impl(const Type2Args& a, hipStream_t s) {
+    using G = WaveFFT<2 * M>;
+    const int planes = a.g.nb * a.g.nzc;
+    constexpr int SCRP = (G::SCR > 2 * M ? G::SCR : 2 * M) + 1;
+    hipError_t e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes),
+                             kT2RowWaves * 64, (size_t)(kT2RowWaves * SCRP + 2 * M) * sizeof(float2), s, a);
+    if (e != hipSuccess) return e;
+    return launch_t2(k_type2_interp, dim3((a.max_vox + kInterpThreads - 1) / kInterpThreads, a.g.nzc),
+                     kInterpThreads, 0, s, a);
+}
+
+template <int M>
 static hipError_t type2_impl(const Type2Args& a, hipStream_t s) {
     using G = WaveFFT<2 * M>;
     const int planes = a.g.nb * a.g.nzc;
     hipError_t e = launch_t2(k_type2_cols<M>, dim3((M / 2 + 1 + kT2Waves - 1) / kT2Waves, planes), kT2Waves * 64,
                              (size_t)(kT2Waves * (G::SCR + 1) + M + 2 * M) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
-    constexpr int SCRP = (G::SCR > 2 * M ? G::SCR : 2 * M) + 1;
-    e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes), kT2RowWaves * 64,
-                  (size_t)(kT2RowWaves * SCRP + 2 * M) * sizeof(float2), s, a);
-    if (e != hipSuccess) return e;
-    return launch_t2(k_type2_interp, dim3((a.max_vox + kInterpThreads - 1) / kInterpThreads, a.g.nzc),
-                     kInterpThreads, 0, s, a);
+    return type2_fine_impl<M>(a, s);
 }
 
 hipError_t launch_type2(const Type2Args& a, hipStream_t s) {
     switch (a.M) {
         case 512: return type2_impl<512>(a, s);
         case 1024: return type2_impl<1024>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_type2_fine(const Type2Args& a, hipStream_t s) {
+    switch (a.M) {
+        case 512: return type2_fine_impl<512>(a, s);
+        case 1024: return type2_fine_impl<1024>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

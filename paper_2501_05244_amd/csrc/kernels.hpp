@@ -136,9 +136,14 @@ struct ChirpArgs {
     const float2* hhat;     // [Z][2M] chirp spectra / (2M * M)
     const float2* tw_m;     // twiddles of size M
     const float2* tw_lb;    // twiddles of size 2M
+    float2* T2;             // [planes][M][2M] (voxel-list output only)
+    const float* dec;       // [M] (-1)^k / phihat(k), FFT order (voxel-list output only)
 };
 hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s);
 hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
+// Scaled spectrum times kernel spectrum, deconvolved and zero-padded to the
+// oversampled line, inverse FFT along y -> T2 (type-2 output of eq. NURSD2_SRSD).
+hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- step 5 (voxel lists)
 struct Type2Args {
@@ -164,6 +169,8 @@ struct Type2Args {
     int first, last, coherent;
 };
 hipError_t launch_type2(const Type2Args& a, hipStream_t s);
+// The fine-grid and interpolation steps alone (T2 already filled).
+hipError_t launch_type2_fine(const Type2Args& a, hipStream_t s);
 
 // ---------------------------------------------------------------- step 8
 struct AdjArgs {

@@ -60,7 +60,7 @@ class Workload:
     hist: np.ndarray | None = None        # float32 [L][T]
     scatterers: np.ndarray | None = None  # float64 [S][3]
     albedo: np.ndarray | None = None      # float64 [S]
-    mode: str = "grid"                    # "grid" | "points" | "srsd"
+    mode: str = "grid"                    # "grid" | "points" | "srsd" | "srsd_points"
     plane_ptr: np.ndarray | None = None   # int32 [Z+1] (points mode)
     voxel_xy: np.ndarray | None = None    # float32 [V][2] (points mode)
     zref: float = 0.0                     # srsd: alpha(z) = zref / z
@@ -247,6 +247,22 @@ def config_srsd(render: bool = True) -> Workload:
     return w
 
 
+def config_srsd_points(render: bool = True, planes: int = 64, per_side: int = 128) -> Workload:
+    """Scaled RSD frustum at voxel lists: the scaled-RSD relay grid (256x256
+    over [-1,1]^2, zref = 1 m) evaluated at the jittered perspective lattices
+    of config_frustum_points (64 planes over [1,4] m, 128x128 points per plane
+    at pitch 15.625 mm * z/1 m): 1,048,576 voxels."""
+    fr = config_frustum_points(render, planes, per_side)
+    w = config_srsd(False)
+    w.hist = fr.hist
+    w.name = "srsd_points"
+    w.mode = "srsd_points"
+    w.plane_ptr = fr.plane_ptr
+    w.voxel_xy = fr.voxel_xy
+    w.grid = Grid(w.grid.x0, w.grid.y0, w.grid.dx, w.grid.dy, w.grid.nx, w.grid.ny, z=fr.grid.z)
+    return w
+
+
 def config_diff(render: bool = True) -> Workload:
     """16,384 random relay samples over 1x1 m, 1,024 bins at 8 ps, 10
     scatterers, 6 cm wavelength (48 frequencies), 128x128x64 voxels; relay
@@ -300,7 +316,7 @@ def config_batch(render: bool = True, n_scenes: int = 64, seed: int = 41) -> lis
 
 def work_units(w: Workload) -> int:
     """Voxel-frequency propagations of one reconstruction."""
-    if w.mode == "points":
+    if w.mode in ("points", "srsd_points"):
         nvox = int(w.plane_ptr[-1])
     else:
         nvox = w.grid.nx * w.grid.ny * len(w.grid.z)
