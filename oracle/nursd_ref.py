@@ -342,6 +342,23 @@ def srsd_points(P, relay_xy, f, frame: Frame, N, z, alphas, plane_ptr, voxel_xy,
     return out
 
 
+def nursd_video(P, relay_xy, f, frame: Frame, grid, xp, times, alphas=None):
+    """4D light transport (eq. Video_Voxel_Freq_Offset): the coherent field of
+    every voxel at each time t, V(x_v, t) = sum_b e^{+j 2 pi f_b t} W_b(x_v),
+    where W_b is the single-frequency field (back-propagation and illumination
+    phase) of NURSD-1, or of the scaled RSD when alphas are given.
+    Returns complex [len(times)][Z][ny][nx]; the video intensity is |V|."""
+    times = np.asarray(times, dtype=np.float64)
+    out = np.zeros((len(times), len(grid.z), grid.ny, grid.nx), dtype=np.complex128)
+    for b, fb in enumerate(f):
+        if alphas is None:
+            Wb = nursd_grid(P[b:b + 1], relay_xy, f[b:b + 1], frame, grid, xp)
+        else:
+            Wb = srsd(P[b:b + 1], relay_xy, f[b:b + 1], frame, grid, xp, alphas)
+        out += np.exp(2j * np.pi * fb * times)[:, None, None, None] * Wb[None]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Step 8: adjoint of the uniform-grid operator and the loss gradients.
 # ---------------------------------------------------------------------------

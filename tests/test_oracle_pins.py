@@ -179,6 +179,29 @@ def test_point_scatterer_focuses_at_its_voxel():
     assert abs(ix - 21) <= 1 and abs(iy - 9) <= 1 and abs(iz - 13) <= 1
 
 
+def test_video_peak_follows_a_measurement_delay():
+    # 4D light transport: at a point scatterer's voxel the video peaks near
+    # t = 0; delaying every histogram by d bins (the returns arrive d dt
+    # later) moves that peak to t = +d dt.  Fixes the sign of the time phase
+    # relative to the temporal transform.
+    w = scenes.config_tiny(render=False)
+    g = w.grid
+    s = np.array([[g.x0 + 21 * g.dx, g.y0 + 9 * g.dy, g.z[13]]])
+    h = scenes.render_transients(w.relay_xy, s, np.ones(1), w.xp, w.wavelet.n_time,
+                                 w.wavelet.dt, w.wavelet.t0)
+    d = 20
+    fr = o.frame_for_workload(w)
+    sub = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[13:14])
+    times = np.arange(-30, 51) * 10e-12
+    peaks = []
+    for hh in (h, np.roll(h, d, axis=1)):
+        P, f = o.phasors_from_workload(w, hh)
+        Vt = o.nursd_video(P, w.relay_xy.astype(np.float64), f, fr, sub, w.xp, times)
+        peaks.append(times[np.argmax(np.abs(Vt[:, 0, 9, 21]))])
+    assert abs(peaks[0]) <= 20e-12
+    assert abs(peaks[1] - peaks[0] - d * w.wavelet.dt) <= 10e-12
+
+
 def test_lateral_psf_width_loose():
     # Lateral resolution 1.22 lambda z / D (eq. Focusing_Res): the lateral
     # half-maximum width of a focused point is within a loose band of it.
