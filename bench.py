@@ -124,8 +124,8 @@ def time_ms(fn, reps: int) -> float:
 
 def secondary(w_spad, dev) -> dict:
     """The other hot-path rows on their own workloads: scaled RSD frustum,
-    NURSD-3 voxel lists, scaled RSD at voxel lists, forward + adjoint, and
-    batched vs plain serving."""
+    NURSD-3 voxel lists, scaled RSD at voxel lists, 4D video, forward +
+    adjoint, and batched vs plain serving."""
     import torch
     from paper_2501_05244_amd.api import Batch, plan_from_workload
     from paper_2501_05244_amd.autograd import nursd
@@ -156,6 +156,16 @@ def secondary(w_spad, dev) -> dict:
     out["srsd_points"] = {"workload": "srsd_points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
                           "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
     del plan
+    # 4D light transport: 32 frames at 50 ps of the SPAD volume
+    w = scenes.config_spad(render=False)
+    plan = plan_from_workload(w, dev)
+    P = plan.phasor(hist)
+    T = 32
+    ms = time_ms(lambda: plan.forward_video(P, T, -0.8e-9, 0.05e-9, vol=False), 3)
+    out["video"] = {"workload": "spad_L65536_F96_256x256x128_32frames", "ms": round(ms, 3),
+                    "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3),
+                    "voxel*frame/s": w.grid.nx * w.grid.ny * len(w.grid.z) * T / (ms * 1e-3)}
+    del plan, P
     # differentiation: forward + adjoint (grad P and grad xy) through autograd
     w = scenes.config_diff()
     plan = plan_from_workload(w, dev)

@@ -188,6 +188,19 @@ int nursd_adjoint(nursd_plan* plan, const void* grad_vol_dev, const void* P_dev,
                   void* grad_P_dev, float* grad_xy_dev, void* ws_dev, size_t ws_bytes,
                   void* stream);
 
+/* 4D light transport (eq. Video_Voxel_Freq_Offset): the coherent field of
+ * every voxel at n_frames times t_j = t_first + j t_step [s],
+ *   V(x_v, t_j) = sum_b e^{+j 2 pi f_b t_j} W_b(x_v),
+ * where W_b is frequency b's field (back-propagation and illumination phase)
+ * of a coherent GRID or SRSD plan; V(x_v, 0) is the forward volume.
+ * Writes video_dev ([n_frames][nz][ny][nx] complex64) and/or video_I_dev
+ * (same shape, |V|, float); either may be NULL but not both.  The plan is
+ * processed in slabs of planes; each slab's per-frequency fields are kept in
+ * the workspace, which must hold nursd_video_workspace_size bytes. */
+int nursd_video_workspace_size(const nursd_plan* plan, size_t* bytes);
+int nursd_forward_video(nursd_plan* plan, const void* P_dev, int32_t n_frames, double t_first, double t_step,
+                        void* video_dev, float* video_I_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
 /* Batched serving of many reconstructions of uneven size (the plans may
  * differ in relay count, grid, frequency count, wavelength and transform
  * size).  All n plans (coherent GRID mode, T a power of two, evenly spaced
@@ -242,6 +255,7 @@ void nursd_batch_destroy(nursd_batch* batch);
 #define NURSD_STAGE_RELAY_GRID 7
 #define NURSD_STAGE_TYPE2 8
 #define NURSD_STAGE_ADJOINT 9
+#define NURSD_STAGE_VIDEO 10
 #define NURSD_NUM_STAGES 16
 int nursd_profile_begin(nursd_plan* plan, uint32_t stage_mask);
 int nursd_profile_end(nursd_plan* plan, double* ms, int32_t* calls);

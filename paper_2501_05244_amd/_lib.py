@@ -23,7 +23,7 @@ ERRORS = {
 }
 MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS = 0, 1, 2, 3
 STAGES = ["phasor", "spread", "fine_y", "kernel_rows", "propagate_cols", "propagate_rows", "chirp_rows",
-          "relay_grid", "type2", "adjoint"]
+          "relay_grid", "type2", "adjoint", "video"]
 NUM_STAGES = 16
 
 
@@ -74,6 +74,9 @@ SIGNATURES = {
     "nursd_forward_phasor": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "nursd_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),
+    "nursd_video_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nursd_forward_video": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]),
     "nursd_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
     "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     "nursd_batch_destroy": (None, [c_void_p]),

@@ -183,6 +183,24 @@ class Plan:
               "nursd_forward_phasor")
         return V, I
 
+    def forward_video(self, P: torch.Tensor, n_frames: int, t_first: float, t_step: float, vol=True,
+                      intensity=True, stream=None):
+        """4D light transport: frames [n_frames][nz][ny][nx] of the coherent
+        field (complex) and/or its magnitude at t_first + j t_step."""
+        _need(P, torch.complex64, (self.F, self.L), "P")
+        shape = (n_frames,) + self.out_shape()
+        V = torch.empty(shape, dtype=torch.complex64, device=self.device) if vol else None
+        I = torch.empty(shape, dtype=torch.float32, device=self.device) if intensity else None
+        n = c_size_t()
+        check(self._lib.nursd_video_workspace_size(self.handle, byref(n)), "nursd_video_workspace_size")
+        if getattr(self, "_vws", None) is None or self._vws.numel() < n.value + 256:
+            self._vws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._vws.data_ptr()
+        ws = c_void_p(base + (-base) % 256)
+        check(self._lib.nursd_forward_video(self.handle, _ptr(P), n_frames, float(t_first), float(t_step), _ptr(V),
+                                            _ptr(I), ws, n, _stream(stream)), "nursd_forward_video")
+        return V, I
+
     def adjoint(self, grad_vol: torch.Tensor, P: torch.Tensor | None = None, stream=None):
         _need(grad_vol, torch.complex64, self.out_shape(), "grad_vol")
         gP = torch.empty((self.F, self.L), dtype=torch.complex64, device=self.device)

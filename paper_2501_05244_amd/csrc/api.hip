@@ -1456,6 +1456,112 @@ int nursd_forward_hist(nursd_plan* p, const float* hist, void* vol, float* I, vo
     return forward_from_P(p, P, vol, I, w, static_cast<hipStream_t>(stream));
 }
 
+namespace {
+
+bool video_ok(const nursd_plan* p) {
+    return p->coherent && (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_SRSD);
+}
+size_t video_field_bytes(const nursd_plan* p) {
+    return align_up((size_t)p->F * p->ZC * p->nx * p->ny * sizeof(float2));
+}
+
+}  // namespace
+
+int nursd_video_workspace_size(const nursd_plan* p, size_t* bytes) {
+    if (!p || !bytes) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!video_ok(p)) return fail(NURSD_ERR_UNSUPPORTED_SIZE, "video needs a coherent GRID or SRSD plan");
+    *bytes = p->ws_bytes + video_field_bytes(p);
+    return NURSD_OK;
+}
+
+int nursd_forward_video(nursd_plan* p, const void* P, int32_t n_frames, double t_first, double t_step,
+                        void* video, float* video_I, void* ws, size_t ws_bytes, void* stream) {
+    if (!p || !P) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!video && !video_I) return fail(NURSD_ERR_ARG, "video and video_I are both NULL");
+    if (n_frames < 1) return fail(NURSD_ERR_ARG, "n_frames must be >= 1");
+    if (!std::isfinite(t_first) || !std::isfinite(t_step)) return fail(NURSD_ERR_ARG, "non-finite time");
+    if (!video_ok(p)) return fail(NURSD_ERR_UNSUPPORTED_SIZE, "video needs a coherent GRID or SRSD plan");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    if (ws_bytes < p->ws_bytes + video_field_bytes(p))
+        return fail(NURSD_ERR_WORKSPACE, "workspace too small for the video: need " +
+                                             std::to_string(p->ws_bytes + video_field_bytes(p)) + " bytes");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    float2* field = reinterpret_cast<float2*>(w + p->ws_bytes);
+    float2* U = reinterpret_cast<float2*>(w + p->off_U);
+    if ((rc = run_spectrum(p, static_cast<const float2*>(P), U, w, s))) return rc;
+    float2* Bt = reinterpret_cast<float2*>(w + p->off_Bt);
+    float2* Yt = reinterpret_cast<float2*>(w + p->off_Yt);
+    float2* u = reinterpret_cast<float2*>(w + p->off_u);
+    const bool scaled = p->mode == NURSD_MODE_SRSD;
+    if (scaled) {
+        RelayGridArgs ra{};
+        ra.U = U;
+        ra.Tg = reinterpret_cast<float2*>(w + p->off_Tg);
+        ra.u = u;
+        ra.M = p->M;
+        ra.N = p->nx;
+        ra.b0 = 0;
+        ra.nb = p->F;
+        ra.tw_m = p->tw(p->M);
+        LAUNCH(p, NURSD_STAGE_RELAY_GRID, RelayGridArgs, launch_relay_grid, ra, s);
+    }
+    // slab by slab: every frequency's field for ZC planes, then the frames
+    for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+        const int nzc = std::min(p->ZC, p->nz - z0);
+        for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+            const int nb = std::min(p->FC, p->F - b0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            if (scaled) {
+                ChirpArgs ca{};
+                ca.g = g;
+                ca.u = u;
+                ca.S1t = reinterpret_cast<float2*>(w + p->off_S1);
+                ca.Bt = Bt;
+                ca.Yt = Yt;
+                ca.M = p->M;
+                ca.N = p->nx;
+                ca.BS = p->BS;
+                ca.ny = p->ny;
+                ca.alpha = p->d_alpha;
+                ca.hhat = p->d_hhat;
+                ca.tw_m = p->tw(p->M);
+                ca.tw_lb = p->tw(2 * p->M);
+                LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
+                LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, ChirpArgs, launch_chirp_cols, ca, s);
+            } else {
+                P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+                LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
+            }
+            P3Args a3 = rows_args(p, g, Yt, nullptr, nullptr, b0, nb);
+            a3.first = 1;
+            a3.field = field;
+            a3.field_z0 = z0;
+            a3.field_nz = p->ZC;
+            LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
+        }
+        VideoArgs va{};
+        va.field = field;
+        va.f = p->d_f;
+        va.V = static_cast<float2*>(video);
+        va.I = video_I;
+        va.F = p->F;
+        va.field_nz = p->ZC;
+        va.nzc = nzc;
+        va.z0 = z0;
+        va.nz = p->nz;
+        va.nvp = p->nx * p->ny;
+        va.T = n_frames;
+        va.t_first = t_first;
+        va.t_step = t_step;
+        LAUNCH(p, NURSD_STAGE_VIDEO, VideoArgs, launch_video, va, s);
+    }
+    return NURSD_OK;
+}
+
 int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad_P, float* grad_xy, void* ws,
                   size_t ws_bytes, void* stream) {
     if (!p || !grad_vol || !grad_P) return fail(NURSD_ERR_ARG, "NULL argument");

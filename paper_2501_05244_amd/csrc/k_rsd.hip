@@ -304,7 +304,10 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
                 const int sl = h * SPG + j;
                 const float2 val = v[h * 8 + d];
                 if (off[sl] < 0) continue;
-                if (a.coherent) {
+                if (a.field) {
+                    a.field[(size_t)(b * a.field_nz + iz - a.field_z0) * ny * nx + off[sl]] = cmul(ph[sl], val);
+                    ph[sl] = cmul(ph[sl], st[sl]);
+                } else if (a.coherent) {
                     acc[sl] = cadd(acc[sl], cmul(ph[sl], val));
                     ph[sl] = cmul(ph[sl], st[sl]);
                 } else {
@@ -312,6 +315,7 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
                 }
             }
     }
+    if (a.field) return;
 #pragma unroll
     for (int sl = 0; sl < NS; ++sl) {
         if (off[sl] < 0) continue;

@@ -111,8 +111,26 @@ struct P3Args {
     double xp0, xp1, xp2;
     int first, last, coherent;
     const float2* tw;
+    // Per-frequency field output (4D video): when set, each frequency's
+    // phased contribution is stored at field[b][iz - field_z0][iy][ix]
+    // (frequency stride field_nz * ny * nx) instead of being summed.
+    float2* field;
+    int field_z0, field_nz;
 };
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s);
+
+// ---------------------------------------------------------------- 4D video
+// V(x, t_j) = sum_b e^{+j 2 pi f_b t_j} W_b(x) for the planes of one slab,
+// t_j = t_first + j t_step (eq. Video_Voxel_Freq_Offset).
+struct VideoArgs {
+    const float2* field;     // [F][field_nz][nvp] per-frequency fields of the slab
+    const double* f;         // [F] frequencies [Hz]
+    float2* V;               // [T][nz][nvp] complex video or NULL
+    float* I;                // [T][nz][nvp] |V| or NULL
+    int F, field_nz, nzc, z0, nz, nvp, T;
+    double t_first, t_step;
+};
+hipError_t launch_video(const VideoArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- step 6
 struct RelayGridArgs {
