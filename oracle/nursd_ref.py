@@ -359,6 +359,38 @@ def nursd_video(P, relay_xy, f, frame: Frame, grid, xp, times, alphas=None):
     return out
 
 
+def nursd_grid_multi(Ps, relay_xy, f, frame: Frame, grid, xps):
+    """Several illumination positions (the integral over x_p in
+    eq. PF_RSD_Defn): V = sum_k NURSD-1(P_k) with the illumination phase of
+    x_p,k; Ps [K][F][L] are the phasors measured under each illumination,
+    xps [K][3].  Returns complex [Z][ny][nx]."""
+    out = None
+    for P, xp in zip(Ps, np.asarray(xps, dtype=np.float64)):
+        V = nursd_grid(P, relay_xy, f, frame, grid, xp)
+        out = V if out is None else out + V
+    return out
+
+
+def subsample_nearest(P, D):
+    """Compression preprocessing of the sampling-criteria section: keep the
+    relay-grid samples on the lattice of stride D per axis (the others are
+    discarded) and fill every grid point from its nearest kept sample
+    (Euclidean distance in grid units; ties go to the first kept sample in
+    row-major order).  P: [..., ny, nx]; returns the same shape."""
+    P = np.asarray(P)
+    ny, nx = P.shape[-2:]
+    ky, kx = np.arange(0, ny, D), np.arange(0, nx, D)
+    KY, KX = np.meshgrid(ky, kx, indexing="ij")
+    kept = np.stack([KY.ravel(), KX.ravel()], 1)                 # row-major order
+    out = np.empty_like(P)
+    for iy in range(ny):
+        for ix in range(nx):
+            d2 = (kept[:, 0] - iy) ** 2 + (kept[:, 1] - ix) ** 2
+            sy, sx = kept[int(np.argmin(d2))]
+            out[..., iy, ix] = P[..., sy, sx]
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Step 8: adjoint of the uniform-grid operator and the loss gradients.
 # ---------------------------------------------------------------------------

@@ -355,6 +355,36 @@ def test_srsd_points_equals_nursd_points_in_stretched_frame():
     assert rel(V, ref) < 1e-11
 
 
+def test_multi_illumination_on_grid_equals_brute_force_rsd():
+    # Several laser positions, each with its own phasors: on-grid relays make
+    # the FFT route exact, so the sum must equal the brute-force RSD sums with
+    # each position's illumination phase.
+    rng = np.random.default_rng(31)
+    grid, xy, frame, f, P = _on_grid_case(rng, F=2)
+    Ps = [P, rng.normal(size=P.shape) + 1j * rng.normal(size=P.shape)]
+    xps = np.array([[0.05, -0.02, 0.0], [-0.07, 0.04, 0.01]])
+    V = o.nursd_grid_multi(Ps, xy, f, frame, grid, xps)
+    vox = o.grid_voxels(grid)
+    ref = sum(o.rsd_direct(Pk, xy, f, vox, xk) for Pk, xk in zip(Ps, xps)).reshape(V.shape)
+    assert rel(V, ref) < 1e-11
+
+
+@pytest.mark.parametrize("D,ny,nx", [(1, 5, 7), (2, 5, 7), (3, 8, 9), (4, 9, 6)])
+def test_subsample_nearest_is_the_separable_lattice_rule(D, ny, nx):
+    # On a product lattice the nearest kept point is found axis by axis: round
+    # i / D to the nearest integer (halves down), clamp to the last kept index.
+    rng = np.random.default_rng(32)
+    P = rng.normal(size=(2, ny, nx)) + 1j * rng.normal(size=(2, ny, nx))
+    out = o.subsample_nearest(P, D)
+
+    def near(i, n):
+        q = np.floor((i + (D - 1) / 2) / D).astype(int) * D   # ties to the lower kept index
+        return np.minimum(q, (n - 1) // D * D)
+    sy, sx = near(np.arange(ny), ny), near(np.arange(nx), nx)
+    assert np.array_equal(out, P[:, sy[:, None], sx[None, :]])
+    assert np.array_equal(out[:, ::D, ::D], P[:, ::D, ::D])     # kept samples unchanged
+
+
 # ------------------------------------------------------------------ step 8
 def _adj_case(rng):
     grid, xy, frame, f, P = _on_grid_case(rng, M=16, n=6, L=12, zs=(0.12, 0.2))
