@@ -124,8 +124,9 @@ def time_ms(fn, reps: int) -> float:
 
 def secondary(w_spad, dev) -> dict:
     """The other hot-path rows on their own workloads: scaled RSD frustum,
-    NURSD-3 voxel lists, scaled RSD at voxel lists, 4D video, forward +
-    adjoint, and batched vs plain serving."""
+    NURSD-3 voxel lists, scaled RSD at voxel lists, 4D video, several
+    illumination positions, the compression gather, forward + adjoint, and
+    batched vs plain serving."""
     import torch
     from paper_2501_05244_amd.api import Batch, plan_from_workload
     from paper_2501_05244_amd.autograd import nursd
@@ -165,7 +166,20 @@ def secondary(w_spad, dev) -> dict:
     out["video"] = {"workload": "spad_L65536_F96_256x256x128_32frames", "ms": round(ms, 3),
                     "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3),
                     "voxel*frame/s": w.grid.nx * w.grid.ny * len(w.grid.z) * T / (ms * 1e-3)}
-    del plan, P
+    # four illumination positions sharing every kernel spectrum
+    K = 4
+    Pk = P.unsqueeze(0).expand(K, -1, -1).contiguous()
+    xps = [[0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [0.0, 0.5, 0.0], [-0.5, -0.5, 0.0]]
+    ms = time_ms(lambda: plan.forward_multi(Pk, xps, vol=False), 3)
+    out["multi_illumination"] = {"workload": "spad_L65536_F96_256x256x128_4positions", "ms": round(ms, 3),
+                                 "voxel*freq*position/s": K * scenes.work_units(w) / (ms * 1e-3)}
+    # compression preprocessing: stride-2 lattice fill of 96 x 256 x 256 grid phasors
+    from paper_2501_05244_amd.api import subsample_nearest
+    Pg = P[:, :65536].reshape(96, 256, 256).contiguous()
+    ms = time_ms(lambda: subsample_nearest(Pg, 2), 10)
+    out["subsample_nearest"] = {"workload": "F96_256x256_stride2", "ms": round(ms, 4),
+                                "GB/s": 2 * Pg.numel() * 8 / (ms * 1e-3) / 1e9}
+    del plan, P, Pk, Pg
     # differentiation: forward + adjoint (grad P and grad xy) through autograd
     w = scenes.config_diff()
     plan = plan_from_workload(w, dev)

@@ -201,6 +201,27 @@ int nursd_video_workspace_size(const nursd_plan* plan, size_t* bytes);
 int nursd_forward_video(nursd_plan* plan, const void* P_dev, int32_t n_frames, double t_first, double t_step,
                         void* video_dev, float* video_I_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Several illumination positions (the integral over x_p of eq. PF_RSD_Defn):
+ * V = sum_k sum_b e^{+j k_b |x_v - x_p,k|} F_{k,b}(x_v), where F_{k,b} is the
+ * back-propagation of the phasors measured under illumination k.  P_dev:
+ * [K][F][L] complex64 (the plan's relay samples, one block per position);
+ * xp_host: [K][3] positions, read before the call returns.  Each kernel
+ * spectrum is generated once per (frequency, plane) and used for every
+ * position.  Coherent GRID plans only; outputs as nursd_forward_phasor.
+ * The workspace must hold nursd_multi_workspace_size bytes (the per-position
+ * spectra are kept). */
+int nursd_multi_workspace_size(const nursd_plan* plan, int32_t K, size_t* bytes);
+int nursd_forward_multi(nursd_plan* plan, const void* P_dev, int32_t K, const double* xp_host, void* vol_dev,
+                        float* I_dev, void* ws_dev, size_t ws_bytes, void* stream);
+
+/* Compression preprocessing (sampling-criteria section): phasors on a
+ * uniform relay grid, in_dev [F][ny][nx] complex64, are kept on the lattice
+ * of stride D along each axis and every grid point is filled from its nearest
+ * kept sample (Euclidean distance; ties go to the lower index) -> out_dev,
+ * same shape, a different buffer.  D = 1 copies.  Needs no plan. */
+int nursd_subsample_nearest(const void* in_dev, void* out_dev, int32_t F, int32_t ny, int32_t nx, int32_t D,
+                            void* stream);
+
 /* Batched serving of many reconstructions of uneven size (the plans may
  * differ in relay count, grid, frequency count, wavelength and transform
  * size).  All n plans (coherent GRID mode, T a power of two, evenly spaced

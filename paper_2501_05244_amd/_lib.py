@@ -77,6 +77,10 @@ SIGNATURES = {
     "nursd_video_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
     "nursd_forward_video": (c_int32, [c_void_p, c_void_p, c_int32, c_double, c_double, c_void_p, c_void_p, c_void_p,
                                       c_size_t, c_void_p]),
+    "nursd_multi_workspace_size": (c_int32, [c_void_p, c_int32, POINTER(c_size_t)]),
+    "nursd_forward_multi": (c_int32, [c_void_p, c_void_p, c_int32, POINTER(c_double), c_void_p, c_void_p, c_void_p,
+                                      c_size_t, c_void_p]),
+    "nursd_subsample_nearest": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p]),
     "nursd_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
     "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
     "nursd_batch_destroy": (None, [c_void_p]),

@@ -201,6 +201,23 @@ class Plan:
                                             _ptr(I), ws, n, _stream(stream)), "nursd_forward_video")
         return V, I
 
+    def forward_multi(self, P: torch.Tensor, xps, vol=True, intensity=True, stream=None):
+        """Several illumination positions: P [K][F][L] phasors measured under
+        each position, xps [K][3]; returns the summed volume and/or |V|."""
+        K = P.shape[0]
+        _need(P, torch.complex64, (K, self.F, self.L), "P")
+        xp = np.ascontiguousarray(np.asarray(xps, dtype=np.float64).reshape(K, 3))
+        V, I = self._outs(vol, intensity)
+        n = c_size_t()
+        check(self._lib.nursd_multi_workspace_size(self.handle, K, byref(n)), "nursd_multi_workspace_size")
+        if getattr(self, "_mws", None) is None or self._mws.numel() < n.value + 256:
+            self._mws = torch.empty(n.value + 256, dtype=torch.uint8, device=self.device)
+        base = self._mws.data_ptr()
+        ws = c_void_p(base + (-base) % 256)
+        check(self._lib.nursd_forward_multi(self.handle, _ptr(P), K, xp.ctypes.data_as(POINTER(c_double)), _ptr(V),
+                                            _ptr(I), ws, n, _stream(stream)), "nursd_forward_multi")
+        return V, I
+
     def adjoint(self, grad_vol: torch.Tensor, P: torch.Tensor | None = None, stream=None):
         _need(grad_vol, torch.complex64, self.out_shape(), "grad_vol")
         gP = torch.empty((self.F, self.L), dtype=torch.complex64, device=self.device)
@@ -212,6 +229,19 @@ class Plan:
         check(self._lib.nursd_adjoint(self.handle, _ptr(grad_vol), _ptr(P), _ptr(gP), _ptr(gxy), ws, n,
                                       _stream(stream)), "nursd_adjoint")
         return gP, gxy
+
+
+def subsample_nearest(P: torch.Tensor, D: int, stream=None) -> torch.Tensor:
+    """Compression preprocessing: keep the relay-grid phasors P [F][ny][nx] on
+    the stride-D lattice and fill every point from its nearest kept sample."""
+    lib = _lib.load()
+    if P.dim() != 3:
+        raise ValueError("P must be [F][ny][nx]")
+    _need(P, torch.complex64, tuple(P.shape), "P")
+    out = torch.empty_like(P)
+    check(lib.nursd_subsample_nearest(_ptr(P), _ptr(out), P.shape[0], P.shape[1], P.shape[2], int(D),
+                                      _stream(stream)), "nursd_subsample_nearest")
+    return out
 
 
 class Batch:

@@ -1562,6 +1562,79 @@ int nursd_forward_video(nursd_plan* p, const void* P, int32_t n_frames, double t
     return NURSD_OK;
 }
 
+namespace {
+
+size_t multi_spectra_bytes(const nursd_plan* p, int K) {
+    return align_up((size_t)K * p->F * p->M * p->M * sizeof(float2));
+}
+
+}  // namespace
+
+int nursd_multi_workspace_size(const nursd_plan* p, int32_t K, size_t* bytes) {
+    if (!p || !bytes) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (K < 1) return fail(NURSD_ERR_ARG, "K must be >= 1");
+    if (p->mode != NURSD_MODE_GRID || !p->coherent)
+        return fail(NURSD_ERR_UNSUPPORTED_SIZE, "several illumination positions need a coherent GRID plan");
+    *bytes = p->ws_bytes + multi_spectra_bytes(p, K);
+    return NURSD_OK;
+}
+
+int nursd_forward_multi(nursd_plan* p, const void* P, int32_t K, const double* xp, void* vol, float* I, void* ws,
+                        size_t ws_bytes, void* stream) {
+    if (!p || !P || !xp) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!vol && !I) return fail(NURSD_ERR_ARG, "vol and I are both NULL");
+    if (K < 1) return fail(NURSD_ERR_ARG, "K must be >= 1");
+    if (p->mode != NURSD_MODE_GRID || !p->coherent)
+        return fail(NURSD_ERR_UNSUPPORTED_SIZE, "several illumination positions need a coherent GRID plan");
+    for (int i = 0; i < 3 * K; ++i)
+        if (!std::isfinite(xp[i])) return fail(NURSD_ERR_GEOMETRY, "non-finite illumination position");
+    int rc = check_ws(p, ws, ws_bytes);
+    if (rc) return rc;
+    if (ws_bytes < p->ws_bytes + multi_spectra_bytes(p, K))
+        return fail(NURSD_ERR_WORKSPACE, "workspace too small for K positions: need " +
+                                             std::to_string(p->ws_bytes + multi_spectra_bytes(p, K)) + " bytes");
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    char* w = static_cast<char*>(ws);
+    const size_t uk = (size_t)p->F * p->M * p->M;
+    float2* Us = reinterpret_cast<float2*>(w + p->ws_bytes);
+    for (int k = 0; k < K; ++k)
+        if ((rc = run_spectrum(p, static_cast<const float2*>(P) + (size_t)k * p->F * p->L, Us + k * uk, w, s)))
+            return rc;
+    float2* V = vol ? static_cast<float2*>(vol) : reinterpret_cast<float2*>(w + p->off_V);
+    float2* Bt = reinterpret_cast<float2*>(w + p->off_Bt);
+    float2* Yt = reinterpret_cast<float2*>(w + p->off_Yt);
+    for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+        const int nb = std::min(p->FC, p->F - b0);
+        for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
+            const int nzc = std::min(p->ZC, p->nz - z0);
+            const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
+            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+            for (int k = 0; k < K; ++k) {       // the kernel spectrum serves every position
+                P2Args a2{g, Bt, Us + k * uk, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+                LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
+                P3Args a3 = rows_args(p, g, Yt, V, I, b0, nb);
+                a3.xp0 = xp[3 * k];
+                a3.xp1 = xp[3 * k + 1];
+                a3.xp2 = xp[3 * k + 2];
+                a3.first = b0 == 0 && k == 0;
+                a3.last = b0 + nb >= p->F && k == K - 1;
+                LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
+            }
+        }
+    }
+    return NURSD_OK;
+}
+
+int nursd_subsample_nearest(const void* in, void* out, int32_t F, int32_t ny, int32_t nx, int32_t D, void* stream) {
+    if (!in || !out) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (in == out) return fail(NURSD_ERR_ARG, "in and out must be different buffers");
+    if (F < 1 || ny < 1 || nx < 1 || D < 1) return fail(NURSD_ERR_ARG, "F, ny, nx and D must be >= 1");
+    HIP_TRY(launch_subsample_nearest(static_cast<const float2*>(in), static_cast<float2*>(out), F, ny, nx, D,
+                                     static_cast<hipStream_t>(stream)));
+    return NURSD_OK;
+}
+
 int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad_P, float* grad_xy, void* ws,
                   size_t ws_bytes, void* stream) {
     if (!p || !grad_vol || !grad_P) return fail(NURSD_ERR_ARG, "NULL argument");

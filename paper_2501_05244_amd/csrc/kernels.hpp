@@ -132,6 +132,9 @@ struct VideoArgs {
 };
 hipError_t launch_video(const VideoArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- compression
+hipError_t launch_subsample_nearest(const float2* in, float2* out, int F, int ny, int nx, int D, hipStream_t s);
+
 // ---------------------------------------------------------------- step 6
 struct RelayGridArgs {
     const float2* U;        // [F][M][M] spectra (scaled by M^-2)

@@ -1,0 +1,129 @@
+"""GPU parity of several illumination positions (sum over x_p of
+eq. PF_RSD_Defn) and of the compression preprocessing (lattice subsampling
+with nearest-sample fill) against the FP64 oracle.  Tolerances: relative L2
+<= 1e-4 for the volumes; the subsampling is index work and must be exact."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nursd_ref as o
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def grid_case(seed, K, n=32, zs=(0.5, 0.7, 0.95, 1.3), L=800, F=4):
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / 32
+    half = n * dx / 2
+    g = scenes.Grid(x0=-half + dx / 2, y0=-half + dx / 2, dx=dx, dy=dx, nx=n, ny=n, z=np.array(zs))
+    xy = rng.uniform(-0.9 * half, 0.9 * half, size=(L, 2)).astype(np.float32)
+    wl = scenes.Wavelet(lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=F)
+    w = scenes.Workload("multi_small", xy, np.zeros(3), wl, g)
+    P = (rng.normal(size=(K, F, L)) + 1j * rng.normal(size=(K, F, L))).astype(np.complex64)
+    xps = np.concatenate([rng.uniform(-0.4, 0.4, size=(K, 2)), rng.uniform(0.0, 0.05, size=(K, 1))], 1)
+    return w, np.ascontiguousarray(P), xps
+
+
+@pytest.mark.parametrize("K,chunks", [(3, (0, 0)), (2, (3, 3))])
+def test_multi_illumination_small(device, K, chunks):
+    print("case: multi illumination small", K, chunks, flush=True)
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P, xps = grid_case(11 + K, K)
+    plan = plan_from_workload(w, device, freq_chunk=chunks[0], plane_chunk=chunks[1])
+    V, I = plan.forward_multi(torch.from_numpy(P).to(device), xps)
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, w.wavelet.n_freq)
+    ref = o.nursd_grid_multi(P.astype(np.complex128), w.relay_xy.astype(np.float64), f, o.frame_for_workload(w),
+                             w.grid, xps)
+    assert rel(V.cpu().numpy(), ref) < TOL
+    assert rel(I.cpu().numpy(), np.abs(ref)) < TOL
+
+
+def test_single_illumination_is_the_forward(device):
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P, xps = grid_case(5, 1)
+    w.xp = xps[0]
+    plan = plan_from_workload(w, device)
+    Pt = torch.from_numpy(P).to(device)
+    V1, _ = plan.forward_multi(Pt, xps, intensity=False)
+    V, _ = plan.forward_phasor(Pt[0].contiguous(), intensity=False)
+    assert torch.equal(V1, V)
+
+
+@pytest.mark.slow
+def test_multi_illumination_spad_full_launch_sampled(device):
+    """The SPAD workload at full size with two laser positions (the second
+    0.5 m off centre), phasors nonzero in two bins per position; the oracle
+    evaluates two whole planes."""
+    print("case: multi illumination spad full", flush=True)
+    from paper_2501_05244_amd.api import plan_from_workload
+    w = scenes.config_spad()
+    xps = np.array([[0.0, 0.0, 0.0], [0.5, -0.25, 0.0]])
+    h2 = scenes.render_transients(w.relay_xy, w.scatterers, w.albedo, xps[1], w.wavelet.n_time, w.wavelet.dt,
+                                  w.wavelet.t0)
+    plan = plan_from_workload(w, device)
+    wl = w.wavelet
+    bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
+    wts = o.phasor_weights(f, wl.lambda_c, wl.sigma_rel, wl.t0)
+    sel = [33, 60]
+    Pin = np.zeros((2, wl.n_freq, w.relay_xy.shape[0]), np.complex64)
+    for k, h in enumerate((w.hist, h2)):
+        Pin[k, sel] = o.temporal_phasor(h, bins[sel], wts[sel])
+    V, _ = plan.forward_multi(torch.from_numpy(Pin).to(device), xps, intensity=False)
+    V = V.cpu().numpy()
+    g = w.grid
+    zi = [10, 100]
+    sub = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[zi])
+    ref = o.nursd_grid_multi(Pin[:, sel].astype(np.complex128), w.relay_xy.astype(np.float64), f[sel],
+                             o.frame_for_workload(w), sub, xps)
+    assert rel(V[zi], ref) < TOL
+
+
+@pytest.mark.parametrize("D,ny,nx", [(1, 7, 5), (2, 9, 8), (3, 10, 13), (4, 33, 31), (5, 64, 64)])
+def test_subsample_nearest_exact(device, D, ny, nx):
+    from paper_2501_05244_amd.api import subsample_nearest
+    rng = np.random.default_rng(D * 100 + ny)
+    P = (rng.normal(size=(3, ny, nx)) + 1j * rng.normal(size=(3, ny, nx))).astype(np.complex64)
+    out = subsample_nearest(torch.from_numpy(P).to(device), D).cpu().numpy()
+    assert np.array_equal(out, o.subsample_nearest(P, D))
+
+
+def test_subsample_nearest_full_grid(device):
+    """96 frequencies of a 256 x 256 relay grid, stride 2 and 4."""
+    from paper_2501_05244_amd.api import subsample_nearest
+    rng = np.random.default_rng(7)
+    P = (rng.normal(size=(96, 256, 256)) + 1j * rng.normal(size=(96, 256, 256))).astype(np.complex64)
+    Pt = torch.from_numpy(P).to(device)
+    for D in (2, 4):
+        out = subsample_nearest(Pt, D).cpu().numpy()
+        assert np.array_equal(out, o.subsample_nearest(P, D))
+
+
+def test_compressed_reconstruction(device):
+    """Relays on a uniform grid, phasors subsampled with stride 2 and filled
+    back, then reconstructed: equals the oracle's NURSD-1 of the oracle's
+    subsampled phasors."""
+    print("case: compressed reconstruction", flush=True)
+    from paper_2501_05244_amd.api import Plan, subsample_nearest
+    rng = np.random.default_rng(3)
+    n, dx, F = 24, 1.0 / 32, 3
+    c = (np.arange(n) - n // 2) * dx
+    X, Y = np.meshgrid(c, c, indexing="xy")                # row-major [iy][ix]
+    xy = np.ascontiguousarray(np.stack([X.ravel(), Y.ravel()], 1).astype(np.float32))
+    P = (rng.normal(size=(F, n, n)) + 1j * rng.normal(size=(F, n, n))).astype(np.complex64)
+    Pc = subsample_nearest(torch.from_numpy(P).to(device), 2).reshape(F, n * n).contiguous()
+    zs = np.array([0.4, 0.7])
+    plan = Plan(torch.from_numpy(xy).to(device), lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=F, z=zs,
+                x0=c[0], y0=c[0], dx=dx, dy=dx, nx=n, ny=n)
+    V, _ = plan.forward_phasor(Pc, intensity=False)
+    g = scenes.Grid(x0=c[0], y0=c[0], dx=dx, dy=dx, nx=n, ny=n, z=zs)
+    fr = o.choose_frame("grid", xy, x0=c[0], y0=c[0], dx=dx, dy=dx, nx=n, ny=n)
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, F)
+    Pref = o.subsample_nearest(P.astype(np.complex128), 2).reshape(F, n * n)
+    ref = o.nursd_grid(Pref, xy.astype(np.float64), f, fr, g, np.zeros(3))
+    assert rel(V.cpu().numpy(), ref) < TOL
