@@ -392,6 +392,59 @@ def subsample_nearest(P, D):
 
 
 # ---------------------------------------------------------------------------
+# 3D NURSD (eq. 3D_NURSD): non-planar relay surfaces.
+# ---------------------------------------------------------------------------
+def kernel3d_samples(f: float, M: int, dx: float, dy: float, Mz: int, dz: float) -> np.ndarray:
+    """3D RSD kernel e^{+j 2 pi f r / c} (eq. 3d_rsd: no 1/r) at
+    (m dx, n dy, p dz), (m, n, p) in I_M^2 x I_Mz; [p][m][n]."""
+    m = centered(M).astype(np.float64)
+    p = centered(Mz).astype(np.float64)
+    r = np.sqrt((p * dz)[:, None, None] ** 2 + (m * dx)[None, :, None] ** 2 + (m * dy)[None, None, :] ** 2)
+    return np.exp(2j * np.pi * f * r / C_LIGHT)
+
+
+def nursd3d_stage1(Pb, relay_xyz, fb, frame: Frame, z0: float, dz: float, Mz: int) -> np.ndarray:
+    """Stage 1 of the 3D NURSD for one frequency: the 3D type-1 NUDFT of the
+    relay samples onto I_M^2 x I_Mz (z frame centred on the plane z0, pitch
+    dz), times the 3D DFT of the sampled 3D kernel, inverse 3D DFT read at the
+    slice z0; returned as that slice's 2D spectrum U0[kx][ky] (so the field
+    at z0 is M^-2 sum_k U0[k] e^{+j k.x~})."""
+    r = np.asarray(relay_xyz, dtype=np.float64)
+    xt = rescale(r[:, 0], frame.cx, frame.Lx)
+    yt = rescale(r[:, 1], frame.cy, frame.Ly)
+    zt = 2.0 * np.pi * (r[:, 2] - z0) / (Mz * dz)
+    kz = centered(Mz).astype(np.float64)
+    M = frame.M
+    U3 = np.stack([nudft1(np.asarray(Pb) * np.exp(-1j * k * zt), xt, yt, M) for k in kz])    # [kz][kx][ky]
+    G3 = kernel3d_samples(fb, M, frame.dx, frame.dy, Mz, dz)
+    Gh2 = np.stack([dft2(g) for g in G3])                                                  # [p][kx][ky]
+    Dz = dft_matrix(Mz, -1.0)                                                              # [kz][p]
+    Gh3 = np.tensordot(Dz, Gh2, axes=(1, 0))                                               # [kz][kx][ky]
+    # inverse DFT along z read at p = 0 (the plane z0): the average over kz
+    return (U3 * Gh3).sum(axis=0) / Mz
+
+
+def nursd3d_grid(P, relay_xyz, f, frame: Frame, grid, xp, z0: float, dz: float, Mz: int):
+    """3D NURSD onto a uniform voxel grid: stage 1 (nursd3d_stage1) to the
+    plane z0, then NURSD-1's plane-to-plane propagation with G = e^{+jkr}/r
+    at distance z_v - z0 and the volume formation of eq. PF_RSD_Defn.
+    grid.z are the voxel depths, all > z0.  Returns V complex [Z][ny][nx]."""
+    mx = np.arange(grid.nx) - grid.nx // 2
+    my = np.arange(grid.ny) - grid.ny // 2
+    xs = frame.cx + mx * frame.dx
+    ys = frame.cy + my * frame.dy
+    z = np.asarray(grid.z, dtype=np.float64)
+    out = np.zeros((len(z), grid.ny, grid.nx), dtype=np.complex128)
+    for b, fb in enumerate(f):
+        U0 = nursd3d_stage1(P[b], relay_xyz, fb, frame, z0, dz, Mz)
+        for iz, zz in enumerate(z):
+            Gh = dft2(kernel_samples(fb, zz - z0, frame.M, frame.dx, frame.dy))
+            Fz = idft2_at(U0 * Gh, mx, my).T
+            out[iz] += illumination_phase(fb, xs[None, :], ys[:, None], zz, xp) * Fz
+    return out
+
+
+# ---------------------------------------------------------------------------
 # Step 8: adjoint of the uniform-grid operator and the loss gradients.
 # ---------------------------------------------------------------------------
 def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None):

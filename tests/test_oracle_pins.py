@@ -385,6 +385,58 @@ def test_subsample_nearest_is_the_separable_lattice_rule(D, ny, nx):
     assert np.array_equal(out[:, ::D, ::D], P[:, ::D, ::D])     # kept samples unchanged
 
 
+def test_3d_stage1_on_lattice_equals_brute_force():
+    # Relays on the 3D lattice (grid points in x, y; z0 + q dz in depth) and
+    # field points in the central window: the 3D FFT route of stage 1 is the
+    # discrete 3D convolution, so it must equal the direct sum of the 3D RSD
+    # kernel over the samples (eq. 3d_rsd) to round-off.
+    rng = np.random.default_rng(41)
+    M, n, dx, Mz, dz, L = 32, 16, 0.02, 8, 0.015, 30
+    z0 = 0.1
+    frame = o.Frame(M, dx, dx, 0.0, 0.0)
+    c = np.arange(n) - n // 2
+    ix, iy = rng.integers(0, n, L), rng.integers(0, n, L)
+    q = rng.integers(-Mz // 4, Mz // 4 + 1, L)
+    xyz = np.stack([c[ix] * dx, c[iy] * dx, z0 + q * dz], 1)
+    P = rng.normal(size=L) + 1j * rng.normal(size=L)
+    fb = 3.1e9
+    U0 = o.nursd3d_stage1(P, xyz, fb, frame, z0, dz, Mz)
+    F0 = o.idft2_at(U0, c, c)                                    # [x][y] on the window
+    X, Y = np.meshgrid(c * dx, c * dx, indexing="ij")
+    r = np.sqrt((X[..., None] - xyz[:, 0]) ** 2 + (Y[..., None] - xyz[:, 1]) ** 2 + (z0 - xyz[:, 2]) ** 2)
+    ref = (np.exp(2j * np.pi * fb * r / o.C_LIGHT) * P).sum(-1)
+    assert rel(F0, ref) < 1e-11
+
+
+def test_3d_nursd_of_a_flat_wall_on_the_lattice_matches_two_stage_brute_force():
+    # A flat wall on the lattice (all z_l = z0 - 2 dz): stage 1 (brute force, as
+    # pinned above) gives the field on the plane z0 on the window; stage 2 is
+    # NURSD-1 of that field from grid positions at z0.  The full 3D NURSD must
+    # equal that composition when the field is confined to the window.
+    rng = np.random.default_rng(42)
+    M, n, dx, Mz, dz, L = 32, 16, 0.02, 8, 0.015, 25
+    z0 = 0.1
+    frame = o.Frame(M, dx, dx, 0.0, 0.0)
+    c = np.arange(n) - n // 2
+    g = scenes.Grid(x0=c[0] * dx, y0=c[0] * dx, dx=dx, dy=dx, nx=n, ny=n, z=np.array([0.25, 0.4]))
+    idx = rng.choice(n * n, L, replace=False)
+    xyz = np.stack([c[idx % n] * dx, c[idx // n] * dx, np.full(L, z0 - 2 * dz)], 1)
+    f = np.array([2.2e9, 3.0e9])
+    P = rng.normal(size=(2, L)) + 1j * rng.normal(size=(2, L))
+    xp = np.array([0.01, 0.0, 0.0])
+    V = o.nursd3d_grid(P, xyz, f, frame, g, xp, z0, dz, Mz)
+    # composition: the stage-1 spectrum, evaluated as a field on the whole
+    # period grid, fed as phasors at those grid points into NURSD-1 (z - z0)
+    m = o.centered(M)
+    X, Y = np.meshgrid(m * dx, m * dx, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], 1)
+    F0 = np.stack([o.idft2_at(o.nursd3d_stage1(P[b], xyz, f[b], frame, z0, dz, Mz), m, m).ravel()
+                   for b in range(2)])
+    gs = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z - z0)
+    ref = o.nursd_grid(F0, pts, f, frame, gs, xp - np.array([0, 0, z0]))
+    assert rel(V, ref) < 1e-10
+
+
 # ------------------------------------------------------------------ step 8
 def _adj_case(rng):
     grid, xy, frame, f, P = _on_grid_case(rng, M=16, n=6, L=12, zs=(0.12, 0.2))
