@@ -124,7 +124,7 @@ def time_ms(fn, reps: int) -> float:
 
 def secondary(w_spad, dev) -> dict:
     """The other hot-path rows on their own workloads: scaled RSD frustum,
-    NURSD-3 voxel lists, scaled RSD at voxel lists, 4D video, several
+    NURSD-3 voxel lists, scaled RSD at voxel lists, 3D NURSD, 4D video, several
     illumination positions, the compression gather, forward + adjoint, and
     batched vs plain serving."""
     import torch
@@ -157,6 +157,15 @@ def secondary(w_spad, dev) -> dict:
     out["srsd_points"] = {"workload": "srsd_points_L65536_F96_1048576vox_64planes", "ms": round(ms, 3),
                           "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
     del plan
+    # 3D NURSD: the SPAD samples on a curved wall (depth within +-5 cm)
+    w = scenes.config_nonplanar()
+    plan = plan_from_workload(w, dev)
+    P3 = plan.phasor(hist)
+    I = torch.empty(plan.out_shape(), dtype=torch.float32, device=dev)
+    ms = time_ms(lambda: plan.forward_phasor(P3, vol=False, out_I=I), 3)
+    out["nursd3d"] = {"workload": "nonplanar_L65536_F96_256x256x128_depthgrid%d" % plan.info["depth3d"], "ms": round(ms, 3),
+                      "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
+    del plan, P3
     # 4D light transport: 32 frames at 50 ps of the SPAD volume
     w = scenes.config_spad(render=False)
     plan = plan_from_workload(w, dev)

@@ -54,6 +54,7 @@ extern "C" {
 #define NURSD_MODE_SRSD 2   /* scaled RSD frustum                           */
 #define NURSD_MODE_SRSD_POINTS 3 /* scaled RSD at per-plane voxel lists
                                     (eq. NURSD2_SRSD)                       */
+#define NURSD_MODE_GRID3D 4 /* non-planar relays, 3D NURSD (eq. 3D_NURSD)  */
 
 /* Phasor-field wavelet and temporal sampling (eq. PF_Response,
  * eq. PFPacket_Omega_Supp).  The F frequencies are DFT bins b of the T-bin
@@ -87,7 +88,15 @@ typedef struct {
  *         lists (plane_ptr, voxel_xy_dev as in POINTS) by a type-2 NUFFT in
  *         each plane's scaled frame (period M dx / alpha_iz around c), the
  *         fusion of the scaled RSD with NURSD-2 (eq. NURSD2_SRSD); outputs
- *         are [V].  Requires nx == ny and a transform size M >= 512. */
+ *         are [V].  Requires nx == ny and a transform size M >= 512.
+ * GRID3D: the GRID voxel grid reconstructed from relay samples at depths
+ *         z_l (relay_z_dev) on a non-planar surface (eq. 3D_NURSD): stage 1
+ *         takes them to the plane z_mid by a 3D type-1 NUFFT onto
+ *         M x M x mz3 modes (depth frame centred on z_mid, pitch dz3), times
+ *         the 3D DFT of the 3D-RSD kernel e^{+jkr} (eq. 3d_rsd), read at
+ *         z_mid; stage 2 propagates from z_mid to each voxel plane (depths
+ *         z[iz] > z_mid) as GRID does.  mz3 = 0 picks the smallest power of
+ *         two >= 8 with every |z_l - z_mid| <= mz3 dz3 / 4 (at most 64). */
 typedef struct {
     int32_t mode;
     double x0, y0;
@@ -100,6 +109,11 @@ typedef struct {
     double zref;                /* SRSD, SRSD_POINTS                            */
     const double* alpha;        /* host [nz] (SRSD, SRSD_POINTS) or NULL        */
     double xp[3];               /* illumination point x_p                       */
+    /* GRID3D: relay depths, the intermediate plane and the depth sampling */
+    const float* relay_z_dev;   /* device [L] relay depths z_l                  */
+    double z_mid;               /* intermediate plane z0 (< every voxel depth)  */
+    double dz3;                 /* depth pitch of the 3D grid, 0 = dx           */
+    int32_t mz3;                /* depth size of the 3D grid, 0 = auto          */
 } nursd_geometry;
 
 /* Numerical options. */
@@ -131,6 +145,7 @@ typedef struct {
     size_t workspace_bytes;
     int32_t freq_chunk;   /* frequencies per propagation launch               */
     int32_t plane_chunk;  /* depth planes per propagation launch              */
+    int32_t depth3d;      /* depth size of the GRID3D stage-1 grid (else 0)   */
 } nursd_plan_info_t;
 
 /* Fill the structs with defaults (pad 2, sigma_os 2, tol 1e-6, coherent,
@@ -277,6 +292,7 @@ void nursd_batch_destroy(nursd_batch* batch);
 #define NURSD_STAGE_TYPE2 8
 #define NURSD_STAGE_ADJOINT 9
 #define NURSD_STAGE_VIDEO 10
+#define NURSD_STAGE_NURSD3D 11
 #define NURSD_NUM_STAGES 16
 int nursd_profile_begin(nursd_plan* plan, uint32_t stage_mask);
 int nursd_profile_end(nursd_plan* plan, double* ms, int32_t* calls);

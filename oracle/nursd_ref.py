@@ -553,7 +553,8 @@ def frame_for_workload(w) -> Frame:
     g = w.grid
     if w.mode == "points":
         return choose_frame("points", w.relay_xy, dx=g.dx, dy=g.dy, voxel_xy=w.voxel_xy, pad=w.pad)
-    # the scaled RSD at voxel lists keeps the scaled RSD's frame (relay grid)
-    mode = "srsd" if w.mode == "srsd_points" else w.mode
+    # the scaled RSD at voxel lists keeps the scaled RSD's frame (relay grid);
+    # the 3D NURSD keeps the uniform grid's lateral frame
+    mode = {"srsd_points": "srsd", "grid3d": "grid"}.get(w.mode, w.mode)
     return choose_frame(mode, w.relay_xy, x0=g.x0, y0=g.y0, dx=g.dx, dy=g.dy, nx=g.nx,
                         ny=g.ny, pad=w.pad)

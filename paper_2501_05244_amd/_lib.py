@@ -21,9 +21,9 @@ ERRORS = {
     -5: "NURSD_ERR_HIP",
     -6: "NURSD_ERR_UNIMPLEMENTED",
 }
-MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS = 0, 1, 2, 3
+MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS, MODE_GRID3D = 0, 1, 2, 3, 4
 STAGES = ["phasor", "spread", "fine_y", "kernel_rows", "propagate_cols", "propagate_rows", "chirp_rows",
-          "relay_grid", "type2", "adjoint", "video"]
+          "relay_grid", "type2", "adjoint", "video", "nursd3d"]
 NUM_STAGES = 16
 
 
@@ -40,6 +40,7 @@ class Geometry(ctypes.Structure):
         ("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("z", POINTER(c_double)),
         ("plane_ptr", POINTER(c_int32)), ("voxel_xy_dev", c_void_p), ("zref", c_double),
         ("alpha", POINTER(c_double)), ("xp", c_double * 3),
+        ("relay_z_dev", c_void_p), ("z_mid", c_double), ("dz3", c_double), ("mz3", c_int32),
     ]
 
 
@@ -55,7 +56,7 @@ class PlanInfo(ctypes.Structure):
         ("M", c_int32), ("Mf", c_int32), ("n_freq", c_int32), ("n_relay", c_int32),
         ("kernel_width", c_int32), ("n_voxels", c_int32), ("dx", c_double), ("dy", c_double),
         ("cx", c_double), ("cy", c_double), ("beta", c_double), ("workspace_bytes", c_size_t),
-        ("freq_chunk", c_int32), ("plane_chunk", c_int32),
+        ("freq_chunk", c_int32), ("plane_chunk", c_int32), ("depth3d", c_int32),
     ]
 
 
@@ -121,4 +122,4 @@ def c_float_p(v) -> c_void_p:
 
 
 __all__ = ["load", "check", "Wavelet", "Geometry", "Options", "PlanInfo", "SIGNATURES",
-           "MODE_GRID", "MODE_POINTS", "MODE_SRSD", "MODE_SRSD_POINTS", "c_float"]
+           "MODE_GRID", "MODE_POINTS", "MODE_SRSD", "MODE_SRSD_POINTS", "MODE_GRID3D", "c_float"]

@@ -13,7 +13,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import MODE_GRID, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS, Geometry, Options, PlanInfo, Wavelet, check
+from ._lib import (MODE_GRID, MODE_GRID3D, MODE_POINTS, MODE_SRSD, MODE_SRSD_POINTS, Geometry, Options, PlanInfo,
+                   Wavelet, check)
 
 
 def _stream(stream=None) -> c_void_p:
@@ -43,7 +44,8 @@ class Plan:
                  n_freq: int, z, mode: int = MODE_GRID, x0=0.0, y0=0.0, dx=1.0, dy=1.0, nx=0, ny=0,
                  bins=None, coherent=True, sigma_rel=0.2, pad=2.0, tol=1e-6, M=0, freq_chunk=0,
                  plane_chunk=0, xp=(0.0, 0.0, 0.0), zref=0.0, alpha=None, plane_ptr=None,
-                 voxel_xy: torch.Tensor | None = None, stream=None):
+                 voxel_xy: torch.Tensor | None = None, relay_z: torch.Tensor | None = None, z_mid=0.0, dz3=0.0,
+                 mz3=0, stream=None):
         self._lib = _lib.load()
         self.handle = None
         L = relay_xy.shape[0]
@@ -85,6 +87,11 @@ class Plan:
             _need(voxel_xy, torch.float32, (voxel_xy.shape[0], 2), "voxel_xy")
             self.voxel_xy = voxel_xy
             geo.voxel_xy_dev = voxel_xy.data_ptr()
+        if relay_z is not None:
+            _need(relay_z, torch.float32, (L,), "relay_z")
+            self.relay_z = relay_z
+            geo.relay_z_dev = relay_z.data_ptr()
+        geo.z_mid, geo.dz3, geo.mz3 = z_mid, dz3, mz3
         opt.n_relay = L
         opt.pad, opt.tol, opt.M = pad, tol, M
         opt.freq_chunk, opt.plane_chunk = freq_chunk, plane_chunk
@@ -298,13 +305,18 @@ def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) ->
     wl, g = w.wavelet, w.grid
     if relay_xy is None:
         relay_xy = torch.from_numpy(np.ascontiguousarray(w.relay_xy)).to(device)
-    mode = {"grid": MODE_GRID, "points": MODE_POINTS, "srsd": MODE_SRSD, "srsd_points": MODE_SRSD_POINTS}[w.mode]
+    mode = {"grid": MODE_GRID, "points": MODE_POINTS, "srsd": MODE_SRSD, "srsd_points": MODE_SRSD_POINTS,
+            "grid3d": MODE_GRID3D}[w.mode]
     extra = {}
     if w.mode in ("points", "srsd_points"):
         extra["plane_ptr"] = w.plane_ptr
         extra["voxel_xy"] = torch.from_numpy(np.ascontiguousarray(w.voxel_xy)).to(device)
     if w.mode in ("srsd", "srsd_points"):
         extra["zref"] = w.zref
+    if w.mode == "grid3d":
+        e = w.extra
+        extra["relay_z"] = torch.from_numpy(np.ascontiguousarray(e["relay_z"], dtype=np.float32)).to(device)
+        extra["z_mid"], extra["dz3"], extra["mz3"] = e["z_mid"], e.get("dz3", 0.0), e.get("mz3", 0)
     args = dict(lambda_c=wl.lambda_c, n_time=wl.n_time, dt=wl.dt, t0=wl.t0, n_freq=wl.n_freq, z=g.z,
                 mode=mode, x0=g.x0, y0=g.y0, dx=g.dx, dy=g.dy, nx=g.nx, ny=g.ny, bins=wl.bins,
                 sigma_rel=wl.sigma_rel, pad=w.pad, xp=tuple(w.xp))

@@ -150,6 +150,12 @@ struct nursd_plan {
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
     size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_G2 = 0, off_T3 = 0, off_G3 = 0;
+    // 3D NURSD: intermediate plane, depth grid, depth weights per relay
+    double z_mid = 0, dz3 = 0;
+    int Mz3 = 0, FZ3 = 1;           // depth size; frequencies per stage-1 chunk
+    float2* d_W3 = nullptr;         // [Mz3][L]
+    double* d_zk3 = nullptr;        // [Mz3] depth offsets |p dz3| of the kernel planes
+    size_t off_Q3 = 0, off_Ut3 = 0;
 
     ~nursd_plan() {
         for (void* p : owned) (void)hipFree(p);
@@ -352,8 +358,9 @@ void layout_workspace(nursd_plan* p) {
     p->off_U = o;
     o = align_up(o + (size_t)p->F * p->M * p->M * c8);
     const size_t planes = (size_t)p->FC * p->ZC;
+    const size_t kplanes = std::max(planes, (size_t)p->FZ3 * p->Mz3);   // kernel rows: also the 3D stage
     p->off_Bt = o;
-    o = align_up(o + planes * (p->M / 2 + 1) * p->BS * c8);
+    o = align_up(o + kplanes * (p->M / 2 + 1) * p->BS * c8);
     p->off_Yt = o;
     o = align_up(o + planes * p->ny * p->M * c8);
     if (p->has_lists()) {
@@ -369,6 +376,12 @@ void layout_workspace(nursd_plan* p) {
         o = align_up(o + (size_t)p->FC3 * 3 * p->M * p->Mf * c8);
         p->off_G3 = o;
         o = align_up(o + (size_t)p->FC3 * 3 * p->Mf * p->Mf * c8);
+    }
+    if (p->mode == NURSD_MODE_GRID3D) {
+        p->off_Q3 = o;
+        o = align_up(o + (size_t)p->Mz3 * p->FZ3 * p->L * c8);
+        p->off_Ut3 = o;
+        o = align_up(o + (size_t)p->Mz3 * p->FZ3 * p->M * p->M * c8);
     }
     if (p->scaled()) {
         p->off_Tg = o;
@@ -431,9 +444,11 @@ ChunkGeom chunk_geom(const nursd_plan* p, int b0, int nb, int z0, int nzc) {
     return g;
 }
 
-int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_t s) {
-    for (int b0 = 0; b0 < p->F; b0 += p->FCn) {
-        const int nb = std::min(p->FCn, p->F - b0);
+// Type-1 NUFFT of n rows of P ([n][L], n = F by default) -> U [n][M][M].
+int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_t s, int n = -1) {
+    if (n < 0) n = p->F;
+    for (int b0 = 0; b0 < n; b0 += p->FCn) {
+        const int nb = std::min(p->FCn, n - b0);
         SpreadArgs sa{};
         sa.P = P;
         sa.ent = p->d_ent;
@@ -651,9 +666,32 @@ int run_srsd_points(nursd_plan* p, const float2* U, float2* V, float* I, char* w
     return NURSD_OK;
 }
 
+// 3D NURSD stage 1: the spectrum U0 of the field on the intermediate plane.
+int run_stage1_3d(nursd_plan* p, const float2* P, float2* U0, char* ws, hipStream_t s) {
+    float2* Q = reinterpret_cast<float2*>(ws + p->off_Q3);
+    float2* Ut = reinterpret_cast<float2*>(ws + p->off_Ut3);
+    float2* Bt = reinterpret_cast<float2*>(ws + p->off_Bt);
+    for (int b0 = 0; b0 < p->F; b0 += p->FZ3) {
+        const int nb = std::min(p->FZ3, p->F - b0);
+        ModulateArgs ma{P, p->d_W3, Q, p->L, p->Mz3, b0, nb};
+        LAUNCH(p, NURSD_STAGE_NURSD3D, ModulateArgs, launch_modulate, ma, s);
+        int rc = run_spectrum(p, Q, Ut, ws, s, p->Mz3 * nb);
+        if (rc) return rc;
+        ChunkGeom g = chunk_geom(p, b0, nb, 0, p->Mz3);
+        g.z = p->d_zk3;
+        g.pitch_x = g.pitch_y = nullptr;
+        P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+        a1.plain = 1;
+        LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
+        Stage1Args sa{g, Bt, Ut, U0, p->M, p->BS, p->Mz3, p->tw(p->M)};
+        LAUNCH(p, NURSD_STAGE_NURSD3D, Stage1Args, launch_stage1_reduce, sa, s);
+    }
+    return NURSD_OK;
+}
+
 int forward_from_P(nursd_plan* p, const float2* P, void* vol, float* I, char* ws, hipStream_t s) {
     float2* U = reinterpret_cast<float2*>(ws + p->off_U);
-    int rc = run_spectrum(p, P, U, ws, s);
+    int rc = p->mode == NURSD_MODE_GRID3D ? run_stage1_3d(p, P, U, ws, s) : run_spectrum(p, P, U, ws, s);
     if (rc) return rc;
     float2* V = vol ? static_cast<float2*>(vol) : reinterpret_cast<float2*>(ws + p->off_V);
     if (!p->coherent) V = nullptr;
@@ -1145,7 +1183,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     // geometry
     p->mode = geo->mode;
     if (p->mode != NURSD_MODE_GRID && p->mode != NURSD_MODE_POINTS && p->mode != NURSD_MODE_SRSD &&
-        p->mode != NURSD_MODE_SRSD_POINTS)
+        p->mode != NURSD_MODE_SRSD_POINTS && p->mode != NURSD_MODE_GRID3D)
         return bail(fail(NURSD_ERR_ARG, "unknown mode"));
     if (geo->nz < 1 || !geo->z) return bail(fail(NURSD_ERR_ARG, "no planes"));
     p->nz = geo->nz;
@@ -1178,7 +1216,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
 
     double vlo[2], vhi[2], mmin = 0;
     std::vector<float> vxy;
-    if (p->mode == NURSD_MODE_GRID || p->scaled()) {
+    if (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_GRID3D || p->scaled()) {
         if (p->nx < 1 || p->ny < 1) return bail(fail(NURSD_ERR_ARG, "nx, ny must be >= 1"));
         p->dx = p->vdx;
         p->dy = p->vdy;
@@ -1273,6 +1311,59 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if ((rc = upload(p, lo, &p->d_row_lo))) return bail(rc);
         if ((rc = upload(p, hi, &p->d_row_hi))) return bail(rc);
         if ((rc = upload(p, p->plane_ptr, &p->d_plane_ptr))) return bail(rc);
+    }
+
+    if (p->mode == NURSD_MODE_GRID3D) {
+        // relays on a non-planar surface: depths, the intermediate plane and
+        // the depth grid of stage 1
+        if (!geo->relay_z_dev) return bail(fail(NURSD_ERR_ARG, "GRID3D mode needs relay_z_dev"));
+        std::vector<float> rz;
+        if ((rc = read_points(geo->relay_z_dev, (size_t)p->L, rz, s))) return bail(rc);
+        p->z_mid = geo->z_mid;
+        if (!std::isfinite(p->z_mid)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite z_mid"));
+        for (double zz : p->z)
+            if (!(zz > p->z_mid)) return bail(fail(NURSD_ERR_GEOMETRY, "voxel planes must lie beyond z_mid"));
+        p->dz3 = geo->dz3 > 0 ? geo->dz3 : p->dx;
+        double ext = 0;
+        for (float v : rz) {
+            if (!std::isfinite(v)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite relay depth"));
+            ext = std::max(ext, std::fabs((double)v - p->z_mid));
+        }
+        if (geo->mz3 > 0) {
+            if (!is_pow2(geo->mz3) || geo->mz3 < 2 || geo->mz3 > 64)
+                return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "mz3 must be a power of two in [2, 64]"));
+            p->Mz3 = geo->mz3;
+            if (!(ext < 0.5 * p->Mz3 * p->dz3))
+                return bail(fail(NURSD_ERR_GEOMETRY, "relay depths outside the depth period of the 3D grid"));
+        } else {
+            for (int m = 8; m <= 64 && !p->Mz3; m *= 2)
+                if (ext <= 0.25 * m * p->dz3) p->Mz3 = m;
+            if (!p->Mz3) return bail(fail(NURSD_ERR_GEOMETRY, "relay depths span more than 16 depth pitches"));
+        }
+        const int Mz = p->Mz3;
+        // W_p(l) = Mz^-1 sum_{kz in I_Mz} e^{-j kz (z~_l + 2 pi p / Mz)}, p in I_Mz
+        std::vector<float2> W((size_t)Mz * p->L);
+        for (int l = 0; l < p->L; ++l) {
+            const double zt = 2.0 * M_PI * ((double)rz[l] - p->z_mid) / (Mz * p->dz3);
+            for (int pi = 0; pi < Mz; ++pi) {
+                const double th = zt + 2.0 * M_PI * (pi - Mz / 2) / Mz;
+                double re = 0, im = 0;
+                for (int kz = -Mz / 2; kz < Mz / 2; ++kz) {
+                    re += std::cos(kz * th);
+                    im -= std::sin(kz * th);
+                }
+                W[(size_t)pi * p->L + l] = make_float2((float)(re / Mz), (float)(im / Mz));
+            }
+        }
+        std::vector<double> zk(Mz);
+        for (int pi = 0; pi < Mz; ++pi) zk[pi] = std::fabs((double)(pi - Mz / 2)) * p->dz3;
+        if ((rc = upload(p, W, &p->d_W3))) return bail(rc);
+        if ((rc = upload(p, zk, &p->d_zk3))) return bail(rc);
+        p->FZ3 = std::max(1, std::min(p->F, 128 / Mz));
+        // stage 2 propagates from z_mid: kernel distances z - z_mid, and the
+        // illumination distance keeps the true depth
+        for (double& zz : p->z) zz -= p->z_mid;
+        p->xp[2] -= p->z_mid;
     }
 
     // chunking: about 128 planes of 512^2 per propagation chunk
@@ -1395,6 +1486,7 @@ int nursd_plan_info(const nursd_plan* p, nursd_plan_info_t* info) {
     info->workspace_bytes = p->ws_bytes;
     info->freq_chunk = p->FC;
     info->plane_chunk = p->ZC;
+    info->depth3d = p->Mz3;
     return NURSD_OK;
 }
 

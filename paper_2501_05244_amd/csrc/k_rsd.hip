@@ -37,6 +37,17 @@ __device__ __forceinline__ float2 rsd_kernel(double r2, double f_over_c) {
     return make_float2(c * ir, s * ir);
 }
 
+// e^{+j 2 pi (r f / c)}: the 3D-RSD kernel (no amplitude), finite at r = 0.
+__device__ __forceinline__ float2 rsd_kernel_plain(double r2, double f_over_c) {
+    float ir;
+    const double r = r2 > 0.0 ? sqrt_f64(r2, &ir) : 0.0;
+    const double cyc = r * f_over_c;
+    const float fr = (float)(cyc - rint(cyc));
+    float s, c;
+    sincos_cycles(fr, &s, &c);
+    return make_float2(c, s);
+}
+
 // e^{+j 2 pi d f / c} for a precomputed distance d.
 __device__ __forceinline__ float2 phase_of(double d, double f_over_c) {
     const double cyc = d * f_over_c;
@@ -89,7 +100,7 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
             v[q * E + e] = make_float2(0.f, 0.f);
             if (my <= H && n <= H) {
                 const double rx = n * px;
-                v[q * E + e] = rsd_kernel(fma(rx, rx, ryz), foc);
+                v[q * E + e] = a.plain ? rsd_kernel_plain(fma(rx, rx, ryz), foc) : rsd_kernel(fma(rx, rx, ryz), foc);
             }
         }
         // even extension: x[n] = x[M - n] for n > M/2, taken from the lane

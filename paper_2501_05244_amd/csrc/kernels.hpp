@@ -88,6 +88,7 @@ struct P1Args {
     float2* Bt;         // [planes][M/2+1][BS]
     int M, BS;
     const float2* tw;   // size M
+    int plain = 0;      // 1: the 3D-RSD kernel e^{+jkr} (no 1/r; r = 0 allowed)
 };
 hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s);
 
@@ -131,6 +132,28 @@ struct VideoArgs {
     double t_first, t_step;
 };
 hipError_t launch_video(const VideoArgs& a, hipStream_t s);
+
+// ---------------------------------------------------------------- 3D NURSD
+// Stage 1 (eq. 3D_NURSD): with W_p(l) the depth weights of relay l for depth
+// index p of the 3D grid, the spectrum at the intermediate plane is
+//   U0[k] = sum_p Ghat(p dz)[k] NUFFT2{P_l W_p(l)}[k].
+struct ModulateArgs {
+    const float2* P;      // [F][L] phasors
+    const float2* W;      // [Mz][L] depth weights
+    float2* Q;            // [Mz][nb][L] modulated phasors
+    int L, Mz, b0, nb;
+};
+hipError_t launch_modulate(const ModulateArgs& a, hipStream_t s);
+
+struct Stage1Args {
+    ChunkGeom g;          // frequencies b0 .. b0+nb-1, planes = the Mz depths
+    const float2* Bt;     // [nb * Mz][M/2+1][BS] kernel quadrant rows (plain kernel)
+    const float2* Ut;     // [Mz][nb][M][M] spectra of the modulated phasors (/ M^2, FFT order)
+    float2* U0;           // [F][M][M] stage-1 spectra (/ M^2, FFT order)
+    int M, BS, Mz;
+    const float2* tw;
+};
+hipError_t launch_stage1_reduce(const Stage1Args& a, hipStream_t s);
 
 // ---------------------------------------------------------------- compression
 hipError_t launch_subsample_nearest(const float2* in, float2* out, int F, int ny, int nx, int D, hipStream_t s);

@@ -1,0 +1,76 @@
+"""GPU parity of the 3D NURSD for non-planar relays (eq. 3D_NURSD) against
+the FP64 oracle's direct 3D NUDFT-1, direct 3D DFT of the 3D-RSD kernel and
+direct plane-to-plane stage.  Tolerance: relative L2 <= 1e-4."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import nursd_ref as o
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+def case(seed, n=24, L=300, F=3, zs=(0.3, 0.45, 0.7), amp=0.05, z_mid=0.08, dz3=0.02, mz3=0, dx=1.0 / 32):
+    rng = np.random.default_rng(seed)
+    half = n * dx / 2
+    g = scenes.Grid(x0=-half + dx / 2, y0=-half + dx / 2, dx=dx, dy=dx, nx=n, ny=n, z=np.array(zs))
+    xy = rng.uniform(-0.9 * half, 0.9 * half, size=(L, 2)).astype(np.float32)
+    rz = scenes.nonplanar_wall(xy, amp) + rng.uniform(-0.002, 0.002, L).astype(np.float32)
+    wl = scenes.Wavelet(lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=F)
+    w = scenes.Workload("nonplanar_small", xy, np.array([0.02, 0.01, 0.0]), wl, g, mode="grid3d",
+                        extra={"relay_z": rz, "z_mid": z_mid, "dz3": dz3, "mz3": mz3})
+    P = np.ascontiguousarray((rng.normal(size=(F, L)) + 1j * rng.normal(size=(F, L))).astype(np.complex64))
+    return w, P
+
+
+def oracle(w, P, f, Mz, grid=None):
+    xyz = np.concatenate([w.relay_xy.astype(np.float64), w.extra["relay_z"].astype(np.float64)[:, None]], 1)
+    return o.nursd3d_grid(P.astype(np.complex128), xyz, f, o.frame_for_workload(w), w.grid if grid is None else grid,
+                          w.xp, w.extra["z_mid"], w.extra["dz3"], Mz)
+
+
+@pytest.mark.parametrize("mz3,chunks", [(0, (0, 0)), (16, (2, 2))])
+def test_nursd3d_small(device, mz3, chunks):
+    print("case: nursd3d small", mz3, chunks, flush=True)
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P = case(3 + mz3, mz3=mz3)
+    plan = plan_from_workload(w, device, freq_chunk=chunks[0], plane_chunk=chunks[1])
+    V, I = plan.forward_phasor(torch.from_numpy(P).to(device))
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, w.wavelet.n_freq)
+    ext = np.abs(w.extra["relay_z"].astype(np.float64) - w.extra["z_mid"]).max()
+    Mz = mz3 or min(m for m in (8, 16, 32, 64) if ext <= m * w.extra["dz3"] / 4)   # the plan's depth rule
+    ref = oracle(w, P, f, Mz)
+    assert rel(V.cpu().numpy(), ref) < TOL
+    assert rel(I.cpu().numpy(), np.abs(ref)) < TOL
+
+
+def test_nursd3d_rejects_bad_geometry(device):
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, _ = case(1, mz3=4)                # depths up to 0.13 m from z_mid, period 4 * 0.02 m
+    with pytest.raises(RuntimeError, match="GEOMETRY"):
+        plan_from_workload(w, device)
+    w, _ = case(1, zs=(0.05, 0.3))       # a voxel plane before the intermediate plane
+    with pytest.raises(RuntimeError, match="GEOMETRY"):
+        plan_from_workload(w, device)
+
+
+@pytest.mark.slow
+def test_nursd3d_medium(device):
+    """2,048 relays on a curved wall, 128 x 128 voxels (M = 256), depth grid of
+    16, two frequencies, four planes."""
+    print("case: nursd3d medium", flush=True)
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P = case(9, n=128, L=2048, F=2, zs=(0.6, 1.0, 1.5, 2.2), amp=0.03, z_mid=0.04, dz3=0.02, mz3=16,
+                dx=1.0 / 128)
+    plan = plan_from_workload(w, device)
+    assert plan.info["M"] == 256
+    V, _ = plan.forward_phasor(torch.from_numpy(P).to(device), intensity=False)
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, 2)
+    ref = oracle(w, P, f, 16)
+    assert rel(V.cpu().numpy(), ref) < TOL

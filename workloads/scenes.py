@@ -60,7 +60,7 @@ class Workload:
     hist: np.ndarray | None = None        # float32 [L][T]
     scatterers: np.ndarray | None = None  # float64 [S][3]
     albedo: np.ndarray | None = None      # float64 [S]
-    mode: str = "grid"                    # "grid" | "points" | "srsd" | "srsd_points"
+    mode: str = "grid"                    # "grid" | "points" | "srsd" | "srsd_points" | "grid3d"
     plane_ptr: np.ndarray | None = None   # int32 [Z+1] (points mode)
     voxel_xy: np.ndarray | None = None    # float32 [V][2] (points mode)
     zref: float = 0.0                     # srsd: alpha(z) = zref / z
@@ -260,6 +260,26 @@ def config_srsd_points(render: bool = True, planes: int = 64, per_side: int = 12
     w.plane_ptr = fr.plane_ptr
     w.voxel_xy = fr.voxel_xy
     w.grid = Grid(w.grid.x0, w.grid.y0, w.grid.dx, w.grid.dy, w.grid.nx, w.grid.ny, z=fr.grid.z)
+    return w
+
+
+def nonplanar_wall(xy: np.ndarray, amp: float) -> np.ndarray:
+    """Depth of a curved relay wall at lateral positions xy: a smooth bump and
+    ripple, |z| <= amp."""
+    x, y = xy[:, 0].astype(np.float64), xy[:, 1].astype(np.float64)
+    return (amp * (0.6 * np.cos(0.5 * np.pi * x) * np.cos(0.5 * np.pi * y) - 0.4 * np.sin(2.3 * x + 1.1 * y))
+            ).astype(np.float32)
+
+
+def config_nonplanar(render: bool = False) -> Workload:
+    """3D NURSD at SPAD scale: the 65,536 oblique SPAD samples of config_spad
+    on a curved wall (depth within +-5 cm), intermediate plane 6 cm in front,
+    3D grid depth pitch 2 cm, 96 frequencies, 256x256x128 voxels over
+    [-1,1]^2 x [1,3] m.  Histograms are not rendered (phasors are inputs)."""
+    w = config_spad(render=False)
+    w.name = "nonplanar"
+    w.mode = "grid3d"
+    w.extra = {"relay_z": nonplanar_wall(w.relay_xy, 0.05), "z_mid": 0.06, "dz3": 0.02}
     return w
 
 
