@@ -943,7 +943,7 @@ int batch_build(nursd_batch* bt, int budget) {
             a.nb = p->F;
             it.push_back(a);
             gx.push_back(p->nbands);
-            gy.push_back(p->F);
+            gy.push_back((p->F + spread_freqs(Mf) - 1) / spread_freqs(Mf));
             FineYArgs f{};
             f.T1 = a.T1;
             f.U = reinterpret_cast<float2*>(ws + sc.off_U);

@@ -6,7 +6,8 @@
 // |z| <= 1, over w fine cells; oversampling sigma = 2 (fine grid Mf = 2M).
 //
 // k_spread_xfft: one workgroup owns a band of kBandRows fine rows (all Mf
-// columns) of one frequency in LDS.  Relay samples are pre-binned per band
+// columns) of spread_freqs frequencies in LDS (the kernel weights of a sample
+// are computed once for all of them).  Relay samples are pre-binned per band
 // and sorted by x; each wavefront owns a disjoint range of columns and walks
 // the samples overlapping it, one sample per step with one lane per kernel
 // tap, so every LDS cell is updated by one wave in a fixed order: no atomics,
@@ -39,24 +40,26 @@ __device__ __forceinline__ float lane_f(float v, int j) {
 template <int MF>
 __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, int by) {
     constexpr int kBandRows = spread_band_rows(MF);
+    constexpr int NF = spread_freqs(MF);
     constexpr int LDT = spread_row_stride<MF>();
-    extern __shared__ float2 tile[];   // [kBandRows][LDT]
+    extern __shared__ float2 tile[];   // [NF][kBandRows][LDT]
     const int band = bx;
-    const int b = a.b0 + by;
+    const int fa = a.b0 + by * NF;                    // first frequency of the block
+    const int nf = min(NF, a.b0 + a.nb - fa);
     const int tid = threadIdx.x;
     const int e0 = a.band_ptr[band], e1 = a.band_ptr[band + 1];
     const int M = a.M;
     const int y0 = band * kBandRows;
-    float2* T1 = a.T1 + (size_t)by * M * MF;
+    float2* T1 = a.T1 + (size_t)by * NF * M * MF;     // chunk-local frequency by * NF
     if (e0 == e1) {
         // empty band: its transform is zero
-        for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
-            const int k = i / kBandRows, r = i % kBandRows;
-            T1[(size_t)k * MF + y0 + r] = make_float2(0.f, 0.f);
+        for (int i = tid; i < nf * M * kBandRows; i += kSpreadThreads) {
+            const int f = i / (M * kBandRows), k = (i / kBandRows) % M, r = i % kBandRows;
+            T1[((size_t)f * M + k) * MF + y0 + r] = make_float2(0.f, 0.f);
         }
         return;
     }
-    for (int i = tid; i < kBandRows * LDT; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
+    for (int i = tid; i < NF * kBandRows * LDT; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
     constexpr int kCols = MF / kSpreadWaves;          // columns owned by one wave
@@ -69,48 +72,56 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     const int w = a.w;
     const int s0 = a.wave_rng[(band * kSpreadWaves + wave) * 2];
     const int s1 = a.wave_rng[(band * kSpreadWaves + wave) * 2 + 1];
-    const float2* Pb = a.P + (size_t)b * a.L;
+    const float2* Pb = a.P + (size_t)fa * a.L;
     const bool tap_ok = ti < w && tj < w;
-    // 64 entries per round trip: each lane fetches one entry and its phasor,
+    // 64 entries per round trip: each lane fetches one entry and its phasors,
     // then the wave walks them in order, broadcasting one per step.
     for (int base = s0; base < s1; base += 64) {
         const int e = base + lane;
         int packed = 0;
         float efx = 0.f, efy = 0.f;
-        float2 ep = make_float2(0.f, 0.f);
+        float2 ep[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ep[f] = make_float2(0.f, 0.f);
         if (e < s1) {
             const SpreadEntry en = a.ent[e];
             packed = ((int)en.ix0 & 0xffff) | ((int)en.iy0 << 16);
             efx = en.fx;
             efy = en.fy;
-            ep = Pb[en.idx];
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+                if (f < nf) ep[f] = Pb[(size_t)f * a.L + en.idx];
         }
         const int cnt = min(64, s1 - base);
         for (int j = 0; j < cnt; ++j) {
             // entry j of the batch, broadcast through scalar registers
             const int pk = __builtin_amdgcn_readlane(packed, j);
             const float fx = lane_f(efx, j), fy = lane_f(efy, j);
-            const float px = lane_f(ep.x, j), py = lane_f(ep.y, j);
             const int cx = (int)(short)(pk & 0xffff) + ti;
             const int cy = (pk >> 16) + tj;
             if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
                 const float wgt = es_kernel(((float)ti - fx) * inv_hw, bl2e) * es_kernel(((float)tj - fy) * inv_hw, bl2e);
-                float2* cell = &tile[(cy - y0) * LDT + cx];
-                float2 c = *cell;
-                c.x = fmaf(px, wgt, c.x);
-                c.y = fmaf(py, wgt, c.y);
-                *cell = c;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const float px = lane_f(ep[f].x, j), py = lane_f(ep[f].y, j);
+                    float2* cell = &tile[(f * kBandRows + cy - y0) * LDT + cx];
+                    float2 c = *cell;
+                    c.x = fmaf(px, wgt, c.x);
+                    c.y = fmaf(py, wgt, c.y);
+                    *cell = c;
+                }
             }
         }
     }
     __syncthreads();
-    fft_lines<MF, kSpreadThreads / kBandRows, false>(tile, LDT, kBandRows, a.tw);
+    fft_lines<MF, kSpreadThreads / (NF * kBandRows), false>(tile, LDT, NF * kBandRows, a.tw);
     // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
-    for (int i = tid; i < M * kBandRows; i += kSpreadThreads) {
-        const int km = i / kBandRows, r = i % kBandRows;      // km = kx mod M
-        const int kf = km < M / 2 ? km : km + (MF - M);       // kx mod MF
-        const float2 v = tile[r * LDT + kf];
-        T1[(size_t)km * MF + y0 + r] = cscale(v, a.decx[km]);
+    for (int i = tid; i < nf * M * kBandRows; i += kSpreadThreads) {
+        const int f = i / (M * kBandRows);
+        const int km = (i / kBandRows) % M, r = i % kBandRows;   // km = kx mod M
+        const int kf = km < M / 2 ? km : km + (MF - M);           // kx mod MF
+        const float2 v = tile[(f * kBandRows + r) * LDT + kf];
+        T1[((size_t)f * M + km) * MF + y0 + r] = cscale(v, a.decx[km]);
     }
 }
 
@@ -182,11 +193,13 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
 template <int MF>
 static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
     constexpr int kBandRows = spread_band_rows(MF);
-    size_t sh = (size_t)kBandRows * spread_row_stride<MF>() * sizeof(float2);
+    constexpr int NF = spread_freqs(MF);
+    size_t sh = (size_t)NF * kBandRows * spread_row_stride<MF>() * sizeof(float2);
     hipError_t e = hipFuncSetAttribute((const void*)k_spread_xfft<MF>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spread_xfft<MF>, dim3(MF / kBandRows, a.nb), dim3(kSpreadThreads), sh, s, a);
+    hipLaunchKernelGGL(k_spread_xfft<MF>, dim3(MF / kBandRows, (a.nb + NF - 1) / NF), dim3(kSpreadThreads), sh, s,
+                       a);
     return hipGetLastError();
 }
 
@@ -227,7 +240,7 @@ hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStr
     switch (Mf) {
 #define NURSD_SG(n) \
     case n: return launch_grouped(k_spread_xfft_grouped<n>, g, kSpreadThreads, \
-                                  (size_t)spread_band_rows(n) * spread_row_stride<n>() * sizeof(float2), s);
+                                  (size_t)spread_freqs(n) * spread_band_rows(n) * spread_row_stride<n>() * sizeof(float2), s);
         NURSD_SG(128) NURSD_SG(256) NURSD_SG(512) NURSD_SG(1024) NURSD_SG(2048)
 #undef NURSD_SG
         default: return hipErrorInvalidValue;

@@ -23,7 +23,10 @@ struct SpreadEntry {
 };
 
 // Fine-grid rows per spreading band (one band of one frequency fills LDS).
-constexpr int spread_band_rows(int Mf) { return Mf <= 1024 ? 16 : 8; }
+constexpr int spread_band_rows(int) { return 8; }
+// Frequencies spread by one workgroup: the kernel weights of a sample are
+// computed once and applied to each of them (one LDS tile per frequency).
+constexpr int spread_freqs(int Mf) { return Mf <= 1024 ? 2 : 1; }
 // Wavefronts per spreading workgroup; wave w owns fine columns
 // [w * Mf / kSpreadWaves, (w + 1) * Mf / kSpreadWaves).
 constexpr int kSpreadWaves = 16;
