@@ -75,7 +75,7 @@ template <int M>
 __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = F::SCR + 1;
-    extern __shared__ float2 sm[];      // [kP1Waves][SCRP], then twiddles [M]
+    extern __shared__ float2 sm[];      // [kP1Waves][SCRP], twiddles [M], Nyquist samples [LB]
     float2* tws = sm + kP1Waves * SCRP;
     for (int i = threadIdx.x; i < M; i += kP1Waves * 64) tws[i] = a.tw[i];
     const int p = by;
@@ -88,6 +88,18 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     constexpr int LB = kP1Waves * LPW;
     const int my0 = bx * LB;
+    // For M >= 128 the sample n = M/2 of a row sits alone in slot E/2 of lane
+    // 0; the block computes those LB samples once, one per thread, instead of
+    // every wave spending a whole slot on one lane.
+    constexpr bool NYQ_LDS = E >= 2;
+    float2* nyq = tws + M;
+    if (NYQ_LDS && tid < LB) {
+        const int my = my0 + tid;
+        const double ry = (my <= H ? my : 0) * py, rx = H * px;
+        nyq[tid] = a.plain ? rsd_kernel_plain(fma(rx, rx, fma(ry, ry, z * z)), foc)
+                           : rsd_kernel(fma(rx, rx, fma(ry, ry, z * z)), foc);
+    }
+    __syncthreads();
     float2 v[F::NV];
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
@@ -98,7 +110,9 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
         for (int e = 0; e < E; ++e) {
             const int n = lane + 64 * e;
             v[q * E + e] = make_float2(0.f, 0.f);
-            if (my <= H && n <= H) {
+            if (NYQ_LDS && 64 * e == H) {
+                if (lane == 0 && my <= H) v[q * E + e] = nyq[wave * LPW + q];
+            } else if (my <= H && n <= H) {
                 const double rx = n * px;
                 v[q * E + e] = a.plain ? rsd_kernel_plain(fma(rx, rx, ryz), foc) : rsd_kernel(fma(rx, rx, ryz), foc);
             }
@@ -117,7 +131,6 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
         }
     }
     float2* scr = sm + wave * SCRP;
-    __syncthreads();
     F::template nat_to_perm<false>(v, scr, tws, lane);
 #pragma unroll
     for (int h = 0; h < F::GPL; ++h)
@@ -426,7 +439,8 @@ hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s) {
         using F = WaveFFT<MM>;
         constexpr int LB = kP1Waves * F::LPW;
         dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
-        return launch_rsd(k_kernel_rows<MM>, grid, kP1Waves * 64, (size_t)(kP1Waves * (F::SCR + 1) + MM) * sizeof(float2),
+        return launch_rsd(k_kernel_rows<MM>, grid, kP1Waves * 64,
+                          (size_t)(kP1Waves * (F::SCR + 1) + MM + kP1Waves * F::LPW) * sizeof(float2),
                           s, a);
     })
 }
@@ -465,7 +479,7 @@ hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t
     NURSD_SWITCH_M(M, {
         using F = WaveFFT<MM>;
         return launch_grouped(k_kernel_rows_grouped<MM>, g, kP1Waves * 64,
-                              (size_t)(kP1Waves * (F::SCR + 1) + MM) * sizeof(float2), s);
+                              (size_t)(kP1Waves * (F::SCR + 1) + MM + kP1Waves * F::LPW) * sizeof(float2), s);
     })
 }
 
