@@ -128,14 +128,21 @@ __device__ __forceinline__ void bluestein_line(float2* v, float2* scr, const flo
     B::template perm_to_nat<true>(v, scr, tw_lb, lane);
 }
 
+// Row pass: 8 rows per block (8 adjacent columns per store of the transposed
+// output); 80 KB of LDS per block at M = 512, so two blocks share a CU.
 constexpr int kChirpWaves = 8;
+// Column passes: one Bluestein line per wave, no block-level exchange (6
+// waves per block, which lets two blocks share a CU, measured slower).
+constexpr int kChirpColWaves = 8;
 
 template <int M>
 __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     using B = WaveFFT<2 * M>;
     constexpr int LB = 2 * M, EB = B::E;
-    constexpr int SCRP = B::SCR + 1;
-    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles [LB]
+    constexpr int SCRP = B::SCR;
+    constexpr int MP = M + 1;                // staging row of the transposed store
+    static_assert(kChirpWaves * MP <= kChirpWaves * SCRP, "staging must fit the scratch");
+    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP] (later [kChirpWaves][MP]), twiddles [LB]
     float2* tws = sm + kChirpWaves * SCRP;
     for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws[i] = a.tw_lb[i];
     __syncthreads();
@@ -158,39 +165,41 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     float2* scr = sm + wave * SCRP;
     bluestein_line<M>(v, scr, tws, hhat, lane);
     // outputs k' = lane + 64 e < M: S[k] with k = k' - M/2, stored at kx = k mod M
-    NURSD_WAVE_SYNC();
+    // in the block's staging rows (they overlap other waves' scratch: barrier)
+    __syncthreads();
+    float2* stage = sm + wave * MP;
 #pragma unroll
     for (int e = 0; e < M / 64; ++e) {
         const int kp = lane + 64 * e;
         const int k = kp - M / 2;
-        scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+        stage[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
     }
     __syncthreads();
     float2* S1 = a.S1t + (size_t)p * M * N;
     for (int i = threadIdx.x; i < M * kChirpWaves; i += kChirpWaves * 64) {
         const int kx = i / kChirpWaves, j = i % kChirpWaves;
-        if (iy0 + j < N) S1[(size_t)kx * N + iy0 + j] = sm[j * SCRP + kx];
+        if (iy0 + j < N) S1[(size_t)kx * N + iy0 + j] = sm[j * MP + kx];
     }
 }
 
 template <int M>
-__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
     constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E;
     static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
     constexpr int SCRP = B::SCR + 1;
-    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles LB, twiddles M
-    float2* tws_lb = sm + kChirpWaves * SCRP;
+    extern __shared__ float2 sm[];           // [kChirpColWaves][SCRP], twiddles LB, twiddles M
+    float2* tws_lb = sm + kChirpColWaves * SCRP;
     float2* tws_m = tws_lb + LB;
-    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws_lb[i] = a.tw_lb[i];
-    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws_m[i] = a.tw_m[i];
+    for (int i = threadIdx.x; i < LB; i += kChirpColWaves * 64) tws_lb[i] = a.tw_lb[i];
+    for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
     __syncthreads();
     const int p = blockIdx.y;
     const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
     (void)b;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kx = blockIdx.x * kChirpWaves + wave;
+    const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;
     const int N = a.N;
     const double ahm = a.alpha[iz] / (2.0 * M);
@@ -255,23 +264,23 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_cols(ChirpArgs a) {
 // -> T2[p][s][jy].  The oversampled line has the Bluestein length 2M, so it
 // shares that transform's twiddles and scratch.
 template <int M>
-__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
     constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E, MF = 2 * M;
     static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
     constexpr int SCRP = B::SCR + 1;
     static_assert(SCRP >= MF, "oversampled line must fit the scratch");
-    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP], twiddles LB, twiddles M
-    float2* tws_lb = sm + kChirpWaves * SCRP;
+    extern __shared__ float2 sm[];           // [kChirpColWaves][SCRP], twiddles LB, twiddles M
+    float2* tws_lb = sm + kChirpColWaves * SCRP;
     float2* tws_m = tws_lb + LB;
-    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws_lb[i] = a.tw_lb[i];
-    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws_m[i] = a.tw_m[i];
+    for (int i = threadIdx.x; i < LB; i += kChirpColWaves * 64) tws_lb[i] = a.tw_lb[i];
+    for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
     __syncthreads();
     const int p = blockIdx.y;
     const int iz = a.g.z0 + p % a.g.nzc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kx = blockIdx.x * kChirpWaves + wave;
+    const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;                      // wave-uniform; no block barriers below
     const int N = a.N;
     const double ahm = a.alpha[iz] / (2.0 * M);
@@ -383,12 +392,12 @@ hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s) {
         case 512: {
             using B = WaveFFT<1024>;
             return launch_k(k_chirp_rows<512>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * B::SCR + 1024) * sizeof(float2), s, a);
         }
         case 1024: {
             using B = WaveFFT<2048>;
             return launch_k(k_chirp_rows<1024>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * B::SCR + 2048) * sizeof(float2), s, a);
         }
         default: return hipErrorInvalidValue;
     }
@@ -399,14 +408,14 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
     switch (a.M) {
         case 512: {
             using B = WaveFFT<1024>;
-            return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
+            return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
                             s, a);
         }
         case 1024: {
             using B = WaveFFT<2048>;
-            return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
+            return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
                             s, a);
         }
         default: return hipErrorInvalidValue;
@@ -418,14 +427,14 @@ hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s) {
     switch (a.M) {
         case 512: {
             using B = WaveFFT<1024>;
-            return launch_k(k_chirp_type2_cols<512>, dim3((512 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
+            return launch_k(k_chirp_type2_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
                             s, a);
         }
         case 1024: {
             using B = WaveFFT<2048>;
-            return launch_k(k_chirp_type2_cols<1024>, dim3((1024 / 2 + 1 + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
+            return launch_k(k_chirp_type2_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
                             s, a);
         }
         default: return hipErrorInvalidValue;
