@@ -12,7 +12,9 @@
 //                 -> fine grid G2[p][jy][jx] (rows no voxel can reach are
 //                 skipped).
 //   k_type2_interp: per voxel, w x w gather from the fine grid of every
-//                 frequency of the chunk, illumination phase, accumulation.
+//                 frequency of the chunk, illumination phase (advanced by a
+//                 per-voxel step factor over the evenly spaced frequencies of
+//                 the chunk), accumulation.
 #include "kernels.hpp"
 #include "wavefft.hpp"
 
@@ -157,11 +159,12 @@ __global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
     const double ty = (y - a.cy) / py * 2.0 + MF / 2;
     const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
     const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
+    const float ihw = (float)(1.0 / hw);
     float wx[8], wy[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        wx[i] = i < a.w ? es_w(((float)i - fx) / (float)hw, a.beta) : 0.f;
-        wy[i] = i < a.w ? es_w(((float)i - fy) / (float)hw, a.beta) : 0.f;
+        wx[i] = i < a.w ? es_w(((float)i - fx) * ihw, a.beta) : 0.f;
+        wy[i] = i < a.w ? es_w(((float)i - fy) * ihw, a.beta) : 0.f;
     }
     const double dd = dist3d(x - a.xp0, y - a.xp1, z - a.xp2);
     float2 acc = make_float2(0.f, 0.f);
@@ -169,15 +172,38 @@ __global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
         if (a.coherent) acc = a.V[v];
         else acc.x = a.I[v];
     }
+    // the w x w taps: rows and columns of the periodic fine grid (w <= 8; the
+    // loops are unrolled so every gather of a frequency is in flight at once)
+    int col[8], rowoff[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        col[i] = (ix0 + i) & (MF - 1);
+        rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
+    }
+    // the chunk's frequencies are evenly spaced: the illumination phase
+    // advances by a fixed per-voxel factor
+    float2 ph = make_float2(1.f, 0.f), st = make_float2(1.f, 0.f);
+    if (a.coherent) {
+        const double cyc0 = dd * (a.g.f[a.g.b0] / kC), cyc1 = dd * (a.g.df / kC);
+        float sn, cs;
+        sincos_cycles((float)(cyc0 - rint(cyc0)), &sn, &cs);
+        ph = make_float2(cs, sn);
+        sincos_cycles((float)(cyc1 - rint(cyc1)), &sn, &cs);
+        st = make_float2(cs, sn);
+    }
     for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
         const int p = (b - a.g.b0) * a.g.nzc + zl;
         const float2* G2 = a.G2 + (size_t)p * MF * MF;
         float2 s = make_float2(0.f, 0.f);
-        for (int j = 0; j < a.w; ++j) {
-            const float2* row = G2 + (size_t)((iy0 + j) & (MF - 1)) * MF;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j >= a.w) break;
+            const float2* row = G2 + rowoff[j];
             float2 r = make_float2(0.f, 0.f);
-            for (int i = 0; i < a.w; ++i) {
-                const float2 gv = row[(ix0 + i) & (MF - 1)];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i >= a.w) break;
+                const float2 gv = row[col[i]];
                 r.x = fmaf(wx[i], gv.x, r.x);
                 r.y = fmaf(wx[i], gv.y, r.y);
             }
@@ -185,11 +211,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
             s.y = fmaf(wy[j], r.y, s.y);
         }
         if (a.coherent) {
-            const double cyc = dd * (a.g.f[b] / kC);
-            const float fr = (float)(cyc - rint(cyc));
-            float sn, cs;
-            sincos_cycles(fr, &sn, &cs);
-            acc = cadd(acc, cmul(make_float2(cs, sn), s));
+            acc = cadd(acc, cmul(ph, s));
+            ph = cmul(ph, st);
         } else {
             acc.x += sqrtf(s.x * s.x + s.y * s.y);
         }
@@ -235,6 +258,7 @@ static hipError_t type2_impl(const Type2Args& a, hipStream_t s) {
 }
 
 hipError_t launch_type2(const Type2Args& a, hipStream_t s) {
+    if (!a.g.uni) return hipErrorInvalidValue;     // phases advance by a fixed step
     switch (a.M) {
         case 512: return type2_impl<512>(a, s);
         case 1024: return type2_impl<1024>(a, s);
@@ -243,6 +267,7 @@ hipError_t launch_type2(const Type2Args& a, hipStream_t s) {
 }
 
 hipError_t launch_type2_fine(const Type2Args& a, hipStream_t s) {
+    if (!a.g.uni) return hipErrorInvalidValue;     // phases advance by a fixed step
     switch (a.M) {
         case 512: return type2_fine_impl<512>(a, s);
         case 1024: return type2_fine_impl<1024>(a, s);
