@@ -135,6 +135,8 @@ struct nursd_plan {
     int* d_plane_ptr = nullptr;   // POINTS
     int* d_row_lo = nullptr;
     int* d_row_hi = nullptr;
+    int* d_col_lo = nullptr;
+    int* d_col_hi = nullptr;
     int max_vox = 0;
     float* d_decx = nullptr;
     float* d_decy = nullptr;
@@ -612,6 +614,8 @@ Type2Args type2_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, 
     t.voxel_xy = p->voxel_xy_dev;
     t.row_lo = p->d_row_lo;
     t.row_hi = p->d_row_hi;
+    t.col_lo = p->d_col_lo;
+    t.col_hi = p->d_col_hi;
     t.max_vox = p->max_vox;
     t.first = b0 == 0;
     t.last = b0 + nb >= p->F;
@@ -1284,18 +1288,17 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     if (p->has_lists()) {
         if (p->M < 512)
             return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "voxel lists need a transform size M >= 512 (set options.M)"));
-        // fine rows each plane's interpolation can reach (centred fine cells;
-        // a scaled plane has pitch dy / alpha)
-        std::vector<int> lo(p->nz), hi(p->nz);
+        // fine rows and columns each plane's interpolation can reach (centred
+        // fine cells; a scaled plane has pitch dx / alpha, dy / alpha)
+        std::vector<int> lo(p->nz), hi(p->nz), clo(p->nz), chi(p->nz);
         const double hw = 0.5 * p->w;
-        for (int iz = 0; iz < p->nz; ++iz) {
+        auto reach = [&](int iz, int axis, double centre, double pitch, int* first, int* last) {
             int a = 1 << 30, c = -(1 << 30);
-            const double pitch = p->mode == NURSD_MODE_SRSD_POINTS ? p->dy / p->alpha[iz] : p->dy;
             for (int v = p->plane_ptr[iz]; v < p->plane_ptr[iz + 1]; ++v) {
-                const double ty = ((double)vxy[2 * v + 1] - p->cy) / pitch * 2.0 + p->Mf / 2;
-                const int iy0 = (int)std::ceil(ty - hw);
-                a = std::min(a, iy0);
-                c = std::max(c, iy0 + p->w - 1);
+                const double t = ((double)vxy[2 * v + axis] - centre) / pitch * 2.0 + p->Mf / 2;
+                const int i0 = (int)std::ceil(t - hw);
+                a = std::min(a, i0);
+                c = std::max(c, i0 + p->w - 1);
             }
             if (a > c) {          // empty plane
                 a = 0;
@@ -1304,12 +1307,19 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
                 a = 0;
                 c = p->Mf - 1;
             }
-            lo[iz] = a;
-            hi[iz] = c;
+            *first = a;
+            *last = c;
+        };
+        for (int iz = 0; iz < p->nz; ++iz) {
+            const bool sc = p->mode == NURSD_MODE_SRSD_POINTS;
+            reach(iz, 1, p->cy, sc ? p->dy / p->alpha[iz] : p->dy, &lo[iz], &hi[iz]);
+            reach(iz, 0, p->cx, sc ? p->dx / p->alpha[iz] : p->dx, &clo[iz], &chi[iz]);
             p->max_vox = std::max(p->max_vox, p->plane_ptr[iz + 1] - p->plane_ptr[iz]);
         }
         if ((rc = upload(p, lo, &p->d_row_lo))) return bail(rc);
         if ((rc = upload(p, hi, &p->d_row_hi))) return bail(rc);
+        if ((rc = upload(p, clo, &p->d_col_lo))) return bail(rc);
+        if ((rc = upload(p, chi, &p->d_col_hi))) return bail(rc);
         if ((rc = upload(p, p->plane_ptr, &p->d_plane_ptr))) return bail(rc);
     }
 

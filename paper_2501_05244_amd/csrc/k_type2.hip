@@ -26,6 +26,7 @@ __device__ __forceinline__ float es_w(float z, float beta) {
 }
 
 constexpr int kT2Waves = 8;
+constexpr int kT2RowWaves = 8;
 
 template <int M>
 __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
@@ -56,6 +57,11 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     const float2* Ub = a.U + (size_t)b * M * M;
     float2* T2 = a.T2 + (size_t)p * M * MF;
+    // only the fine rows the row pass reads are stored: kT2RowWaves-row bands
+    // from the first row any voxel of the plane reaches (periodic)
+    const int iz = a.g.z0 + p % a.g.nzc;
+    const int lo = a.row_lo[iz];
+    const int nrows = ((a.row_hi[iz] - lo) / kT2RowWaves + 1) * kT2RowWaves;
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int s = side ? ((M - kx) & (M - 1)) : kx;
@@ -85,12 +91,10 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
             for (int d = 0; d < 8; ++d) {
                 int q;
                 const int jy = G::perm_k(lane, h, d, q);
-                T2[(size_t)s * MF + jy] = v[h * 8 + d];
+                if (((jy - lo) & (MF - 1)) < nrows) T2[(size_t)s * MF + jy] = v[h * 8 + d];
             }
     }
 }
-
-constexpr int kT2RowWaves = 8;
 
 template <int M>
 __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
@@ -125,13 +129,15 @@ __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
     G::template nat_to_perm<true>(v, row, tws, lane);
     const int jy = (jy0 + wave) & (MF - 1);
     float2* G2 = a.G2 + ((size_t)p * MF + jy) * MF;
+    // only the fine columns some voxel of the plane reaches are stored
+    const int clo = a.col_lo[iz], ncols = a.col_hi[iz] - clo + 1;
 #pragma unroll
     for (int h = 0; h < G::GPL; ++h)
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             int q;
             const int jx = G::perm_k(lane, h, d, q);
-            G2[jx] = v[h * 8 + d];
+            if (((jx - clo) & (MF - 1)) < ncols) G2[jx] = v[h * 8 + d];
         }
 }
 

@@ -212,6 +212,8 @@ struct Type2Args {
     const float* voxel_xy;   // [V][2]
     const int* row_lo;       // [Z] first fine row any voxel of the plane reaches (may be < 0)
     const int* row_hi;       // [Z] last such row
+    const int* col_lo;       // [Z] first fine column any voxel of the plane reaches (may be < 0)
+    const int* col_hi;       // [Z] last such column
     int max_vox;             // largest voxel count of a plane
     int first, last, coherent;
 };
