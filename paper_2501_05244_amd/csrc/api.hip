@@ -661,6 +661,8 @@ int run_srsd_points(nursd_plan* p, const float2* U, float2* V, float* I, char* w
             ca.tw_lb = p->tw(2 * p->M);
             ca.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
             ca.dec = p->d_decy;
+            ca.row_lo = p->d_row_lo;
+            ca.row_hi = p->d_row_hi;
             LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
             LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, ChirpArgs, launch_chirp_type2_cols, ca, s);
             Type2Args t = type2_args(p, g, Bt, U, V, I, ws, b0, nb);

@@ -296,6 +296,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     const float2* S1 = a.S1t + (size_t)p * M * N;
     float2* T2 = a.T2 + (size_t)p * M * MF;
+    const int lo = a.row_lo[iz], hi = a.row_hi[iz];     // fine rows the row pass reads
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int s = side ? ((M - kx) & (M - 1)) : kx;
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
             for (int d = 0; d < 8; ++d) {
                 int q;
                 const int jy = B::perm_k(lane, h, d, q);
-                T2[(size_t)s * MF + jy] = v[h * 8 + d];
+                if (type2_row_stored(jy, lo, hi, MF)) T2[(size_t)s * MF + jy] = v[h * 8 + d];
             }
     }
 }

@@ -26,7 +26,7 @@ __device__ __forceinline__ float es_w(float z, float beta) {
 }
 
 constexpr int kT2Waves = 8;
-constexpr int kT2RowWaves = 8;
+constexpr int kT2RowWaves = kType2RowBand;
 
 template <int M>
 __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
@@ -57,11 +57,9 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     const float2* Ub = a.U + (size_t)b * M * M;
     float2* T2 = a.T2 + (size_t)p * M * MF;
-    // only the fine rows the row pass reads are stored: kT2RowWaves-row bands
-    // from the first row any voxel of the plane reaches (periodic)
+    // only the fine rows the row pass reads are stored
     const int iz = a.g.z0 + p % a.g.nzc;
-    const int lo = a.row_lo[iz];
-    const int nrows = ((a.row_hi[iz] - lo) / kT2RowWaves + 1) * kT2RowWaves;
+    const int lo = a.row_lo[iz], hi = a.row_hi[iz];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
         const int s = side ? ((M - kx) & (M - 1)) : kx;
@@ -91,7 +89,7 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
             for (int d = 0; d < 8; ++d) {
                 int q;
                 const int jy = G::perm_k(lane, h, d, q);
-                if (((jy - lo) & (MF - 1)) < nrows) T2[(size_t)s * MF + jy] = v[h * 8 + d];
+                if (type2_row_stored(jy, lo, hi, MF)) T2[(size_t)s * MF + jy] = v[h * 8 + d];
             }
     }
 }

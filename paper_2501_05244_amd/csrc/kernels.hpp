@@ -185,6 +185,8 @@ struct ChirpArgs {
     const float2* tw_lb;    // twiddles of size 2M
     float2* T2;             // [planes][M][2M] (voxel-list output only)
     const float* dec;       // [M] (-1)^k / phihat(k), FFT order (voxel-list output only)
+    const int* row_lo;      // [Z] reachable fine rows of each plane (voxel-list output only)
+    const int* row_hi;
 };
 hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s);
 hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
@@ -193,6 +195,13 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
 hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- step 5 (voxel lists)
+// Fine rows the type-2 row pass transforms per block; the column passes store
+// T2 only in the bands of kType2RowBand rows from a plane's first reachable row.
+constexpr int kType2RowBand = 8;
+__device__ __forceinline__ bool type2_row_stored(int jy, int lo, int hi, int mf) {
+    const int nrows = ((hi - lo) / kType2RowBand + 1) * kType2RowBand;
+    return ((jy - lo) & (mf - 1)) < nrows;
+}
 struct Type2Args {
     ChunkGeom g;
     const float2* Bt;        // [planes][M/2+1][BS]
