@@ -241,8 +241,8 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     constexpr int RB = NW * LPW;
     constexpr int NPRE = M * RB / (NW * 64);     // tile values per thread
     static_assert(M * RB % (NW * 64) == 0, "tile must divide over the block");
-    extern __shared__ float2 sm[];      // [NW][SCRP], then twiddles [M]
-    float2* tws = sm + NW * SCRP;
+    extern __shared__ float2 sm[];      // two tiles [2][NW][SCRP], then twiddles [M]
+    float2* tws = sm + 2 * NW * SCRP;
     for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
     const int zl = by;
     const int iz = a.g.z0 + zl;
@@ -295,25 +295,36 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
         const int iy = iy0 + i % RB;
         pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
     }
-    float2* rows = sm + wave * SCRP;
-    for (int b = a.g.b0; b < b_end; ++b) {
-        __syncthreads();
+    // Two tiles alternate: while the waves transform their rows of frequency b
+    // (each wave uses its own row of the tile as FFT scratch), frequency b+1 is
+    // stored into the other tile and b+2 is loaded, with one barrier per step.
+    auto store_tile = [&](float2* tile) {
 #pragma unroll
         for (int r = 0; r < NPRE; ++r) {
             const int i = tid + r * NW * 64;
             const int s = i / RB, j = i % RB;
-            sm[(j / LPW) * SCRP + (j % LPW) * M + s] = pre[r];
+            tile[(j / LPW) * SCRP + (j % LPW) * M + s] = pre[r];
         }
-        __syncthreads();
-        if (b + 1 < b_end) {
-            Yb += fstride;
+    };
+    auto load_tile = [&]() {
+        Yb += fstride;
 #pragma unroll
-            for (int r = 0; r < NPRE; ++r) {
-                const int i = tid + r * NW * 64;
-                const int iy = iy0 + i % RB;
-                pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
-            }
+        for (int r = 0; r < NPRE; ++r) {
+            const int i = tid + r * NW * 64;
+            const int iy = iy0 + i % RB;
+            pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
         }
+    };
+    store_tile(sm);
+    if (a.g.b0 + 1 < b_end) load_tile();
+    for (int b = a.g.b0; b < b_end; ++b) {
+        __syncthreads();
+        float2* cur = sm + ((b - a.g.b0) & 1) * NW * SCRP;
+        if (b + 1 < b_end) {
+            store_tile(sm + ((b + 1 - a.g.b0) & 1) * NW * SCRP);
+            if (b + 2 < b_end) load_tile();
+        }
+        float2* rows = cur + wave * SCRP;
         float2 v[F::NV];
 #pragma unroll
         for (int q = 0; q < LPW; ++q)
@@ -383,7 +394,8 @@ __global__ __launch_bounds__(kP2Waves * 64, 6) void k_propagate_cols_grouped(Gro
 }
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
-    propagate_rows_body<M, HALF>(a, blockIdx.x, blockIdx.y);
+    const int v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    propagate_rows_body<M, HALF>(a, v % gridDim.x, v / gridDim.x);
 }
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows_grouped(Group<P3Args> g) {
@@ -466,12 +478,12 @@ hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
             constexpr int NW = (p3_waves<MM, true>());
             constexpr int RB = NW * F::LPW;
             return launch_rsd((k_propagate_rows<MM, true>), dim3((a.ny + RB - 1) / RB, a.g.nzc), NW * 64,
-                              (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
+                              (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s, a);
         }
         constexpr int NW = (p3_waves<MM, false>());
         constexpr int RB = NW * F::LPW;
         return launch_rsd((k_propagate_rows<MM, false>), dim3((a.ny + RB - 1) / RB, a.g.nzc), NW * 64,
-                          (size_t)(NW * SCRP + MM) * sizeof(float2), s, a);
+                          (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s, a);
     })
 }
 
@@ -498,11 +510,11 @@ hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& 
         if (half) {
             constexpr int NW = (p3_waves<MM, true>());
             return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64,
-                                  (size_t)(NW * SCRP + MM) * sizeof(float2), s);
+                                  (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
         }
         constexpr int NW = (p3_waves<MM, false>());
         return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64,
-                              (size_t)(NW * SCRP + MM) * sizeof(float2), s);
+                              (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
     })
 }
 
