@@ -171,8 +171,11 @@ int nursd_workspace_size(const nursd_plan* plan, size_t* bytes);
 void nursd_plan_destroy(nursd_plan* plan);
 
 /* Step 1 alone: temporal phasor transform (eq. PF_Response with the
- * band-pass of eq. PFPacket_Omega_Supp).  hist_dev: [L][T] float;
- * P_dev: [F][L] complex64 output. */
+ * band-pass of eq. PFPacket_Omega_Supp).  hist_dev: [L][T] float, 8-byte
+ * aligned (16-byte alignment with T = 2048 or 4096 takes the faster
+ * one-wavefront-per-histogram kernel); P_dev: [F][L] complex64 output.
+ * Errors: ARG (NULL or misaligned pointer), UNSUPPORTED_SIZE, HIP.  The same
+ * alignment rule holds for every entry point that takes histograms. */
 int nursd_phasor(nursd_plan* plan, const float* hist_dev, void* P_dev, void* stream);
 
 /* Steps 2-3 alone: type-1 NUFFT of P_dev ([F][L] complex64) onto the

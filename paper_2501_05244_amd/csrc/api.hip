@@ -1512,6 +1512,7 @@ void nursd_plan_destroy(nursd_plan* p) { delete p; }
 
 int nursd_phasor(nursd_plan* p, const float* hist, void* P, void* stream) {
     if (!p || !hist || !P) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (reinterpret_cast<uintptr_t>(hist) & 7) return fail(NURSD_ERR_ARG, "histograms must be 8-byte aligned");
     if (!is_pow2(p->T) || p->T < 256 || p->T > 8192)
         return fail(NURSD_ERR_UNSUPPORTED_SIZE, "T must be a power of two in [256, 8192]");
     PhasorArgs a{};
@@ -1843,6 +1844,7 @@ int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const*
     bool changed = false;
     for (int i = 0; i < n; ++i) {
         if (!hist[i] || !I[i]) return fail(NURSD_ERR_ARG, "NULL histogram or output pointer");
+        if (reinterpret_cast<uintptr_t>(hist[i]) & 7) return fail(NURSD_ERR_ARG, "histograms must be 8-byte aligned");
         if (hist[i] != bt->hist[i] || I[i] != bt->I[i]) changed = true;
         bt->hist[i] = hist[i];
         bt->I[i] = I[i];

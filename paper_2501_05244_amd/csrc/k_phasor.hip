@@ -4,13 +4,25 @@
 //   P[b][l] = w(f_b) e^{-j 2 pi f_b t0} sum_t H[l][t] e^{-j 2 pi b t / T}
 // (the phasor-field response of eq. PF_Response with the Gaussian
 // band-pass illumination of eq. PFPacket_Omega_Supp).  The real T-point
-// transform is computed as one T/2-point complex FFT of z[t] = h[2t] + j h[2t+1]
-// in LDS, then split: X[b] = E[b] + e^{-j 2 pi b/T} O[b] with
+// transform is one T/2-point complex transform Z of z[t] = h[2t] + j h[2t+1],
+// split as X[b] = E[b] + e^{-j 2 pi b/T} O[b] with
 // E = (Z[b] + conj Z[T/2-b]) / 2 and O = (Z[b] - conj Z[T/2-b]) / (2j).
 // HBM-bound: each histogram is read once, F values written per sample.
+//
+// For T = 2048 and 4096 one wavefront transforms one histogram at a time in
+// registers: Z is split once more into the N = T/4-point transforms A of the
+// even and B of the odd z samples (Z[n] = A[n mod N] + W_{T/2}^n B[n mod N]),
+// each a register-resident wave FFT, and the next histogram's loads are in
+// flight meanwhile.  Since X is linear in Z[b] and conj Z[T/2-b],
+//   X[b] = (al A[b] + be conj A[-b]) + W_{T/2}^b (al B[b] + be conj B[-b])
+// with al = (1 - j t_b) / 2, be = (1 + j t_b) / 2, t_b = e^{-j 2 pi b/T} and
+// indices mod N, so the A and B halves are gathered one after the other
+// through the same LDS scratch.  Other T (and histograms that are not
+// 16-byte aligned) use a block-level LDS transform per histogram.
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "persistent.hpp"
+#include "wavefft.hpp"
 
 namespace nursd {
 
@@ -50,13 +62,132 @@ __device__ __forceinline__ void phasor_body(const PhasorArgs& a, int bx) {
     }
 }
 
+constexpr int kPhasorWaves = kPhasorThreads / 64;
+
+// LDS of the wavefront variant: twiddles [N], staged outputs [F][group],
+// per-wave scratch.
+template <int TH>
+constexpr size_t phasor_wave_lds(int F) {
+    return (size_t)(TH / 2 + F * kPhasorGroup + kPhasorWaves * WaveFFT<TH / 2>::SCR) * sizeof(float2);
+}
+
+template <int TH>
+__device__ __forceinline__ void phasor_wave_body(const PhasorArgs& a, int bx) {
+    constexpr int N = TH / 2;
+    using W = WaveFFT<N>;
+    static_assert(W::LPW == 1, "one transform per wavefront");
+    constexpr int E = W::E;
+    extern __shared__ float2 smem[];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    float2* tws = smem;                                      // [N]
+    float2* out = smem + N;                                  // [F][kPhasorGroup]
+    float2* scr = out + a.F * kPhasorGroup + wave * W::SCR;  // this wave's scratch
+    for (int i = tid; i < N; i += kPhasorThreads) tws[i] = a.tw[2 * i];
+    __syncthreads();
+    const int l0 = bx * kPhasorGroup;
+    const int nr = min(kPhasorGroup, a.L - l0);
+    // histogram r of the group -> z[2m], z[2m+1] for m = lane + 64 e
+    float4 pre[E];
+    auto load = [&](int r) {
+        const float4* row = reinterpret_cast<const float4*>(a.hist + (size_t)(l0 + r) * a.T);
+#pragma unroll
+        for (int e = 0; e < E; ++e) pre[e] = row[lane + 64 * e];
+    };
+    // spectrum half h (0: A, 1: B) gathered into the staged outputs of r
+    auto gather = [&](int half, int r) {
+        for (int j = lane; j < a.F; j += 64) {
+            const int b = a.bins[j];
+            const float2 t = a.tb[j];
+            const float2 u1 = scr[b & (N - 1)];
+            const float2 u2 = cconj(scr[(N - b) & (N - 1)]);
+            // al u1 + be u2 with al = (1 - j t)/2, be = (1 + j t)/2
+            const float2 jt = make_float2(-t.y, t.x);
+            float2 x = cscale(cadd(cadd(u1, u2), cmul(jt, csub(u2, u1))), 0.5f);
+            x = cmul(a.wt[j], x);
+            if (half == 0) {
+                out[j * kPhasorGroup + r] = x;
+            } else {
+                const float2 w2 = cmul(t, t);                   // W_{T/2}^b
+                out[j * kPhasorGroup + r] = cadd(out[j * kPhasorGroup + r], cmul(w2, x));
+            }
+        }
+    };
+    // natural-order spectrum of a wave FFT into the scratch
+    auto spill = [&](const float2* v) {
+#pragma unroll
+        for (int h = 0; h < W::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                scr[W::perm_k(lane, h, d, q)] = v[h * 8 + d];
+            }
+    };
+    int r = wave;
+    if (r < nr) load(r);
+    for (; r < nr; r += kPhasorWaves) {                      // wave-uniform
+        float2 va[E], vb[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            va[e] = make_float2(pre[e].x, pre[e].y);
+            vb[e] = make_float2(pre[e].z, pre[e].w);
+        }
+        if (r + kPhasorWaves < nr) load(r + kPhasorWaves);
+        W::template nat_to_perm<false>(va, scr, tws, lane);
+        spill(va);
+        NURSD_WAVE_SYNC();
+        gather(0, r);
+        NURSD_WAVE_SYNC();
+        W::template nat_to_perm<false>(vb, scr, tws, lane);
+        spill(vb);
+        NURSD_WAVE_SYNC();
+        gather(1, r);
+        NURSD_WAVE_SYNC();
+    }
+    __syncthreads();
+    for (int i = tid; i < a.F * kPhasorGroup; i += kPhasorThreads) {
+        const int j = i / kPhasorGroup, rr = i % kPhasorGroup;
+        if (rr < nr) a.P[(size_t)j * a.L + l0 + rr] = out[i];
+    }
+}
+
+// The wavefront variant needs rows of whole float4 (T of 2048 or 4096 and a
+// 16-byte aligned histogram).
+template <int TH>
+__device__ __forceinline__ bool phasor_wave_ok(const PhasorArgs& a) {
+    return TH >= 1024 && TH <= 2048 && (reinterpret_cast<uintptr_t>(a.hist) & 15) == 0;
+}
+
 template <int TH>
 __global__ __launch_bounds__(kPhasorThreads) void k_phasor(PhasorArgs a) {
+    if constexpr (TH >= 1024 && TH <= 2048) {
+        if (phasor_wave_ok<TH>(a)) {
+            phasor_wave_body<TH>(a, blockIdx.x);
+            return;
+        }
+    }
     phasor_body<TH>(a, blockIdx.x);
 }
 template <int TH>
 __global__ __launch_bounds__(kPhasorThreads) void k_phasor_grouped(Group<PhasorArgs> g) {
-    persistent_loop(g, [](const PhasorArgs& a, int bx, int) { phasor_body<TH>(a, bx); });
+    persistent_loop(g, [](const PhasorArgs& a, int bx, int) {
+        if constexpr (TH >= 1024 && TH <= 2048) {
+            if (phasor_wave_ok<TH>(a)) {
+                phasor_wave_body<TH>(a, bx);
+                return;
+            }
+        }
+        phasor_body<TH>(a, bx);
+    });
+}
+
+template <int TH>
+static size_t phasor_lds(int F) {
+    const size_t blockwise = (size_t)(TH + F * kPhasorGroup) * sizeof(float2);
+    if constexpr (TH >= 1024 && TH <= 2048) {
+        const size_t wave = phasor_wave_lds<TH>(F);
+        return wave > blockwise ? wave : blockwise;
+    }
+    return blockwise;
 }
 
 
@@ -85,17 +216,18 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
 hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s) {
     const int TH = a.T / 2;
     dim3 grid((a.L + kPhasorGroup - 1) / kPhasorGroup);
-    size_t sh = (size_t)(TH + a.F * kPhasorGroup) * sizeof(float2);
     switch (TH) {
 #define NURSD_PH(n)                                                                          \
-    case n:                                                                                  \
+    case n: {                                                                                \
+        const size_t sh = phasor_lds<n>(a.F);                                                \
         if (sh > 65536) {                                                                    \
             hipError_t e = hipFuncSetAttribute((const void*)k_phasor<n>,                     \
                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh); \
             if (e != hipSuccess) return e;                                                   \
         }                                                                                    \
         hipLaunchKernelGGL(k_phasor<n>, grid, dim3(kPhasorThreads), sh, s, a);               \
-        break;
+        break;                                                                               \
+    }
         NURSD_PH(128) NURSD_PH(256) NURSD_PH(512) NURSD_PH(1024) NURSD_PH(2048) NURSD_PH(4096)
 #undef NURSD_PH
         default: return hipErrorInvalidValue;
@@ -104,10 +236,9 @@ hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_phasor_grouped(int T, int F_max, const Group<PhasorArgs>& g, hipStream_t s) {
-    const size_t sh = (size_t)(T / 2 + F_max * kPhasorGroup) * sizeof(float2);
     switch (T / 2) {
 #define NURSD_PG(n) \
-    case n: return launch_grouped(k_phasor_grouped<n>, g, kPhasorThreads, sh, s);
+    case n: return launch_grouped(k_phasor_grouped<n>, g, kPhasorThreads, phasor_lds<n>(F_max), s);
         NURSD_PG(128) NURSD_PG(256) NURSD_PG(512) NURSD_PG(1024) NURSD_PG(2048) NURSD_PG(4096)
 #undef NURSD_PG
         default: return hipErrorInvalidValue;

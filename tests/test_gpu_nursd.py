@@ -53,6 +53,39 @@ def test_phasor_tiny(device, tiny):
     assert rel(P, Pref) < 2e-6
 
 
+@pytest.mark.parametrize("T,F,offset", [(2048, 37, 0), (4096, 130, 0), (2048, 16, 2)])
+def test_phasor_wavefront_ragged(device, T, F, offset):
+    """Phasor stage at T = 2048 and 4096 (one wavefront per histogram), with
+    a relay count that leaves a partial group of 16 and F above 128; offset 2
+    floats starts the rows on an 8-byte (not 16-byte) boundary, which takes
+    the block-level transform instead."""
+    print(f"case: phasor T={T} F={F} offset={offset}", flush=True)
+    w = scenes.config_tiny(render=False)
+    L = 1000
+    w.relay_xy = w.relay_xy[:L]
+    w.wavelet.n_time = T
+    w.wavelet.dt = 4e-12
+    w.wavelet.n_freq = F
+    w.wavelet.t0 = 1.3e-9
+    rng = np.random.default_rng(7)
+    hist = rng.poisson(3.0, size=(L, T)).astype(np.float32)
+    plan = plan_for(w, device)
+    buf = torch.zeros(offset + L * T, dtype=torch.float32, device=device)
+    buf[offset:] = torch.from_numpy(hist.ravel()).to(device)
+    P = plan.phasor(buf[offset:].view(L, T)).cpu().numpy()
+    Pref, _ = o.phasors_from_workload(w, hist)
+    assert rel(P, Pref) < 2e-6
+
+
+def test_phasor_rejects_misaligned_histograms(device, tiny):
+    """A histogram pointer off an 8-byte boundary is refused on the host."""
+    plan = plan_for(tiny, device)
+    L, T = tiny.hist.shape
+    buf = torch.zeros(1 + L * T, dtype=torch.float32, device=device)
+    with pytest.raises(RuntimeError, match="aligned"):
+        plan.phasor(buf[1:].view(L, T))
+
+
 def test_spectrum_tiny(device, tiny):
     print("case: spectrum tiny", flush=True)
     plan = plan_for(tiny, device)
