@@ -129,6 +129,7 @@ struct nursd_plan {
     double* d_py = nullptr;
     double* d_alpha = nullptr;
     float2* d_hhat = nullptr; // [Z][2M] chirp spectra (SRSD)
+    float2* d_chirp = nullptr; // [Z][M] chirps e^{-j pi alpha m^2 / M} (SRSD)
     float* d_relay = nullptr;     // [L][2] plan-owned copy of the relay positions
     int relay_row_lo = 0, relay_row_hi = -1;
     int FC3 = 4;                  // frequencies per adjoint type-2 chunk
@@ -557,6 +558,7 @@ int run_srsd(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipS
             ca.ny = p->ny;
             ca.alpha = p->d_alpha;
             ca.hhat = p->d_hhat;
+            ca.chirp = p->d_chirp;
             ca.tw_m = p->tw(p->M);
             ca.tw_lb = p->tw(2 * p->M);
             LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
@@ -657,6 +659,7 @@ int run_srsd_points(nursd_plan* p, const float2* U, float2* V, float* I, char* w
             ca.ny = p->ny;
             ca.alpha = p->d_alpha;
             ca.hhat = p->d_hhat;
+            ca.chirp = p->d_chirp;
             ca.tw_m = p->tw(p->M);
             ca.tw_lb = p->tw(2 * p->M);
             ca.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
@@ -1448,6 +1451,16 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
                                                           (float)(line[k].imag() / ((double)LB * M)));
             }
             if ((rc = upload(p, hh, &p->d_hhat))) return bail(rc);
+            // the chirp itself, c[j] = e^{-j pi alpha m^2 / M} at m = j - M/2
+            std::vector<float2> cz((size_t)p->nz * M);
+            for (int iz = 0; iz < p->nz; ++iz)
+                for (int j = 0; j < M; ++j) {
+                    const double m = (double)(j - M / 2);
+                    const double cyc = std::fmod(p->alpha[iz] * m * m / (2.0 * M), 1.0);
+                    cz[(size_t)iz * M + j] = make_float2((float)std::cos(2.0 * M_PI * cyc),
+                                                         (float)-std::sin(2.0 * M_PI * cyc));
+                }
+            if ((rc = upload(p, cz, &p->d_chirp))) return bail(rc);
         }
     }
     {
@@ -1633,6 +1646,7 @@ int nursd_forward_video(nursd_plan* p, const void* P, int32_t n_frames, double t
                 ca.ny = p->ny;
                 ca.alpha = p->d_alpha;
                 ca.hhat = p->d_hhat;
+                ca.chirp = p->d_chirp;
                 ca.tw_m = p->tw(p->M);
                 ca.tw_lb = p->tw(2 * p->M);
                 LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);

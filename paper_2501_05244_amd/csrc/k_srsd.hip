@@ -12,28 +12,22 @@
 //   alpha k n = alpha/2 (k^2 + n^2 - (k - n)^2):
 //   S[k] = e^{-j pi alpha k^2/M} sum_n (u[n] e^{-j pi alpha n^2/M}) e^{+j pi alpha (k-n)^2/M},
 // a linear convolution done with FFTs of length LB = 2M >= M + N - 1 against
-// the precomputed spectrum of the chirp (one table per plane).  Chirp phase
-// arguments are reduced in FP64 before the FP32 sin/cos.
-//   k_chirp_rows: Bluestein along x for each of the N rows; store transposed
+// the precomputed spectrum of the chirp.  Both are per-plane tables built on
+// the host from FP64 arguments: the chirp c[m] = e^{-j pi alpha m^2 / M} for
+// m in [-M/2, M/2) (the input chirp of n in I_N is c[n]) and its spectrum.
+//   k_chirp_rows: Bluestein along x for each of the N rows, times the input
+//                 chirp of the y pass (one value per row); store transposed
 //                 S1t[p][kx][iy].
-//   k_chirp_cols: Bluestein along y for kx and -kx, multiply by the DCT of the
-//                 kernel sampled at pitch d/alpha (finished from k_kernel_rows
-//                 output, even in kx), inverse FFT along y, keep the window.
+//   k_chirp_cols: Bluestein along y for kx and -kx; the output chirp is
+//                 folded into the DCT of the kernel sampled at pitch d/alpha
+//                 (finished from k_kernel_rows output, even in kx), which both
+//                 columns multiply; inverse FFT along y, keep the window.
 // The x pass of the inverse transform and the volume formation are the
 // uniform-grid k_propagate_rows with per-plane voxel pitch d/alpha.
 #include "kernels.hpp"
 #include "wavefft.hpp"
 
 namespace nursd {
-
-// e^{-j pi alpha n^2 / M} (sgn = -1) or e^{+...} (sgn = +1); FP64 reduction.
-__device__ __forceinline__ float2 chirp(int n, double alpha_over_2M, float sgn) {
-    const double cyc = alpha_over_2M * (double)((long long)n * n);
-    const float fr = (float)(cyc - rint(cyc));
-    float s, c;
-    sincos_cycles(fr, &s, &c);
-    return make_float2(c, sgn * s);
-}
 
 constexpr int kGridWaves = 8;
 
@@ -152,15 +146,16 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     const int N = a.N;
     const int iy0 = blockIdx.x * kChirpWaves;
     const int iy = iy0 + wave;
-    const double ahm = a.alpha[iz] / (2.0 * M);
     const float2* hhat = a.hhat + (size_t)iz * LB;
+    const float2* cz = a.chirp + (size_t)iz * M;          // c[m] at m + M/2
+    const int D = M / 2 - N / 2;                           // c of n - N/2 at n + D
     const float2* urow = a.u + ((size_t)b * N + (iy < N ? iy : 0)) * N;
     float2 v[B::NV];
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
         const int n = lane + 64 * e;
         v[e] = make_float2(0.f, 0.f);
-        if (iy < N && n < N) v[e] = cmul(urow[n], chirp(n - N / 2, ahm, -1.f));
+        if (iy < N && n < N) v[e] = cmul(urow[n], cz[n + D]);
     }
     float2* scr = sm + wave * SCRP;
     bluestein_line<M>(v, scr, tws, hhat, lane);
@@ -168,11 +163,12 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     // in the block's staging rows (they overlap other waves' scratch: barrier)
     __syncthreads();
     float2* stage = sm + wave * MP;
+    const float2 cy = cz[(iy < N ? iy : 0) + D];             // input chirp of the y pass
 #pragma unroll
     for (int e = 0; e < M / 64; ++e) {
         const int kp = lane + 64 * e;
         const int k = kp - M / 2;
-        stage[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+        stage[(k + M) & (M - 1)] = cmul(cmul(v[e], cz[kp]), cy);
     }
     __syncthreads();
     float2* S1 = a.S1t + (size_t)p * M * N;
@@ -202,7 +198,6 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
     const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;
     const int N = a.N;
-    const double ahm = a.alpha[iz] / (2.0 * M);
     const float2* hhat = a.hhat + (size_t)iz * LB;
     float2* scr = sm + wave * SCRP;
     // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows
@@ -214,6 +209,16 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
         g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
     }
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
+    // fold the output chirp c[ky] into the kernel line
+    const float2* cz = a.chirp + (size_t)iz * M;
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            g[h * 8 + d] = cmul(g[h * 8 + d], cz[(k + M / 2) & (M - 1)]);
+        }
     const float2* S1 = a.S1t + (size_t)p * M * N;
     float2* Yp = a.Yt + (size_t)p * M * a.ny;
     const int half = a.ny / 2;
@@ -226,15 +231,15 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
         for (int e = 0; e < EB; ++e) {
             const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = cmul(S1[(size_t)s * N + n], chirp(n - N / 2, ahm, -1.f));
+            if (n < N) v[e] = S1[(size_t)s * N + n];
         }
         bluestein_line<M>(v, scr, tws_lb, hhat, lane);
-        // scaled spectrum column S[s][ky] (natural), staged to LDS in FFT order
+        // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
         NURSD_WAVE_SYNC();
 #pragma unroll
         for (int e = 0; e < M / 64; ++e) {
             const int k = lane + 64 * e - M / 2;
-            scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+            scr[(k + M) & (M - 1)] = v[e];
         }
         NURSD_WAVE_SYNC();
         float2 x[F::NV];
@@ -283,7 +288,6 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
     const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;                      // wave-uniform; no block barriers below
     const int N = a.N;
-    const double ahm = a.alpha[iz] / (2.0 * M);
     const float2* hhat = a.hhat + (size_t)iz * LB;
     float2* scr = sm + wave * SCRP;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
@@ -294,6 +298,16 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
         g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
     }
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
+    // fold the output chirp c[ky] into the kernel line
+    const float2* cz = a.chirp + (size_t)iz * M;
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            g[h * 8 + d] = cmul(g[h * 8 + d], cz[(k + M / 2) & (M - 1)]);
+        }
     const float2* S1 = a.S1t + (size_t)p * M * N;
     float2* T2 = a.T2 + (size_t)p * M * MF;
     const int lo = a.row_lo[iz], hi = a.row_hi[iz];     // fine rows the row pass reads
@@ -306,15 +320,15 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
         for (int e = 0; e < EB; ++e) {
             const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = cmul(S1[(size_t)s * N + n], chirp(n - N / 2, ahm, -1.f));
+            if (n < N) v[e] = S1[(size_t)s * N + n];
         }
         bluestein_line<M>(v, scr, tws_lb, hhat, lane);
-        // scaled spectrum column S[s][ky] (natural), staged to LDS in FFT order
+        // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
         NURSD_WAVE_SYNC();
 #pragma unroll
         for (int e = 0; e < M / 64; ++e) {
             const int k = lane + 64 * e - M / 2;
-            scr[(k + M) & (M - 1)] = cmul(v[e], chirp(k, ahm, -1.f));
+            scr[(k + M) & (M - 1)] = v[e];
         }
         NURSD_WAVE_SYNC();
         const float dxs = a.dec[s];

@@ -181,6 +181,7 @@ struct ChirpArgs {
     int M, N, BS, ny;
     const double* alpha;    // [Z]
     const float2* hhat;     // [Z][2M] chirp spectra / (2M * M)
+    const float2* chirp;    // [Z][M] e^{-j pi alpha m^2 / M}, m = j - M/2
     const float2* tw_m;     // twiddles of size M
     const float2* tw_lb;    // twiddles of size 2M
     float2* T2;             // [planes][M][2M] (voxel-list output only)
