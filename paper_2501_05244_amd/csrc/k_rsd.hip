@@ -372,16 +372,9 @@ template <int M>
 __global__ __launch_bounds__(kP1Waves * 64, (M >= 1024 ? 4 : 8)) void k_kernel_rows_grouped(Group<P1Args> g) {
     persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M>(a, bx, by); });
 }
-// Workgroups are handed to the 8 XCDs round-robin by linear id.  The column
-// pass renumbers them so that each XCD works through a contiguous run of
-// (plane, kx block) work items: the planes of one frequency share its
-// spectrum U, which then stays in that XCD's L2.
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_contiguous(int lin, int total) {
-    const int x = lin % kXcds, k = lin / kXcds;
-    const int start = x * (total / kXcds) + min(x, total % kXcds);
-    return start + k;
-}
+// The column pass renumbers its workgroups (xcd_contiguous) so that each XCD
+// works through a contiguous run of (plane, kx block) work items: the planes
+// of one frequency share its spectrum U, which then stays in that XCD's L2.
 
 template <int M>
 __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {

@@ -125,9 +125,10 @@ __device__ __forceinline__ void bluestein_line(float2* v, float2* scr, const flo
 // Row pass: 8 rows per block (8 adjacent columns per store of the transposed
 // output); 80 KB of LDS per block at M = 512, so two blocks share a CU.
 constexpr int kChirpWaves = 8;
-// Column passes: one Bluestein line per wave, no block-level exchange (6
-// waves per block, which lets two blocks share a CU, measured slower).
-constexpr int kChirpColWaves = 8;
+// Column passes: one Bluestein line per wave, no block-level exchange.  Four
+// waves per block (49 KB of LDS at M = 512) and at most 168 VGPRs let three
+// blocks share a CU, three waves per SIMD.
+constexpr int kChirpColWaves = 4;
 
 template <int M>
 __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
@@ -140,11 +141,14 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     float2* tws = sm + kChirpWaves * SCRP;
     for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws[i] = a.tw_lb[i];
     __syncthreads();
-    const int p = blockIdx.y;
+    // neighbouring row blocks (which share the cache lines of the transposed
+    // store) run on the same XCD
+    const int item = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int p = item / gridDim.x;
     const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int N = a.N;
-    const int iy0 = blockIdx.x * kChirpWaves;
+    const int iy0 = (item % gridDim.x) * kChirpWaves;
     const int iy = iy0 + wave;
     const float2* hhat = a.hhat + (size_t)iz * LB;
     const float2* cz = a.chirp + (size_t)iz * M;          // c[m] at m + M/2
@@ -179,7 +183,7 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
 }
 
 template <int M>
-__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 3, 8))) void k_chirp_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
     constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E;
@@ -269,7 +273,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
 // -> T2[p][s][jy].  The oversampled line has the Bluestein length 2M, so it
 // shares that transform's twiddles and scratch.
 template <int M>
-__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 3, 8))) void k_chirp_type2_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
     constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E, MF = 2 * M;
