@@ -25,7 +25,7 @@ __device__ __forceinline__ float es_w(float z, float beta) {
     return __expf(beta * (sqrtf(t) - 1.0f));
 }
 
-constexpr int kT2Waves = 8;
+constexpr int kT2Waves = 4;
 constexpr int kT2RowWaves = kType2RowBand;
 
 template <int M>
@@ -98,10 +98,14 @@ template <int M>
 __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
     using G = WaveFFT<2 * M>;
     constexpr int H = M / 2, MF = 2 * M, EG = G::E;
-    constexpr int SCRP = (G::SCR > MF ? G::SCR : MF) + 1;
+    constexpr int TP = M + 1;               // tile row: the M data values of a line
     constexpr int RB = kT2RowWaves;
-    extern __shared__ float2 sm[];          // [RB][SCRP], twiddles MF
-    float2* tws = sm + RB * SCRP;
+    static_assert(TP <= G::SCR && H % 64 == 0, "tile layout");
+    // The block's RB rows are staged compactly (the zero padding is never
+    // stored), read into registers, and the tile is then reused as the waves'
+    // FFT scratch: 80 KB at M = 512, so two blocks share a CU.
+    extern __shared__ float2 sm[];          // tile [RB][TP] / scratch [RB][SCR], twiddles MF
+    float2* tws = sm + RB * G::SCR;
     for (int i = threadIdx.x; i < MF; i += kT2RowWaves * 64) tws[i] = a.tw_f[i];
     const int p = blockIdx.y;
     const int iz = a.g.z0 + p % a.g.nzc;
@@ -112,19 +116,21 @@ __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
     for (int i = threadIdx.x; i < M * RB; i += kT2RowWaves * 64) {
         const int kx = i / RB, j = i % RB;
         const int jy = (jy0 + j) & (MF - 1);
-        const int kf = kx < H ? kx : kx + (MF - M);
-        sm[j * SCRP + kf] = T2[(size_t)kx * MF + jy];
-    }
-    for (int i = threadIdx.x; i < (MF - M) * RB; i += kT2RowWaves * 64) {
-        const int kk = i / RB, j = i % RB;
-        sm[j * SCRP + H + kk] = make_float2(0.f, 0.f);
+        sm[j * TP + kx] = T2[(size_t)kx * MF + jy];
     }
     __syncthreads();
-    float2* row = sm + wave * SCRP;
+    // natural zero-padded line: kx < H at n = kx, kx >= H at n = kx + MF - M
     float2 v[G::NV];
 #pragma unroll
-    for (int e = 0; e < EG; ++e) v[e] = row[lane + 64 * e];
-    G::template nat_to_perm<true>(v, row, tws, lane);
+    for (int e = 0; e < EG; ++e) {
+        const int n = lane + 64 * e;
+        if (64 * e < H) v[e] = sm[wave * TP + n];
+        else if (64 * e >= MF - H) v[e] = sm[wave * TP + n - (MF - M)];
+        else v[e] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();                        // all rows read: the tile becomes scratch
+    float2* scr = sm + wave * G::SCR;
+    G::template nat_to_perm<true>(v, scr, tws, lane);
     const int jy = (jy0 + wave) & (MF - 1);
     float2* G2 = a.G2 + ((size_t)p * MF + jy) * MF;
     // only the fine columns some voxel of the plane reaches are stored
@@ -243,9 +249,8 @@ template <int M>
 static hipError_t type2_fine_impl(const Type2Args& a, hipStream_t s) {
     using G = WaveFFT<2 * M>;
     const int planes = a.g.nb * a.g.nzc;
-    constexpr int SCRP = (G::SCR > 2 * M ? G::SCR : 2 * M) + 1;
     hipError_t e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes),
-                             kT2RowWaves * 64, (size_t)(kT2RowWaves * SCRP + 2 * M) * sizeof(float2), s, a);
+                             kT2RowWaves * 64, (size_t)(kT2RowWaves * G::SCR + 2 * M) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
     return launch_t2(k_type2_interp, dim3((a.max_vox + kInterpThreads - 1) / kInterpThreads, a.g.nzc),
                      kInterpThreads, 0, s, a);
