@@ -287,18 +287,33 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
     }
     for (int b = 0; b < p->nbands; ++b) ptr[b + 1] += ptr[b];
     p->n_ent = (int)out.size();
-    // entry range of each spreading wave: taps of entry e reach columns
-    // ix0 .. ix0 + w - 1, so wave columns [c_lo, c_hi) need ix0 in [c_lo - w + 1, c_hi)
-    std::vector<int> rng((size_t)p->nbands * kSpreadWaves * 2);
-    const int cols = Mf / kSpreadWaves;
+    // Column range and entry range of each spreading wave.  The columns of a
+    // band are split where the band's entries (sorted by ix0) reach equal
+    // counts, so that all waves of a workgroup walk about as many samples
+    // (relays usually cover only part of the period).  Taps of entry e reach
+    // columns ix0 .. ix0 + w - 1, so wave columns [c_lo, c_hi) need ix0 in
+    // [c_lo - w + 1, c_hi).
+    std::vector<int> rng((size_t)p->nbands * kSpreadWaves * 4);
     for (int b = 0; b < p->nbands; ++b) {
         auto first = ents.begin() + ptr[b], last = ents.begin() + ptr[b + 1];
+        const long n = last - first;
+        int bound[kSpreadWaves + 1];
+        bound[0] = 0;
+        bound[kSpreadWaves] = Mf;
+        for (int wv = 1; wv < kSpreadWaves; ++wv) {
+            int c = n > 0 ? (first + (n * wv) / kSpreadWaves)->ix0 : (wv * Mf) / kSpreadWaves;
+            c = std::min(std::max(c, bound[wv - 1]), Mf);
+            bound[wv] = c;
+        }
         for (int wv = 0; wv < kSpreadWaves; ++wv) {
-            const int lo = wv * cols - w + 1, hi = (wv + 1) * cols;
+            const int lo = bound[wv] - w + 1, hi = bound[wv + 1];
             auto a = std::lower_bound(first, last, lo, [](const E& e, int v) { return e.ix0 < v; });
             auto c = std::lower_bound(first, last, hi, [](const E& e, int v) { return e.ix0 < v; });
-            rng[((size_t)b * kSpreadWaves + wv) * 2] = (int)(a - ents.begin());
-            rng[((size_t)b * kSpreadWaves + wv) * 2 + 1] = (int)(c - ents.begin());
+            int* r = &rng[((size_t)b * kSpreadWaves + wv) * 4];
+            r[0] = (int)(a - ents.begin());
+            r[1] = (int)(c - ents.begin());
+            r[2] = bound[wv];
+            r[3] = bound[wv + 1];
         }
     }
     if (p->d_ent) {

@@ -8,8 +8,8 @@
 // k_spread_xfft: one workgroup owns a band of kBandRows fine rows (all Mf
 // columns) of spread_freqs frequencies in LDS (the kernel weights of a sample
 // are computed once for all of them).  Relay samples are pre-binned per band
-// and sorted by x; each wavefront owns a disjoint range of columns and walks
-// the samples overlapping it, one sample per step with one lane per kernel
+// and sorted by x; each wavefront owns a disjoint range of columns (split so
+// the waves' sample counts balance) and walks the samples overlapping it, one sample per step with one lane per kernel
 // tap, so every LDS cell is updated by one wave in a fixed order: no atomics,
 // bitwise reproducible.  The band is then FFT'd along x in LDS and only the
 // M kept modes are written, scaled by the x deconvolution factor.
@@ -62,16 +62,15 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     for (int i = tid; i < NF * kBandRows * LDT; i += kSpreadThreads) tile[i] = make_float2(0.f, 0.f);
     __syncthreads();
 
-    constexpr int kCols = MF / kSpreadWaves;          // columns owned by one wave
     static_assert(kSpreadThreads == kSpreadWaves * 64, "one wave per column range");
     const int wave = tid >> 6, lane = tid & 63;
-    const int c_lo = wave * kCols, c_hi = c_lo + kCols;
+    const int* rng = a.wave_rng + (band * kSpreadWaves + wave) * 4;
+    const int c_lo = rng[2], c_hi = rng[3];             // columns owned by this wave
     const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
     const float inv_hw = 1.0f / a.half_w;
     const float bl2e = a.beta * 1.4426950408889634f;
     const int w = a.w;
-    const int s0 = a.wave_rng[(band * kSpreadWaves + wave) * 2];
-    const int s1 = a.wave_rng[(band * kSpreadWaves + wave) * 2 + 1];
+    const int s0 = rng[0], s1 = rng[1];
     const float2* Pb = a.P + (size_t)fa * a.L;
     const bool tap_ok = ti < w && tj < w;
     // 64 entries per round trip: each lane fetches one entry and its phasors,

@@ -27,8 +27,9 @@ constexpr int spread_band_rows(int) { return 8; }
 // Frequencies spread by one workgroup: the kernel weights of a sample are
 // computed once and applied to each of them (one LDS tile per frequency).
 constexpr int spread_freqs(int Mf) { return Mf <= 1024 ? 2 : 1; }
-// Wavefronts per spreading workgroup; wave w owns fine columns
-// [w * Mf / kSpreadWaves, (w + 1) * Mf / kSpreadWaves).
+// Wavefronts per spreading workgroup; each owns a contiguous range of fine
+// columns of the band (chosen on the host so the waves walk similar numbers
+// of samples).
 constexpr int kSpreadWaves = 16;
 
 struct TwTables {
@@ -52,7 +53,7 @@ struct SpreadArgs {
     const float2* P;              // [F][L] (frequency-major)
     const SpreadEntry* ent;       // entries sorted by band, then u
     const int* band_ptr;          // [nbands + 1]
-    const int* wave_rng;          // [nbands][kSpreadWaves][2]: entry range of each wave's columns
+    const int* wave_rng;          // [nbands][kSpreadWaves][4]: entry range, then column range, of each wave
     float2* T1;                   // [Fc][M][Mf]: x-transformed bands, kx row-major
     const float* decx;            // [M] (-1)^kx / (phihat(kx) M^2), FFT order
     const float2* tw;             // twiddles of size Mf
