@@ -14,7 +14,8 @@
 //   k_type2_interp: per voxel, w x w gather from the fine grid of every
 //                 frequency of the chunk, illumination phase (advanced by a
 //                 per-voxel step factor over the evenly spaced frequencies of
-//                 the chunk), accumulation.
+//                 the chunk), accumulation; the frequencies are split over the
+//                 waves of a workgroup and their partial sums added in LDS.
 #include "kernels.hpp"
 #include "wavefft.hpp"
 
@@ -151,87 +152,103 @@ __device__ __forceinline__ double dist3d(double x, double y, double z) {
     return sqrt_f64(d2, &inv);
 }
 
-constexpr int kInterpThreads = 256;
+// One workgroup per 64 voxels of a plane; its kInterpWaves waves split the
+// chunk's frequencies (wave w takes b0 + w, b0 + w + kInterpWaves, ...), so a
+// launch has kInterpWaves times as many waves as voxel groups, and the partial
+// sums meet in LDS, added in wave order (bitwise reproducible).  Two waves
+// measured best: more of them gather from more fine grids at once.
+constexpr int kInterpWaves = 2;
 
-__global__ __launch_bounds__(kInterpThreads) void k_type2_interp(Type2Args a) {
+__global__ __launch_bounds__(kInterpWaves * 64) void k_type2_interp(Type2Args a) {
+    __shared__ float2 part[kInterpWaves][64];
     const int zl = blockIdx.y;
     const int iz = a.g.z0 + zl;
-    const int v = a.plane_ptr[iz] + blockIdx.x * kInterpThreads + threadIdx.x;
-    if (v >= a.plane_ptr[iz + 1]) return;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int v = a.plane_ptr[iz] + blockIdx.x * 64 + lane;
+    const bool live = v < a.plane_ptr[iz + 1];
     const int MF = a.Mf;
-    const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
-    const double z = a.g.z[iz];
-    const double hw = 0.5 * a.w;
-    // plane pitch: the frame pitch, or dx / alpha on a scaled plane
-    const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
-    const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
-    const double tx = (x - a.cx) / px * 2.0 + MF / 2;
-    const double ty = (y - a.cy) / py * 2.0 + MF / 2;
-    const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
-    const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
-    const float ihw = (float)(1.0 / hw);
-    float wx[8], wy[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        wx[i] = i < a.w ? es_w(((float)i - fx) * ihw, a.beta) : 0.f;
-        wy[i] = i < a.w ? es_w(((float)i - fy) * ihw, a.beta) : 0.f;
-    }
-    const double dd = dist3d(x - a.xp0, y - a.xp1, z - a.xp2);
     float2 acc = make_float2(0.f, 0.f);
-    if (!a.first) {
-        if (a.coherent) acc = a.V[v];
-        else acc.x = a.I[v];
-    }
-    // the w x w taps: rows and columns of the periodic fine grid (w <= 8; the
-    // loops are unrolled so every gather of a frequency is in flight at once)
-    int col[8], rowoff[8];
+    if (live) {
+        const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
+        const double z = a.g.z[iz];
+        const double hw = 0.5 * a.w;
+        // plane pitch: the frame pitch, or dx / alpha on a scaled plane
+        const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
+        const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
+        const double tx = (x - a.cx) / px * 2.0 + MF / 2;
+        const double ty = (y - a.cy) / py * 2.0 + MF / 2;
+        const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
+        const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
+        const float ihw = (float)(1.0 / hw);
+        float wx[8], wy[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        col[i] = (ix0 + i) & (MF - 1);
-        rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
-    }
-    // the chunk's frequencies are evenly spaced: the illumination phase
-    // advances by a fixed per-voxel factor
-    float2 ph = make_float2(1.f, 0.f), st = make_float2(1.f, 0.f);
-    if (a.coherent) {
-        const double cyc0 = dd * (a.g.f[a.g.b0] / kC), cyc1 = dd * (a.g.df / kC);
-        float sn, cs;
-        sincos_cycles((float)(cyc0 - rint(cyc0)), &sn, &cs);
-        ph = make_float2(cs, sn);
-        sincos_cycles((float)(cyc1 - rint(cyc1)), &sn, &cs);
-        st = make_float2(cs, sn);
-    }
-    for (int b = a.g.b0; b < a.g.b0 + a.g.nb; ++b) {
-        const int p = (b - a.g.b0) * a.g.nzc + zl;
-        const float2* G2 = a.G2 + (size_t)p * MF * MF;
-        float2 s = make_float2(0.f, 0.f);
+        for (int i = 0; i < 8; ++i) {
+            wx[i] = i < a.w ? es_w(((float)i - fx) * ihw, a.beta) : 0.f;
+            wy[i] = i < a.w ? es_w(((float)i - fy) * ihw, a.beta) : 0.f;
+        }
+        const double dd = dist3d(x - a.xp0, y - a.xp1, z - a.xp2);
+        // the w x w taps: rows and columns of the periodic fine grid (w <= 8;
+        // the loops are unrolled so every gather of a frequency is in flight
+        // at once)
+        int col[8], rowoff[8];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            if (j >= a.w) break;
-            const float2* row = G2 + rowoff[j];
-            float2 r = make_float2(0.f, 0.f);
+        for (int i = 0; i < 8; ++i) {
+            col[i] = (ix0 + i) & (MF - 1);
+            rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
+        }
+        // the chunk's frequencies are evenly spaced: this wave's illumination
+        // phase advances by a fixed per-voxel factor (kInterpWaves steps)
+        float2 ph = make_float2(1.f, 0.f), st = make_float2(1.f, 0.f);
+        if (a.coherent && wave < a.g.nb) {
+            const double cyc0 = dd * (a.g.f[a.g.b0 + wave] / kC);
+            const double cyc1 = dd * (kInterpWaves * a.g.df / kC);
+            float sn, cs;
+            sincos_cycles((float)(cyc0 - rint(cyc0)), &sn, &cs);
+            ph = make_float2(cs, sn);
+            sincos_cycles((float)(cyc1 - rint(cyc1)), &sn, &cs);
+            st = make_float2(cs, sn);
+        }
+        for (int bl = wave; bl < a.g.nb; bl += kInterpWaves) {
+            const float2* G2 = a.G2 + (size_t)(bl * a.g.nzc + zl) * MF * MF;
+            float2 sum = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                if (i >= a.w) break;
-                const float2 gv = row[col[i]];
-                r.x = fmaf(wx[i], gv.x, r.x);
-                r.y = fmaf(wx[i], gv.y, r.y);
+            for (int j = 0; j < 8; ++j) {
+                if (j >= a.w) break;
+                const float2* row = G2 + rowoff[j];
+                float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    if (i >= a.w) break;
+                    const float2 gv = row[col[i]];
+                    r.x = fmaf(wx[i], gv.x, r.x);
+                    r.y = fmaf(wx[i], gv.y, r.y);
+                }
+                sum.x = fmaf(wy[j], r.x, sum.x);
+                sum.y = fmaf(wy[j], r.y, sum.y);
             }
-            s.x = fmaf(wy[j], r.x, s.x);
-            s.y = fmaf(wy[j], r.y, s.y);
-        }
-        if (a.coherent) {
-            acc = cadd(acc, cmul(ph, s));
-            ph = cmul(ph, st);
-        } else {
-            acc.x += sqrtf(s.x * s.x + s.y * s.y);
+            if (a.coherent) {
+                acc = cadd(acc, cmul(ph, sum));
+                ph = cmul(ph, st);
+            } else {
+                acc.x += sqrtf(sum.x * sum.x + sum.y * sum.y);
+            }
         }
     }
+    part[wave][lane] = acc;
+    __syncthreads();
+    if (wave != 0 || !live) return;
+    float2 tot = make_float2(0.f, 0.f);
+    if (!a.first) {
+        if (a.coherent) tot = a.V[v];
+        else tot.x = a.I[v];
+    }
+#pragma unroll
+    for (int w = 0; w < kInterpWaves; ++w) tot = cadd(tot, part[w][lane]);
     if (a.coherent) {
-        a.V[v] = acc;
-        if (a.last && a.I) a.I[v] = sqrtf(acc.x * acc.x + acc.y * acc.y);
+        a.V[v] = tot;
+        if (a.last && a.I) a.I[v] = sqrtf(tot.x * tot.x + tot.y * tot.y);
     } else {
-        a.I[v] = acc.x;
+        a.I[v] = tot.x;
     }
 }
 
@@ -252,8 +269,7 @@ static hipError_t type2_fine_impl(const Type2Args& a, hipStream_t s) {
     hipError_t e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes),
                              kT2RowWaves * 64, (size_t)(kT2RowWaves * G::SCR + 2 * M) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
-    return launch_t2(k_type2_interp, dim3((a.max_vox + kInterpThreads - 1) / kInterpThreads, a.g.nzc),
-                     kInterpThreads, 0, s, a);
+    return launch_t2(k_type2_interp, dim3((a.max_vox + 63) / 64, a.g.nzc), kInterpWaves * 64, 0, s, a);
 }
 
 template <int M>
