@@ -1446,25 +1446,33 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
             if ((rc = upload(p, px, &p->d_px))) return bail(rc);
             if ((rc = upload(p, py, &p->d_py))) return bail(rc);
             if ((rc = upload(p, p->alpha, &p->d_alpha))) return bail(rc);
-            // spectra of the Bluestein chirps h'[j] = e^{+j pi alpha (j - D)^2 / M},
-            // j in [-(N-1), M-1] at j mod LB, D = M/2 - N/2, divided by LB (inverse
-            // FFT of the convolution) and by M (each of the two passes carries one
-            // factor of the M^-2 of the final inverse transform)
-            const int M = p->M, N = p->nx, LB = 2 * M, D = M / 2 - N / 2;
-            std::vector<float2> hh((size_t)p->nz * LB);
-            std::vector<std::complex<double>> line(LB);
-            for (int iz = 0; iz < p->nz; ++iz) {
-                std::fill(line.begin(), line.end(), std::complex<double>(0, 0));
-                for (int j = -(N - 1); j <= M - 1; ++j) {
-                    const double dd = (double)(j - D);
-                    const double cyc = std::fmod(p->alpha[iz] * dd * dd / (2.0 * M), 1.0);
-                    line[(j + LB) % LB] = std::polar(1.0, 2.0 * M_PI * cyc);
+            // Bluestein chirp h'[j] = e^{+j pi alpha (j - D)^2 / M}, D = M/2 - N/2.
+            // The M outputs of a scaled line come in two halves k' in
+            // [k0, k0 + M/2), k0 = 0, M/2; half k0 is the circular convolution
+            // of length M of the pre-chirped input (n in [0, N)) with
+            // h'[k0 + j], j in [-(N-1), M/2 - 1] at j mod M, exact while
+            // N + M/2 - 1 <= M.  Spectra stored [Z][2][M], divided by M (inverse
+            // FFT of the convolution) and by M (each of the two passes carries
+            // one factor of the M^-2 of the final inverse transform).
+            const int M = p->M, N = p->nx, D = M / 2 - N / 2;
+            if (N + M / 2 - 1 > M)
+                return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "scaled RSD needs M >= 2 (N - 1) (pad >= 2)"));
+            std::vector<float2> hh((size_t)p->nz * 2 * M);
+            std::vector<std::complex<double>> line(M);
+            for (int iz = 0; iz < p->nz; ++iz)
+                for (int half = 0; half < 2; ++half) {
+                    const int k0 = half * (M / 2);
+                    std::fill(line.begin(), line.end(), std::complex<double>(0, 0));
+                    for (int j = -(N - 1); j <= M / 2 - 1; ++j) {
+                        const double dd = (double)(k0 + j - D);
+                        const double cyc = std::fmod(p->alpha[iz] * dd * dd / (2.0 * M), 1.0);
+                        line[(j + M) % M] = std::polar(1.0, 2.0 * M_PI * cyc);
+                    }
+                    fft64(line);
+                    for (int k = 0; k < M; ++k)
+                        hh[((size_t)iz * 2 + half) * M + k] =
+                            make_float2((float)(line[k].real() / ((double)M * M)), (float)(line[k].imag() / ((double)M * M)));
                 }
-                fft64(line);
-                for (int k = 0; k < LB; ++k)
-                    hh[(size_t)iz * LB + k] = make_float2((float)(line[k].real() / ((double)LB * M)),
-                                                          (float)(line[k].imag() / ((double)LB * M)));
-            }
             if ((rc = upload(p, hh, &p->d_hhat))) return bail(rc);
             // the chirp itself, c[j] = e^{-j pi alpha m^2 / M} at m = j - M/2
             std::vector<float2> cz((size_t)p->nz * M);

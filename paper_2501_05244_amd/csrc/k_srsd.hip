@@ -11,10 +11,12 @@
 // separable, each 1D pass by Bluestein's identity
 //   alpha k n = alpha/2 (k^2 + n^2 - (k - n)^2):
 //   S[k] = e^{-j pi alpha k^2/M} sum_n (u[n] e^{-j pi alpha n^2/M}) e^{+j pi alpha (k-n)^2/M},
-// a linear convolution done with FFTs of length LB = 2M >= M + N - 1 against
-// the precomputed spectrum of the chirp.  Both are per-plane tables built on
-// the host from FP64 arguments: the chirp c[m] = e^{-j pi alpha m^2 / M} for
-// m in [-M/2, M/2) (the input chirp of n in I_N is c[n]) and its spectrum.
+// a linear convolution.  The M outputs are split into two halves of M/2, each
+// a circular convolution of length M (>= N + M/2 - 1 for N <= M/2 + 1) against
+// its own precomputed chirp spectrum; both share the forward FFT of the
+// pre-chirped input.  The tables are per plane and built on the host from
+// FP64 arguments: the chirp c[m] = e^{-j pi alpha m^2 / M} for m in
+// [-M/2, M/2) (the input chirp of n in I_N is c[n]) and the two spectra.
 //   k_chirp_rows: Bluestein along x for each of the N rows, times the input
 //                 chirp of the y pass (one value per row); store transposed
 //                 S1t[p][kx][iy].
@@ -104,22 +106,37 @@ __global__ __launch_bounds__(kGridWaves * 64) void k_relay_grid_cols(RelayGridAr
         }
 }
 
-// Bluestein on one LB-point line held by a wave.  In: natural layout with the
-// pre-chirped input in [0, N).  Out: natural layout of the convolution.
+// Scaled DFT of one M-point line held by a wave, as two Bluestein
+// convolutions of length M (one per half of the outputs) sharing the forward
+// transform.  In: natural layout, v[e] = a[lane + 64 e], the pre-chirped input
+// in [0, N) and zero above.  Out: natural layout of the M convolution
+// outputs.  hh: the plane's two spectra [2][M], FFT order.
 template <int M>
-__device__ __forceinline__ void bluestein_line(float2* v, float2* scr, const float2* __restrict__ tw_lb,
-                                               const float2* __restrict__ hhat, int lane) {
-    using B = WaveFFT<2 * M>;
-    B::template nat_to_perm<false>(v, scr, tw_lb, lane);
+__device__ __forceinline__ void bluestein_halves(float2* v, float2* scr, const float2* __restrict__ tw,
+                                                 const float2* __restrict__ hh, int lane) {
+    using F = WaveFFT<M>;
+    constexpr int E = F::E, HE = E / 2;
+    static_assert(F::LPW == 1 && E % 2 == 0, "one line per wave");
+    F::template nat_to_perm<false>(v, scr, tw, lane);
+    float2 out[E];
 #pragma unroll
-    for (int h = 0; h < B::GPL; ++h)
+    for (int half = 0; half < 2; ++half) {
+        float2 b[F::NV];
 #pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            int q;
-            const int k = B::perm_k(lane, h, d, q);
-            v[h * 8 + d] = cmul(v[h * 8 + d], hhat[k]);
-        }
-    B::template perm_to_nat<true>(v, scr, tw_lb, lane);
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                b[h * 8 + d] = cmul(v[h * 8 + d], hh[half * M + k]);
+            }
+        F::template perm_to_nat<true>(b, scr, tw, lane);
+        // outputs t = lane + 64 e < M/2 of this half are outputs half * M/2 + t
+#pragma unroll
+        for (int e = 0; e < HE; ++e) out[half * HE + e] = b[e];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = out[e];
 }
 
 // Row pass: 8 rows per block (8 adjacent columns per store of the transposed
@@ -132,14 +149,14 @@ constexpr int kChirpColWaves = 4;
 
 template <int M>
 __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
-    using B = WaveFFT<2 * M>;
-    constexpr int LB = 2 * M, EB = B::E;
-    constexpr int SCRP = B::SCR;
+    using F = WaveFFT<M>;
+    constexpr int E = F::E;
+    constexpr int SCRP = F::SCR;
     constexpr int MP = M + 1;                // staging row of the transposed store
-    static_assert(kChirpWaves * MP <= kChirpWaves * SCRP, "staging must fit the scratch");
-    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP] (later [kChirpWaves][MP]), twiddles [LB]
+    static_assert(MP <= SCRP, "staging must fit the scratch");
+    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP] (later [kChirpWaves][MP]), twiddles [M]
     float2* tws = sm + kChirpWaves * SCRP;
-    for (int i = threadIdx.x; i < LB; i += kChirpWaves * 64) tws[i] = a.tw_lb[i];
+    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws[i] = a.tw_m[i];
     __syncthreads();
     // neighbouring row blocks (which share the cache lines of the transposed
     // store) run on the same XCD
@@ -150,19 +167,19 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     const int N = a.N;
     const int iy0 = (item % gridDim.x) * kChirpWaves;
     const int iy = iy0 + wave;
-    const float2* hhat = a.hhat + (size_t)iz * LB;
+    const float2* hh = a.hhat + (size_t)iz * 2 * M;
     const float2* cz = a.chirp + (size_t)iz * M;          // c[m] at m + M/2
     const int D = M / 2 - N / 2;                           // c of n - N/2 at n + D
     const float2* urow = a.u + ((size_t)b * N + (iy < N ? iy : 0)) * N;
-    float2 v[B::NV];
+    float2 v[F::NV];
 #pragma unroll
-    for (int e = 0; e < EB; ++e) {
+    for (int e = 0; e < E; ++e) {
         const int n = lane + 64 * e;
         v[e] = make_float2(0.f, 0.f);
         if (iy < N && n < N) v[e] = cmul(urow[n], cz[n + D]);
     }
     float2* scr = sm + wave * SCRP;
-    bluestein_line<M>(v, scr, tws, hhat, lane);
+    bluestein_halves<M>(v, scr, tws, hh, lane);
     // outputs k' = lane + 64 e < M: S[k] with k = k' - M/2, stored at kx = k mod M
     // in the block's staging rows (they overlap other waves' scratch: barrier)
     __syncthreads();
@@ -183,16 +200,13 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
 }
 
 template <int M>
-__global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 3, 8))) void k_chirp_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
-    using B = WaveFFT<2 * M>;
-    constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E;
+    constexpr int H = M / 2, E = F::E;
     static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
-    constexpr int SCRP = B::SCR + 1;
-    extern __shared__ float2 sm[];           // [kChirpColWaves][SCRP], twiddles LB, twiddles M
-    float2* tws_lb = sm + kChirpColWaves * SCRP;
-    float2* tws_m = tws_lb + LB;
-    for (int i = threadIdx.x; i < LB; i += kChirpColWaves * 64) tws_lb[i] = a.tw_lb[i];
+    constexpr int SCRP = F::SCR + 1;
+    extern __shared__ float2 sm[];           // [kChirpColWaves][SCRP], twiddles M
+    float2* tws_m = sm + kChirpColWaves * SCRP;
     for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
     __syncthreads();
     const int p = blockIdx.y;
@@ -202,7 +216,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_pe
     const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;
     const int N = a.N;
-    const float2* hhat = a.hhat + (size_t)iz * LB;
+    const float2* hh = a.hhat + (size_t)iz * 2 * M;
     float2* scr = sm + wave * SCRP;
     // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
@@ -230,14 +244,14 @@ __global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_pe
     for (int side = 0; side < 2; ++side) {
         const int s = side ? ((M - kx) & (M - 1)) : kx;
         if (side && s == kx) break;
-        float2 v[B::NV];
+        float2 v[F::NV];
 #pragma unroll
-        for (int e = 0; e < EB; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
             if (n < N) v[e] = S1[(size_t)s * N + n];
         }
-        bluestein_line<M>(v, scr, tws_lb, hhat, lane);
+        bluestein_halves<M>(v, scr, tws_m, hh, lane);
         // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
         NURSD_WAVE_SYNC();
 #pragma unroll
@@ -273,7 +287,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_pe
 // -> T2[p][s][jy].  The oversampled line has the Bluestein length 2M, so it
 // shares that transform's twiddles and scratch.
 template <int M>
-__global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 3, 8))) void k_chirp_type2_cols(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
     constexpr int H = M / 2, LB = 2 * M, EB = B::E, E = F::E, MF = 2 * M;
@@ -292,7 +306,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_pe
     const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;                      // wave-uniform; no block barriers below
     const int N = a.N;
-    const float2* hhat = a.hhat + (size_t)iz * LB;
+    const float2* hh = a.hhat + (size_t)iz * 2 * M;
     float2* scr = sm + wave * SCRP;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
     float2 g[F::NV];
@@ -326,7 +340,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) __attribute__((amdgpu_waves_pe
             v[e] = make_float2(0.f, 0.f);
             if (n < N) v[e] = S1[(size_t)s * N + n];
         }
-        bluestein_line<M>(v, scr, tws_lb, hhat, lane);
+        bluestein_halves<M>(v, scr, tws_m, hh, lane);
         // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
         NURSD_WAVE_SYNC();
 #pragma unroll
@@ -409,14 +423,14 @@ hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s) {
     const int planes = a.g.nb * a.g.nzc;
     switch (a.M) {
         case 512: {
-            using B = WaveFFT<1024>;
+            using F = WaveFFT<512>;
             return launch_k(k_chirp_rows<512>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * B::SCR + 1024) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 512) * sizeof(float2), s, a);
         }
         case 1024: {
-            using B = WaveFFT<2048>;
+            using F = WaveFFT<1024>;
             return launch_k(k_chirp_rows<1024>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * B::SCR + 2048) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 1024) * sizeof(float2), s, a);
         }
         default: return hipErrorInvalidValue;
     }
@@ -426,16 +440,14 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
     const int planes = a.g.nb * a.g.nzc;
     switch (a.M) {
         case 512: {
-            using B = WaveFFT<1024>;
+            using F = WaveFFT<512>;
             return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
-                            s, a);
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (F::SCR + 1) + 512) * sizeof(float2), s, a);
         }
         case 1024: {
-            using B = WaveFFT<2048>;
+            using F = WaveFFT<1024>;
             return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
-                            s, a);
+                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (F::SCR + 1) + 1024) * sizeof(float2), s, a);
         }
         default: return hipErrorInvalidValue;
     }
