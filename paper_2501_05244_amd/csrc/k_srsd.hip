@@ -139,12 +139,39 @@ __device__ __forceinline__ void bluestein_halves(float2* v, float2* scr, const f
     for (int e = 0; e < E; ++e) v[e] = out[e];
 }
 
+// As bluestein_halves, but each output k' (centred k = k' - M/2) is written to
+// dst[k mod M] (FFT order) as soon as its half is done, so no registers hold
+// the first half while the second is transformed.
+template <int M>
+__device__ __forceinline__ void bluestein_halves_to(float2* v, float2* scr, const float2* __restrict__ tw,
+                                                    const float2* __restrict__ hh, float2* dst, int lane) {
+    using F = WaveFFT<M>;
+    constexpr int E = F::E, HE = E / 2;
+    static_assert(F::LPW == 1 && E % 2 == 0, "one line per wave");
+    F::template nat_to_perm<false>(v, scr, tw, lane);
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        float2 b[F::NV];
+#pragma unroll
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                b[h * 8 + d] = cmul(v[h * 8 + d], hh[half * M + k]);
+            }
+        F::template perm_to_nat<true>(b, scr, tw, lane);
+#pragma unroll
+        for (int e = 0; e < HE; ++e) dst[(half * (M / 2) + lane + 64 * e + M / 2) & (M - 1)] = b[e];
+    }
+}
+
 // Row pass: 8 rows per block (8 adjacent columns per store of the transposed
 // output); 80 KB of LDS per block at M = 512, so two blocks share a CU.
 constexpr int kChirpWaves = 8;
-// Column passes: one Bluestein line per wave, no block-level exchange.  Four
-// waves per block (49 KB of LDS at M = 512) and at most 168 VGPRs let three
-// blocks share a CU, three waves per SIMD.
+// Column passes: one Bluestein line per wave, no block-level exchange, four
+// waves per block (35 KB of LDS at M = 512 for k_chirp_cols, so four blocks
+// share a CU).
 constexpr int kChirpColWaves = 4;
 
 template <int M>
@@ -154,21 +181,27 @@ __global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
     constexpr int SCRP = F::SCR;
     constexpr int MP = M + 1;                // staging row of the transposed store
     static_assert(MP <= SCRP, "staging must fit the scratch");
-    extern __shared__ float2 sm[];           // [kChirpWaves][SCRP] (later [kChirpWaves][MP]), twiddles [M]
+    // [kChirpWaves][SCRP] FFT scratch (later [kChirpWaves][MP] staging), twiddles
+    // [M], the plane's chirp spectra [2][M] and chirp [M]
+    extern __shared__ float2 sm[];
     float2* tws = sm + kChirpWaves * SCRP;
-    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) tws[i] = a.tw_m[i];
-    __syncthreads();
+    float2* hh = tws + M;
+    float2* cz = hh + 2 * M;                 // c[m] at m + M/2
     // neighbouring row blocks (which share the cache lines of the transposed
     // store) run on the same XCD
     const int item = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
     const int p = item / gridDim.x;
     const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
+    for (int i = threadIdx.x; i < M; i += kChirpWaves * 64) {
+        tws[i] = a.tw_m[i];
+        cz[i] = a.chirp[(size_t)iz * M + i];
+    }
+    for (int i = threadIdx.x; i < 2 * M; i += kChirpWaves * 64) hh[i] = a.hhat[(size_t)iz * 2 * M + i];
+    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int N = a.N;
     const int iy0 = (item % gridDim.x) * kChirpWaves;
     const int iy = iy0 + wave;
-    const float2* hh = a.hhat + (size_t)iz * 2 * M;
-    const float2* cz = a.chirp + (size_t)iz * M;          // c[m] at m + M/2
     const int D = M / 2 - N / 2;                           // c of n - N/2 at n + D
     const float2* urow = a.u + ((size_t)b * N + (iy < N ? iy : 0)) * N;
     float2 v[F::NV];
@@ -205,19 +238,22 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
     constexpr int H = M / 2, E = F::E;
     static_assert(F::LPW == 1, "scaled RSD needs M >= 512 per wave line");
     constexpr int SCRP = F::SCR + 1;
-    extern __shared__ float2 sm[];           // [kChirpColWaves][SCRP], twiddles M
-    float2* tws_m = sm + kChirpColWaves * SCRP;
+    // [kChirpColWaves][SCRP] FFT scratch, [kChirpColWaves][M] scaled spectrum
+    // lines, twiddles [M]
+    extern __shared__ float2 sm[];
+    float2* lines = sm + kChirpColWaves * SCRP;
+    float2* tws_m = lines + kChirpColWaves * M;
+    const int p = blockIdx.y;
+    const int iz = a.g.z0 + p % a.g.nzc;
+    const float2* hh = a.hhat + (size_t)iz * 2 * M;     // read through the caches (LDS is the occupancy limit)
     for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
     __syncthreads();
-    const int p = blockIdx.y;
-    const int b = a.g.b0 + p / a.g.nzc, iz = a.g.z0 + p % a.g.nzc;
-    (void)b;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kx = blockIdx.x * kChirpColWaves + wave;
     if (kx > H) return;
     const int N = a.N;
-    const float2* hh = a.hhat + (size_t)iz * 2 * M;
     float2* scr = sm + wave * SCRP;
+    float2* line = lines + wave * M;
     // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
     float2 g[F::NV];
@@ -251,14 +287,8 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
             v[e] = make_float2(0.f, 0.f);
             if (n < N) v[e] = S1[(size_t)s * N + n];
         }
-        bluestein_halves<M>(v, scr, tws_m, hh, lane);
-        // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
-        NURSD_WAVE_SYNC();
-#pragma unroll
-        for (int e = 0; e < M / 64; ++e) {
-            const int k = lane + 64 * e - M / 2;
-            scr[(k + M) & (M - 1)] = v[e];
-        }
+        // scaled spectrum column S[s][ky] / c[ky], in FFT order in LDS
+        bluestein_halves_to<M>(v, scr, tws_m, hh, line, lane);
         NURSD_WAVE_SYNC();
         float2 x[F::NV];
 #pragma unroll
@@ -267,7 +297,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
             for (int d = 0; d < 8; ++d) {
                 int q;
                 const int k = F::perm_k(lane, h, d, q);
-                x[h * 8 + d] = cmul(scr[k], g[h * 8 + d]);
+                x[h * 8 + d] = cmul(line[k], g[h * 8 + d]);
             }
         NURSD_WAVE_SYNC();
         F::template perm_to_nat<true>(x, scr, tws_m, lane);
@@ -425,12 +455,12 @@ hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s) {
         case 512: {
             using F = WaveFFT<512>;
             return launch_k(k_chirp_rows<512>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 512) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 4 * 512) * sizeof(float2), s, a);
         }
         case 1024: {
             using F = WaveFFT<1024>;
             return launch_k(k_chirp_rows<1024>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 1024) * sizeof(float2), s, a);
+                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 4 * 1024) * sizeof(float2), s, a);
         }
         default: return hipErrorInvalidValue;
     }
@@ -442,12 +472,14 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
         case 512: {
             using F = WaveFFT<512>;
             return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (F::SCR + 1) + 512) * sizeof(float2), s, a);
+                            kChirpColWaves * 64,
+                            (size_t)(kChirpColWaves * (F::SCR + 1 + 512) + 512) * sizeof(float2), s, a);
         }
         case 1024: {
             using F = WaveFFT<1024>;
             return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (F::SCR + 1) + 1024) * sizeof(float2), s, a);
+                            kChirpColWaves * 64,
+                            (size_t)(kChirpColWaves * (F::SCR + 1 + 1024) + 1024) * sizeof(float2), s, a);
         }
         default: return hipErrorInvalidValue;
     }
