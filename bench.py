@@ -196,6 +196,11 @@ def secondary(w_spad, dev) -> dict:
     xy = torch.from_numpy(w.relay_xy).to(dev)
     tgt = torch.zeros(plan.out_shape(), dtype=torch.complex64, device=dev)
 
+    V = torch.empty(plan.out_shape(), dtype=torch.complex64, device=dev)
+    ms = time_ms(lambda: plan.forward_phasor(P, out_vol=V, intensity=False), 10)
+    out["diff_forward"] = {"workload": "diff_L16384_F48_128x128x64", "ms": round(ms, 3),
+                           "voxel*freq/s": scenes.work_units(w) / (ms * 1e-3)}
+
     def step():
         Pg = P.detach().requires_grad_(True)
         xg = xy.detach().requires_grad_(True)
