@@ -260,7 +260,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = lane + 64 * e;
-        g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
+        g[e] = load_last(&Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)]);
     }
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     // fold the output chirp c[ky] into the kernel line
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
         for (int e = 0; e < E; ++e) {
             const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = S1[(size_t)s * N + n];
+            if (n < N) v[e] = load_last(&S1[(size_t)s * N + n]);
         }
         // scaled spectrum column S[s][ky] / c[ky], in FFT order in LDS
         bluestein_halves_to<M>(v, scr, tws_m, hh, line, lane);
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = lane + 64 * e;
-        g[e] = Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)];
+        g[e] = load_last(&Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)]);
     }
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     // fold the output chirp c[ky] into the kernel line
@@ -368,7 +368,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
         for (int e = 0; e < EB; ++e) {
             const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = S1[(size_t)s * N + n];
+            if (n < N) v[e] = load_last(&S1[(size_t)s * N + n]);
         }
         bluestein_halves<M>(v, scr, tws_m, hh, lane);
         // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order

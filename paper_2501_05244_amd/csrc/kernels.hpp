@@ -206,6 +206,15 @@ __device__ __forceinline__ int xcd_contiguous(int lin, int total) {
     return start + k;
 }
 
+// Load of data read for the last time (an intermediate the next kernels do
+// not need): marked non-temporal, so the caches evict it first and keep what
+// the next kernel reads.
+__device__ __forceinline__ float2 load_last(const float2* p) {
+    typedef float v2f __attribute__((ext_vector_type(2)));
+    const v2f t = __builtin_nontemporal_load(reinterpret_cast<const v2f*>(p));
+    return make_float2(t.x, t.y);
+}
+
 // ---------------------------------------------------------------- step 5 (voxel lists)
 // Fine rows the type-2 row pass transforms per block; the column passes store
 // T2 only in the bands of kType2RowBand rows from a plane's first reachable row.
