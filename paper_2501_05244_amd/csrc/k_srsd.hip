@@ -314,8 +314,8 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
 // up to the product S[s][ky] Ghat'[kx][ky]; then the type-2 steps of the
 // NUFFT section along y: deconvolve by the kernel's Fourier coefficients in
 // x and y, zero-pad to the 2M-point oversampled line, inverse FFT
-// -> T2[p][s][jy].  The oversampled line has the Bluestein length 2M, so it
-// shares that transform's twiddles and scratch.
+// -> T2[p][s][jy].  The Bluestein lines (length M) run in the first M slots of
+// the scratch of the 2M-point oversampled line.
 template <int M>
 __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
     using F = WaveFFT<M>;

@@ -181,10 +181,10 @@ struct ChirpArgs {
     float2* Yt;             // [planes][M][ny]
     int M, N, BS, ny;
     const double* alpha;    // [Z]
-    const float2* hhat;     // [Z][2M] chirp spectra / (2M * M)
+    const float2* hhat;     // [Z][2][M] chirp spectra of the two output halves / (M * M)
     const float2* chirp;    // [Z][M] e^{-j pi alpha m^2 / M}, m = j - M/2
     const float2* tw_m;     // twiddles of size M
-    const float2* tw_lb;    // twiddles of size 2M
+    const float2* tw_lb;    // twiddles of size 2M (oversampled type-2 line)
     float2* T2;             // [planes][M][2M] (voxel-list output only)
     const float* dec;       // [M] (-1)^k / phihat(k), FFT order (voxel-list output only)
     const int* row_lo;      // [Z] reachable fine rows of each plane (voxel-list output only)
