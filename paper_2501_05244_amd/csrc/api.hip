@@ -136,8 +136,11 @@ struct nursd_plan {
     int* d_plane_ptr = nullptr;   // POINTS
     int* d_row_lo = nullptr;
     int* d_row_hi = nullptr;
-    int* d_col_lo = nullptr;
-    int* d_col_hi = nullptr;
+    int* d_plane_band = nullptr;  // interpolation entries of voxel lists (see Type2Args)
+    int* d_lband_ptr = nullptr;
+    int* d_ent_vox = nullptr;
+    int* d_vox_ent = nullptr;
+    int n_lent = 0;
     int max_vox = 0;
     float* d_decx = nullptr;
     float* d_decy = nullptr;
@@ -152,7 +155,7 @@ struct nursd_plan {
     std::vector<int> ev_stage;
     // workspace layout
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0, ws_bytes = 0;
-    size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_G2 = 0, off_T3 = 0, off_G3 = 0;
+    size_t off_Tg = 0, off_u = 0, off_S1 = 0, off_T2 = 0, off_PT = 0, off_T3 = 0, off_G3 = 0;
     // 3D NURSD: intermediate plane, depth grid, depth weights per relay
     double z_mid = 0, dz3 = 0;
     int Mz3 = 0, FZ3 = 1;           // depth size; frequencies per stage-1 chunk
@@ -384,8 +387,8 @@ void layout_workspace(nursd_plan* p) {
     if (p->has_lists()) {
         p->off_T2 = o;
         o = align_up(o + planes * p->M * p->Mf * c8);
-        p->off_G2 = o;
-        o = align_up(o + planes * p->Mf * p->Mf * c8);
+        p->off_PT = o;
+        o = align_up(o + (size_t)p->FC * std::max(p->n_lent, 1) * c8);
     }
     p->off_V = o;
     o = align_up(o + (size_t)p->nvox() * c8);
@@ -611,7 +614,12 @@ Type2Args type2_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, 
     t.Bt = Bt;
     t.U = U;
     t.T2 = reinterpret_cast<float2*>(ws + p->off_T2);
-    t.G2 = reinterpret_cast<float2*>(ws + p->off_G2);
+    t.part = reinterpret_cast<float2*>(ws + p->off_PT);
+    t.n_lent = p->n_lent;
+    t.plane_band = p->d_plane_band;
+    t.band_ptr = p->d_lband_ptr;
+    t.ent_vox = p->d_ent_vox;
+    t.vox_ent = p->d_vox_ent;
     t.V = V;
     t.I = I;
     t.dec = p->d_decy;
@@ -631,8 +639,6 @@ Type2Args type2_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, 
     t.voxel_xy = p->voxel_xy_dev;
     t.row_lo = p->d_row_lo;
     t.row_hi = p->d_row_hi;
-    t.col_lo = p->d_col_lo;
-    t.col_hi = p->d_col_hi;
     t.max_vox = p->max_vox;
     t.first = b0 == 0;
     t.last = b0 + nb >= p->F;
@@ -1308,38 +1314,63 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     if (p->has_lists()) {
         if (p->M < 512)
             return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "voxel lists need a transform size M >= 512 (set options.M)"));
-        // fine rows and columns each plane's interpolation can reach (centred
-        // fine cells; a scaled plane has pitch dx / alpha, dy / alpha)
-        std::vector<int> lo(p->nz), hi(p->nz), clo(p->nz), chi(p->nz);
+        // fine rows each plane's interpolation can reach (centred fine cells;
+        // a scaled plane has pitch dy / alpha)
+        std::vector<int> lo(p->nz), hi(p->nz);
         const double hw = 0.5 * p->w;
-        auto reach = [&](int iz, int axis, double centre, double pitch, int* first, int* last) {
+        const int MF = p->Mf, RB = kType2RowBand;
+        if (p->w > RB) return bail(fail(NURSD_ERR_ARG, "kernel width above the interpolation band"));
+        auto first_row = [&](int v, double pitch) {
+            const double t = ((double)vxy[2 * v + 1] - p->cy) / pitch * 2.0 + MF / 2;
+            return (int)std::ceil(t - hw);
+        };
+        // interpolation entries: a voxel's w rows fall in one or two bands of
+        // RB rows counted from the plane's first reachable row; one entry per
+        // (voxel, band), sorted by plane, band and voxel
+        std::vector<int> pband(p->nz + 1, 0), bptr(1, 0), evox, vent((size_t)p->nvox() * 2, -1);
+        for (int iz = 0; iz < p->nz; ++iz) {
+            const double pitch = p->mode == NURSD_MODE_SRSD_POINTS ? p->dy / p->alpha[iz] : p->dy;
             int a = 1 << 30, c = -(1 << 30);
             for (int v = p->plane_ptr[iz]; v < p->plane_ptr[iz + 1]; ++v) {
-                const double t = ((double)vxy[2 * v + axis] - centre) / pitch * 2.0 + p->Mf / 2;
-                const int i0 = (int)std::ceil(t - hw);
+                const int i0 = first_row(v, pitch);
                 a = std::min(a, i0);
                 c = std::max(c, i0 + p->w - 1);
             }
             if (a > c) {          // empty plane
                 a = 0;
                 c = -1;
-            } else if (c - a + 1 >= p->Mf) {
+            } else if (c - a + 1 >= MF) {
                 a = 0;
-                c = p->Mf - 1;
+                c = MF - 1;
             }
-            *first = a;
-            *last = c;
-        };
-        for (int iz = 0; iz < p->nz; ++iz) {
-            const bool sc = p->mode == NURSD_MODE_SRSD_POINTS;
-            reach(iz, 1, p->cy, sc ? p->dy / p->alpha[iz] : p->dy, &lo[iz], &hi[iz]);
-            reach(iz, 0, p->cx, sc ? p->dx / p->alpha[iz] : p->dx, &clo[iz], &chi[iz]);
+            lo[iz] = a;
+            hi[iz] = c;
+            const int nb = c >= a ? (c - a) / RB + 1 : 0;
+            pband[iz + 1] = pband[iz] + nb;
+            std::vector<std::vector<int>> lists(nb);
+            for (int v = p->plane_ptr[iz]; v < p->plane_ptr[iz + 1]; ++v) {
+                const int i0 = first_row(v, pitch);
+                const int b0 = ((i0 - a) & (MF - 1)) / RB, b1 = ((i0 + p->w - 1 - a) & (MF - 1)) / RB;
+                lists[b0].push_back(v);
+                if (b1 != b0) lists[b1].push_back(v);
+            }
+            for (int b = 0; b < nb; ++b) {
+                for (int v : lists[b]) {
+                    int* ve = &vent[2 * (size_t)v];
+                    ve[ve[0] < 0 ? 0 : 1] = (int)evox.size();
+                    evox.push_back(v);
+                }
+                bptr.push_back((int)evox.size());
+            }
             p->max_vox = std::max(p->max_vox, p->plane_ptr[iz + 1] - p->plane_ptr[iz]);
         }
+        p->n_lent = (int)evox.size();
         if ((rc = upload(p, lo, &p->d_row_lo))) return bail(rc);
         if ((rc = upload(p, hi, &p->d_row_hi))) return bail(rc);
-        if ((rc = upload(p, clo, &p->d_col_lo))) return bail(rc);
-        if ((rc = upload(p, chi, &p->d_col_hi))) return bail(rc);
+        if ((rc = upload(p, pband, &p->d_plane_band))) return bail(rc);
+        if ((rc = upload(p, bptr, &p->d_lband_ptr))) return bail(rc);
+        if ((rc = upload(p, evox, &p->d_ent_vox))) return bail(rc);
+        if ((rc = upload(p, vent, &p->d_vox_ent))) return bail(rc);
         if ((rc = upload(p, p->plane_ptr, &p->d_plane_ptr))) return bail(rc);
     }
 

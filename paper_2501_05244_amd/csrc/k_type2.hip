@@ -8,14 +8,15 @@
 //                 U[+kx], U[-kx] and the x and y deconvolution factors
 //                 (with the (-1)^k of the centred fine grid), zero-padded
 //                 Mf-point inverse FFT along y -> T2[p][kx][jy].
-//   k_type2_rows: Mf-point inverse FFT along x of the zero-padded rows
-//                 -> fine grid G2[p][jy][jx] (rows no voxel can reach are
-//                 skipped).
-//   k_type2_interp: per voxel, w x w gather from the fine grid of every
-//                 frequency of the chunk, illumination phase (advanced by a
-//                 per-voxel step factor over the evenly spaced frequencies of
-//                 the chunk), accumulation; the frequencies are split over the
-//                 waves of a workgroup and their partial sums added in LDS.
+//   k_type2_band: per band of kType2RowBand fine rows, Mf-point inverse FFT
+//                 along x of the zero-padded rows, kept in LDS, and the w x w
+//                 interpolation of every voxel whose taps reach the band,
+//                 restricted to those rows -> partial sums per (frequency,
+//                 voxel-band entry).  The fine grid is never stored.
+//   k_type2_gather: per voxel, its one or two partial sums of every frequency
+//                 of the chunk, illumination phase (advanced by a per-voxel
+//                 step factor over the evenly spaced frequencies of the
+//                 chunk), accumulation.
 #include "kernels.hpp"
 #include "wavefft.hpp"
 
@@ -95,22 +96,58 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
     }
 }
 
+__device__ __forceinline__ double dist3d(double x, double y, double z) {
+    const double d2 = x * x + y * y + z * z;
+    float inv;
+    return sqrt_f64(d2, &inv);
+}
+
+// Fine-grid position of voxel v on plane iz: first tap (ix0, iy0), offsets of
+// the voxel from them (fx, fy) in fine cells, and its w x w kernel weights.
+__device__ __forceinline__ void voxel_taps(const Type2Args& a, int v, int iz, int& ix0, int& iy0, float* wx,
+                                           float* wy) {
+    const int MF = a.Mf;
+    const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
+    const double hw = 0.5 * a.w;
+    // plane pitch: the frame pitch, or dx / alpha on a scaled plane
+    const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
+    const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
+    const double tx = (x - a.cx) / px * 2.0 + MF / 2;
+    const double ty = (y - a.cy) / py * 2.0 + MF / 2;
+    ix0 = (int)ceil(tx - hw);
+    iy0 = (int)ceil(ty - hw);
+    const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
+    const float ihw = (float)(1.0 / hw);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        wx[i] = i < a.w ? es_w(((float)i - fx) * ihw, a.beta) : 0.f;
+        wy[i] = i < a.w ? es_w(((float)i - fy) * ihw, a.beta) : 0.f;
+    }
+}
+
+// One workgroup per band of RB fine rows of one (frequency, plane): inverse
+// FFT along x of the band's zero-padded rows, kept in LDS, then the w x w
+// interpolation of every voxel whose taps reach the band, restricted to the
+// band's rows; the partial sums go to part[frequency][entry].
 template <int M>
-__global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
+__global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_band(Type2Args a) {
     using G = WaveFFT<2 * M>;
     constexpr int H = M / 2, MF = 2 * M, EG = G::E;
     constexpr int TP = M + 1;               // tile row: the M data values of a line
     constexpr int RB = kT2RowWaves;
-    static_assert(TP <= G::SCR && H % 64 == 0, "tile layout");
+    static_assert(TP <= G::SCR && MF <= G::SCR && H % 64 == 0, "tile layout");
     // The block's RB rows are staged compactly (the zero padding is never
     // stored), read into registers, and the tile is then reused as the waves'
-    // FFT scratch: 80 KB at M = 512, so two blocks share a CU.
-    extern __shared__ float2 sm[];          // tile [RB][TP] / scratch [RB][SCR], twiddles MF
+    // FFT scratch and finally holds the transformed rows: 80 KB at M = 512, so
+    // two blocks share a CU.
+    extern __shared__ float2 sm[];          // tile [RB][TP] / scratch and rows [RB][SCR], twiddles MF
     float2* tws = sm + RB * G::SCR;
     for (int i = threadIdx.x; i < MF; i += kT2RowWaves * 64) tws[i] = a.tw_f[i];
     const int p = blockIdx.y;
-    const int iz = a.g.z0 + p % a.g.nzc;
-    const int jy0 = a.row_lo[iz] + blockIdx.x * RB;
+    const int zl = p % a.g.nzc, bl = p / a.g.nzc;
+    const int iz = a.g.z0 + zl;
+    const int band = blockIdx.x;
+    const int jy0 = a.row_lo[iz] + band * RB;
     if (jy0 > a.row_hi[iz]) return;         // block-uniform
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const float2* T2 = a.T2 + (size_t)p * M * MF;
@@ -132,123 +169,90 @@ __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_rows(Type2Args a) {
     __syncthreads();                        // all rows read: the tile becomes scratch
     float2* scr = sm + wave * G::SCR;
     G::template nat_to_perm<true>(v, scr, tws, lane);
-    const int jy = (jy0 + wave) & (MF - 1);
-    float2* G2 = a.G2 + ((size_t)p * MF + jy) * MF;
-    // only the fine columns some voxel of the plane reaches are stored
-    const int clo = a.col_lo[iz], ncols = a.col_hi[iz] - clo + 1;
+    // row jy0 + wave of the fine grid, natural column order, in this wave's region
 #pragma unroll
     for (int h = 0; h < G::GPL; ++h)
 #pragma unroll
         for (int d = 0; d < 8; ++d) {
             int q;
-            const int jx = G::perm_k(lane, h, d, q);
-            if (((jx - clo) & (MF - 1)) < ncols) G2[jx] = v[h * 8 + d];
+            scr[G::perm_k(lane, h, d, q)] = v[h * 8 + d];
         }
+    __syncthreads();
+    const int bi = a.plane_band[iz] + band;
+    const int e1 = a.band_ptr[bi + 1];
+    float2* part = a.part + (size_t)bl * a.n_lent;
+    for (int e = a.band_ptr[bi] + threadIdx.x; e < e1; e += kT2RowWaves * 64) {
+        int ix0, iy0;
+        float wx[8], wy[8];
+        voxel_taps(a, a.ent_vox[e], iz, ix0, iy0, wx, wy);
+        int col[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) col[i] = (ix0 + i) & (MF - 1);
+        float2 sum = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (j >= a.w) break;
+            const int lr = (iy0 + j - jy0) & (MF - 1);       // row within the band
+            if (lr >= RB) continue;
+            const float2* row = sm + lr * G::SCR;
+            float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (i >= a.w) break;
+                const float2 gv = row[col[i]];
+                r.x = fmaf(wx[i], gv.x, r.x);
+                r.y = fmaf(wx[i], gv.y, r.y);
+            }
+            sum.x = fmaf(wy[j], r.x, sum.x);
+            sum.y = fmaf(wy[j], r.y, sum.y);
+        }
+        part[e] = sum;
+    }
 }
 
-__device__ __forceinline__ double dist3d(double x, double y, double z) {
-    const double d2 = x * x + y * y + z * z;
-    float inv;
-    return sqrt_f64(d2, &inv);
-}
+constexpr int kGatherThreads = 256;
 
-// One workgroup per 64 voxels of a plane; its kInterpWaves waves split the
-// chunk's frequencies (wave w takes b0 + w, b0 + w + kInterpWaves, ...), so a
-// launch has kInterpWaves times as many waves as voxel groups, and the partial
-// sums meet in LDS, added in wave order (bitwise reproducible).  Two waves
-// measured best: more of them gather from more fine grids at once.
-constexpr int kInterpWaves = 2;
-
-__global__ __launch_bounds__(kInterpWaves * 64) void k_type2_interp(Type2Args a) {
-    __shared__ float2 part[kInterpWaves][64];
+// Per voxel: the partial sums of its one or two bands for every frequency of
+// the chunk, times the illumination phase (advanced by a per-voxel step factor
+// over the evenly spaced frequencies of the chunk), accumulated into V / I.
+__global__ __launch_bounds__(kGatherThreads) void k_type2_gather(Type2Args a) {
     const int zl = blockIdx.y;
     const int iz = a.g.z0 + zl;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int v = a.plane_ptr[iz] + blockIdx.x * 64 + lane;
-    const bool live = v < a.plane_ptr[iz + 1];
-    const int MF = a.Mf;
+    const int v = a.plane_ptr[iz] + blockIdx.x * kGatherThreads + threadIdx.x;
+    if (v >= a.plane_ptr[iz + 1]) return;
+    const int e0 = a.vox_ent[2 * v], e1 = a.vox_ent[2 * v + 1];
     float2 acc = make_float2(0.f, 0.f);
-    if (live) {
-        const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
-        const double z = a.g.z[iz];
-        const double hw = 0.5 * a.w;
-        // plane pitch: the frame pitch, or dx / alpha on a scaled plane
-        const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
-        const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
-        const double tx = (x - a.cx) / px * 2.0 + MF / 2;
-        const double ty = (y - a.cy) / py * 2.0 + MF / 2;
-        const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
-        const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
-        const float ihw = (float)(1.0 / hw);
-        float wx[8], wy[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            wx[i] = i < a.w ? es_w(((float)i - fx) * ihw, a.beta) : 0.f;
-            wy[i] = i < a.w ? es_w(((float)i - fy) * ihw, a.beta) : 0.f;
-        }
-        const double dd = dist3d(x - a.xp0, y - a.xp1, z - a.xp2);
-        // the w x w taps: rows and columns of the periodic fine grid (w <= 8;
-        // the loops are unrolled so every gather of a frequency is in flight
-        // at once)
-        int col[8], rowoff[8];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            col[i] = (ix0 + i) & (MF - 1);
-            rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
-        }
-        // the chunk's frequencies are evenly spaced: this wave's illumination
-        // phase advances by a fixed per-voxel factor (kInterpWaves steps)
-        float2 ph = make_float2(1.f, 0.f), st = make_float2(1.f, 0.f);
-        if (a.coherent && wave < a.g.nb) {
-            const double cyc0 = dd * (a.g.f[a.g.b0 + wave] / kC);
-            const double cyc1 = dd * (kInterpWaves * a.g.df / kC);
-            float sn, cs;
-            sincos_cycles((float)(cyc0 - rint(cyc0)), &sn, &cs);
-            ph = make_float2(cs, sn);
-            sincos_cycles((float)(cyc1 - rint(cyc1)), &sn, &cs);
-            st = make_float2(cs, sn);
-        }
-        for (int bl = wave; bl < a.g.nb; bl += kInterpWaves) {
-            const float2* G2 = a.G2 + (size_t)(bl * a.g.nzc + zl) * MF * MF;
-            float2 sum = make_float2(0.f, 0.f);
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                if (j >= a.w) break;
-                const float2* row = G2 + rowoff[j];
-                float2 r = make_float2(0.f, 0.f);
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    if (i >= a.w) break;
-                    const float2 gv = row[col[i]];
-                    r.x = fmaf(wx[i], gv.x, r.x);
-                    r.y = fmaf(wx[i], gv.y, r.y);
-                }
-                sum.x = fmaf(wy[j], r.x, sum.x);
-                sum.y = fmaf(wy[j], r.y, sum.y);
-            }
-            if (a.coherent) {
-                acc = cadd(acc, cmul(ph, sum));
-                ph = cmul(ph, st);
-            } else {
-                acc.x += sqrtf(sum.x * sum.x + sum.y * sum.y);
-            }
-        }
-    }
-    part[wave][lane] = acc;
-    __syncthreads();
-    if (wave != 0 || !live) return;
-    float2 tot = make_float2(0.f, 0.f);
     if (!a.first) {
-        if (a.coherent) tot = a.V[v];
-        else tot.x = a.I[v];
+        if (a.coherent) acc = a.V[v];
+        else acc.x = a.I[v];
     }
-#pragma unroll
-    for (int w = 0; w < kInterpWaves; ++w) tot = cadd(tot, part[w][lane]);
+    float2 ph = make_float2(1.f, 0.f), st = make_float2(1.f, 0.f);
     if (a.coherent) {
-        a.V[v] = tot;
-        if (a.last && a.I) a.I[v] = sqrtf(tot.x * tot.x + tot.y * tot.y);
+        const double x = a.voxel_xy[2 * v], y = a.voxel_xy[2 * v + 1];
+        const double dd = dist3d(x - a.xp0, y - a.xp1, a.g.z[iz] - a.xp2);
+        const double cyc0 = dd * (a.g.f[a.g.b0] / kC), cyc1 = dd * (a.g.df / kC);
+        float sn, cs;
+        sincos_cycles((float)(cyc0 - rint(cyc0)), &sn, &cs);
+        ph = make_float2(cs, sn);
+        sincos_cycles((float)(cyc1 - rint(cyc1)), &sn, &cs);
+        st = make_float2(cs, sn);
+    }
+    for (int bl = 0; bl < a.g.nb; ++bl) {
+        const float2* part = a.part + (size_t)bl * a.n_lent;
+        float2 s = part[e0];
+        if (e1 >= 0) s = cadd(s, part[e1]);
+        if (a.coherent) {
+            acc = cadd(acc, cmul(ph, s));
+            ph = cmul(ph, st);
+        } else {
+            acc.x += sqrtf(s.x * s.x + s.y * s.y);
+        }
+    }
+    if (a.coherent) {
+        a.V[v] = acc;
+        if (a.last && a.I) a.I[v] = sqrtf(acc.x * acc.x + acc.y * acc.y);
     } else {
-        a.I[v] = tot.x;
+        a.I[v] = acc.x;
     }
 }
 
@@ -266,10 +270,11 @@ template <int M>
 static hipError_t type2_fine_impl(const Type2Args& a, hipStream_t s) {
     using G = WaveFFT<2 * M>;
     const int planes = a.g.nb * a.g.nzc;
-    hipError_t e = launch_t2(k_type2_rows<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes),
+    hipError_t e = launch_t2(k_type2_band<M>, dim3((2 * M + kT2RowWaves - 1) / kT2RowWaves, planes),
                              kT2RowWaves * 64, (size_t)(kT2RowWaves * G::SCR + 2 * M) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
-    return launch_t2(k_type2_interp, dim3((a.max_vox + 63) / 64, a.g.nzc), kInterpWaves * 64, 0, s, a);
+    return launch_t2(k_type2_gather, dim3((a.max_vox + kGatherThreads - 1) / kGatherThreads, a.g.nzc),
+                     kGatherThreads, 0, s, a);
 }
 
 template <int M>

@@ -228,7 +228,6 @@ struct Type2Args {
     const float2* Bt;        // [planes][M/2+1][BS]
     const float2* U;         // [F][M][M]
     float2* T2;              // [planes][M][Mf]
-    float2* G2;              // [planes][Mf][Mf] oversampled fine grids
     float2* V;               // [V] or NULL
     float* I;                // [V] or NULL
     const float* dec;        // [M] (-1)^k / phihat(k), FFT order
@@ -242,8 +241,14 @@ struct Type2Args {
     const float* voxel_xy;   // [V][2]
     const int* row_lo;       // [Z] first fine row any voxel of the plane reaches (may be < 0)
     const int* row_hi;       // [Z] last such row
-    const int* col_lo;       // [Z] first fine column any voxel of the plane reaches (may be < 0)
-    const int* col_hi;       // [Z] last such column
+    // interpolation entries: one per (voxel, band of kType2RowBand fine rows
+    // from row_lo its taps reach), sorted by plane, then band, then voxel
+    const int* plane_band;   // [Z+1] first band of each plane in band_ptr
+    const int* band_ptr;     // [bands + 1] entry range of each band
+    const int* ent_vox;      // [n_lent] voxel of each entry
+    const int* vox_ent;      // [V][2] entries of each voxel (the second -1 if one)
+    float2* part;            // [frequencies of the chunk][n_lent] partial sums
+    int n_lent;
     int max_vox;             // largest voxel count of a plane
     int first, last, coherent;
 };
