@@ -15,13 +15,15 @@
 //                FFT along x, transposed store Rt[p][kx][iy].
 //   k_adj_cols:  forward FFT along y of Rt rows +kx and -kx, times conj(Ghat)
 //                (cosine transform of the quadrant rows), summed over the
-//                chunk's planes in registers, added to St_b.
+//                chunk's planes (the waves of a workgroup take the planes in
+//                turn, their sums added in LDS in wave order), added to St_b.
 //   k_adj_t2_cols / k_adj_t2_rows: three type-2 fine grids per frequency
 //                (plain, kx- and ky-weighted spectra), deconvolved and
 //                zero-padded, inverse FFT along y then x.
 //   k_adj_interp: per relay sample, w x w gather from the three grids of
-//                every frequency of the chunk; grad_P written, grad_xy summed
-//                over frequencies in a fixed order.
+//                every frequency of the chunk (the waves of a workgroup take
+//                the frequencies in turn); grad_P written, grad_xy summed over
+//                frequencies in a fixed order.
 #include "kernels.hpp"
 #include "wavefft.hpp"
 
@@ -111,15 +113,17 @@ template <int M>
 __global__ __launch_bounds__(kAdjColWaves * 64) void k_adj_cols(AdjArgs a) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
-    extern __shared__ float2 sm[];          // [waves][SCR], twiddles M
+    static_assert(kAdjColWaves * F::NV * 64 <= kAdjColWaves * F::SCR, "reduction must fit the scratch");
+    extern __shared__ float2 sm[];          // [waves][SCR] (then the partial sums), twiddles M
     float2* tws = sm + kAdjColWaves * F::SCR;
     for (int i = threadIdx.x; i < M; i += kAdjColWaves * 64) tws[i] = a.tw_m[i];
     __syncthreads();
     const int fb = blockIdx.y;
     const int b = a.g.b0 + fb;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kx0 = (blockIdx.x * kAdjColWaves + wave) * LPW;
-    if (kx0 > H) return;
+    // one group of LPW kx lines per workgroup (kx0 <= H by the grid); its
+    // waves take the chunk's planes in turn and their sums meet in LDS
+    const int kx0 = blockIdx.x * LPW;
     float2* scr = sm + wave * F::SCR;
     const int ny = a.ny, half = ny / 2;
     float2 acc[2][F::NV];
@@ -127,7 +131,7 @@ __global__ __launch_bounds__(kAdjColWaves * 64) void k_adj_cols(AdjArgs a) {
     for (int sd = 0; sd < 2; ++sd)
 #pragma unroll
         for (int i = 0; i < F::NV; ++i) acc[sd][i] = make_float2(0.f, 0.f);
-    for (int zl = 0; zl < a.g.nzc; ++zl) {
+    for (int zl = wave; zl < a.g.nzc; zl += kAdjColWaves) {
         const int p = fb * a.g.nzc + zl;
         const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
         float2 g[F::NV];
@@ -163,19 +167,29 @@ __global__ __launch_bounds__(kAdjColWaves * 64) void k_adj_cols(AdjArgs a) {
     }
     float2* St = a.St + (size_t)b * M * M;
 #pragma unroll
-    for (int sd = 0; sd < 2; ++sd)
+    for (int sd = 0; sd < 2; ++sd) {
+        __syncthreads();                    // scratch free (FFTs or the previous side done)
 #pragma unroll
-        for (int h = 0; h < F::GPL; ++h)
+        for (int i = 0; i < F::NV; ++i) sm[(wave * F::NV + i) * 64 + lane] = acc[sd][i];
+        __syncthreads();
+        if (wave == 0) {
 #pragma unroll
-            for (int d = 0; d < 8; ++d) {
-                int q;
-                const int k = F::perm_k(lane, h, d, q);
-                const int kx = kx0 + q;
-                const int s = sd ? ((M - kx) & (M - 1)) : kx;
-                if (kx > H || (sd && s == kx)) continue;
-                float2* o = St + (size_t)s * M + k;
-                *o = a.first ? acc[sd][h * 8 + d] : cadd(*o, acc[sd][h * 8 + d]);
-            }
+            for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    const int i = h * 8 + d;
+                    float2 t = sm[i * 64 + lane];
+                    for (int w = 1; w < kAdjColWaves; ++w) t = cadd(t, sm[(w * F::NV + i) * 64 + lane]);
+                    int q;
+                    const int k = F::perm_k(lane, h, d, q);
+                    const int kx = kx0 + q;
+                    const int s = sd ? ((M - kx) & (M - 1)) : kx;
+                    if (kx > H || (sd && s == kx)) continue;
+                    float2* o = St + (size_t)s * M + k;
+                    *o = a.first ? t : cadd(*o, t);
+                }
+        }
+    }
 }
 
 // Three type-2 spectra per frequency: q = 0 plain, 1 times j 2 pi kx / Lx,
@@ -277,57 +291,75 @@ __device__ __forceinline__ float es_a(float z, float beta) {
     return __expf(beta * (sqrtf(t) - 1.0f));
 }
 
-__global__ __launch_bounds__(256) void k_adj_interp(AdjArgs a) {
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= a.L) return;
-    const int MF = a.Mf;
-    const double hw = 0.5 * a.w;
-    const double tx = ((double)a.relay[2 * l] - a.cx) / a.g.dx * 2.0 + MF / 2;
-    const double ty = ((double)a.relay[2 * l + 1] - a.cy) / a.g.dy * 2.0 + MF / 2;
-    const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
-    const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
-    float wx[8], wy[8];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        wx[i] = i < a.w ? es_a(((float)i - fx) / (float)hw, a.beta) : 0.f;
-        wy[i] = i < a.w ? es_a(((float)i - fy) / (float)hw, a.beta) : 0.f;
-    }
+constexpr int kAdjInterpWaves = 8;
+
+// One workgroup per 64 relay samples; its waves take the chunk's frequencies
+// in turn (grad_P per frequency), and the position gradients of the waves are
+// added in LDS in wave order.
+__global__ __launch_bounds__(kAdjInterpWaves * 64) void k_adj_interp(AdjArgs a) {
+    __shared__ float2 gpart[kAdjInterpWaves][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 64 + lane;
+    const bool live = l < a.L;
     float gx = 0.f, gy = 0.f;
-    if (!a.first_b && a.grad_xy) {
-        gx = a.grad_xy[2 * l];
-        gy = a.grad_xy[2 * l + 1];
-    }
-    for (int fb = 0; fb < a.g.nb; ++fb) {
-        const int b = a.g.b0 + fb;
-        float2 val[3];
+    if (live) {
+        const int MF = a.Mf;
+        const double hw = 0.5 * a.w;
+        const double tx = ((double)a.relay[2 * l] - a.cx) / a.g.dx * 2.0 + MF / 2;
+        const double ty = ((double)a.relay[2 * l + 1] - a.cy) / a.g.dy * 2.0 + MF / 2;
+        const int ix0 = (int)ceil(tx - hw), iy0 = (int)ceil(ty - hw);
+        const float fx = (float)(tx - ix0), fy = (float)(ty - iy0);
+        const float ihw = (float)(1.0 / hw);
+        float wx[8], wy[8];
+        int col[8], rowoff[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            wx[i] = i < a.w ? es_a(((float)i - fx) * ihw, a.beta) : 0.f;
+            wy[i] = i < a.w ? es_a(((float)i - fy) * ihw, a.beta) : 0.f;
+            col[i] = (ix0 + i) & (MF - 1);
+            rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
+        }
         const int nq = a.grad_xy ? 3 : 1;
-        for (int qk = 0; qk < nq; ++qk) {
-            const float2* G3 = a.G3 + ((size_t)fb * 3 + qk) * MF * MF;
-            float2 s = make_float2(0.f, 0.f);
-            for (int j = 0; j < a.w; ++j) {
-                const float2* row = G3 + (size_t)((iy0 + j) & (MF - 1)) * MF;
-                float2 r = make_float2(0.f, 0.f);
-                for (int i = 0; i < a.w; ++i) {
-                    const float2 g = row[(ix0 + i) & (MF - 1)];
-                    r.x = fmaf(wx[i], g.x, r.x);
-                    r.y = fmaf(wx[i], g.y, r.y);
+        for (int fb = wave; fb < a.g.nb; fb += kAdjInterpWaves) {
+            const int b = a.g.b0 + fb;
+            float2 val[3];
+            for (int qk = 0; qk < nq; ++qk) {
+                const float2* G3 = a.G3 + ((size_t)fb * 3 + qk) * MF * MF;
+                float2 sum = make_float2(0.f, 0.f);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    if (j >= a.w) break;
+                    const float2* row = G3 + rowoff[j];
+                    float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        if (i >= a.w) break;
+                        const float2 g = row[col[i]];
+                        r.x = fmaf(wx[i], g.x, r.x);
+                        r.y = fmaf(wx[i], g.y, r.y);
+                    }
+                    sum.x = fmaf(wy[j], r.x, sum.x);
+                    sum.y = fmaf(wy[j], r.y, sum.y);
                 }
-                s.x = fmaf(wy[j], r.x, s.x);
-                s.y = fmaf(wy[j], r.y, s.y);
+                val[qk] = sum;
             }
-            val[qk] = s;
-        }
-        a.grad_P[(size_t)b * a.L + l] = val[0];
-        if (a.grad_xy) {
-            const float2 pv = a.P[(size_t)b * a.L + l];
-            gx += pv.x * val[1].x + pv.y * val[1].y;     // Re(conj(P) D)
-            gy += pv.x * val[2].x + pv.y * val[2].y;
+            a.grad_P[(size_t)b * a.L + l] = val[0];
+            if (a.grad_xy) {
+                const float2 pv = a.P[(size_t)b * a.L + l];
+                gx += pv.x * val[1].x + pv.y * val[1].y;     // Re(conj(P) D)
+                gy += pv.x * val[2].x + pv.y * val[2].y;
+            }
         }
     }
-    if (a.grad_xy) {
-        a.grad_xy[2 * l] = gx;
-        a.grad_xy[2 * l + 1] = gy;
-    }
+    if (!a.grad_xy) return;                 // uniform: no barrier below is skipped by part of the block
+    gpart[wave][lane] = make_float2(gx, gy);
+    __syncthreads();
+    if (wave != 0 || !live) return;
+    float2 t = a.first_b ? make_float2(0.f, 0.f) : make_float2(a.grad_xy[2 * l], a.grad_xy[2 * l + 1]);
+#pragma unroll
+    for (int w = 0; w < kAdjInterpWaves; ++w) t = cadd(t, gpart[w][lane]);
+    a.grad_xy[2 * l] = t.x;
+    a.grad_xy[2 * l + 1] = t.y;
 }
 
 template <typename Args>
@@ -349,8 +381,7 @@ static hipError_t adj_planes_impl(const AdjArgs& a, hipStream_t s) {
     hipError_t e = launch_a(k_adj_rows<M>, dim3((a.ny + RB - 1) / RB, a.g.nzc), NW * 64,
                             (size_t)(NW * SCRP + M) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
-    constexpr int LB = kAdjColWaves * F::LPW;
-    return launch_a(k_adj_cols<M>, dim3((M / 2 + 1 + LB - 1) / LB, a.g.nb), kAdjColWaves * 64,
+    return launch_a(k_adj_cols<M>, dim3((M / 2 + 1 + F::LPW - 1) / F::LPW, a.g.nb), kAdjColWaves * 64,
                     (size_t)(kAdjColWaves * F::SCR + M) * sizeof(float2), s, a);
 }
 
@@ -378,7 +409,7 @@ static hipError_t adj_t2_impl(const AdjArgs& a, hipStream_t s) {
     e = launch_a(k_adj_t2_rows<MF>, dim3((MF + RB - 1) / RB, a.g.nb, nq), 8 * 64,
                  (size_t)(8 * SCRP + MF) * sizeof(float2), s, a);
     if (e != hipSuccess) return e;
-    return launch_a(k_adj_interp, dim3((a.L + 255) / 256), 256, 0, s, a);
+    return launch_a(k_adj_interp, dim3((a.L + 63) / 64), kAdjInterpWaves * 64, 0, s, a);
 }
 
 hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s) {
