@@ -12,7 +12,9 @@ TOL = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def adj_case(seed=11, n=20, L=200, nz=3, F=3):

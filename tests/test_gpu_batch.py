@@ -11,7 +11,9 @@ pytestmark = pytest.mark.gpu
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def small_scenes():

@@ -14,7 +14,9 @@ TOL = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def grid_case(seed, K, n=32, zs=(0.5, 0.7, 0.95, 1.3), L=800, F=4):

@@ -17,7 +17,9 @@ TOL = 1e-4
 def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
-    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    r = float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def to_fft_order(Uc, M):

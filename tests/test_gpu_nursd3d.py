@@ -13,7 +13,9 @@ TOL = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def case(seed, n=24, L=300, F=3, zs=(0.3, 0.45, 0.7), amp=0.05, z_mid=0.08, dz3=0.02, mz3=0, dx=1.0 / 32):

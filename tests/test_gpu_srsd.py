@@ -12,7 +12,9 @@ TOL = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def srsd_case(n, seed, L=1500, zs=(0.6, 0.9, 1.4), F=2):

@@ -13,7 +13,9 @@ TOL = 1e-4
 
 
 def rel(a, b):
-    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    r = float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+    print(f"  rel-L2 {r:.3e}", flush=True)
+    return r
 
 
 def case(n, seed, counts=(300, 0, 517), zs=(0.6, 0.9, 1.4), L=1500, F=2, zref=0.55):
