@@ -83,7 +83,10 @@ typedef struct {
  *         (dx, dy) / alpha_iz, alpha_iz = alpha[iz] if alpha != NULL else
  *         zref / z[iz]; voxel (ix, iy) of plane iz lies at
  *         c + ((ix - nx/2) dx, (iy - ny/2) dy) / alpha_iz with
- *         c = (x0 + (nx/2) dx, y0 + (ny/2) dy).  Requires 0 < alpha <= 1.
+ *         c = (x0 + (nx/2) dx, y0 + (ny/2) dy).  Requires 0 < alpha <= 1,
+ *         nx == ny, M >= 512 and M >= 2 (nx - 1) (the scaled DFT runs as
+ *         two length-M convolutions per line; pad 2 always satisfies it);
+ *         otherwise plan creation fails with UNSUPPORTED_SIZE.
  * SRSD_POINTS: the SRSD relay grid and scales, evaluated at per-plane voxel
  *         lists (plane_ptr, voxel_xy_dev as in POINTS) by a type-2 NUFFT in
  *         each plane's scaled frame (period M dx / alpha_iz around c), the
