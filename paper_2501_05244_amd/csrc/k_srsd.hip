@@ -167,7 +167,8 @@ __device__ __forceinline__ void bluestein_halves_to(float2* v, float2* scr, cons
 }
 
 // Row pass: 8 rows per block (8 adjacent columns per store of the transposed
-// output); 80 KB of LDS per block at M = 512, so two blocks share a CU.
+// output); 52 KB of LDS per block at M = 512 and at most 80 VGPRs, so three
+// blocks share a CU.
 constexpr int kChirpWaves = 8;
 // Column passes: one Bluestein line per wave, no block-level exchange, four
 // waves per block (35 KB of LDS at M = 512 for k_chirp_cols, so four blocks
@@ -175,7 +176,7 @@ constexpr int kChirpWaves = 8;
 constexpr int kChirpColWaves = 4;
 
 template <int M>
-__global__ __launch_bounds__(kChirpWaves * 64) void k_chirp_rows(ChirpArgs a) {
+__global__ __launch_bounds__(kChirpWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 6, 8))) void k_chirp_rows(ChirpArgs a) {
     using F = WaveFFT<M>;
     constexpr int E = F::E;
     constexpr int SCRP = F::SCR;
