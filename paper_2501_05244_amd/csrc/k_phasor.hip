@@ -93,13 +93,19 @@ __device__ __forceinline__ void phasor_wave_body(const PhasorArgs& a, int bx) {
 #pragma unroll
         for (int e = 0; e < E; ++e) pre[e] = row[lane + 64 * e];
     };
+    // The spectrum sits in the scratch at a swizzled index: bits 5 and up of
+    // k (one bit for N = 512, two for N = 1024) are XORed into bits 2 and up,
+    // so the 32 lanes of each half-wave of a spill store hit distinct bank
+    // pairs (the natural index puts 2 or 4 of them on one pair).  The map
+    // permutes each aligned block of 32 entries: the scratch size is unchanged.
+    auto sw = [](int k) { return k ^ (((k >> 5) & (E / 4 - 1)) << 2); };
     // spectrum half h (0: A, 1: B) gathered into the staged outputs of r
     auto gather = [&](int half, int r) {
         for (int j = lane; j < a.F; j += 64) {
             const int b = a.bins[j];
             const float2 t = a.tb[j];
-            const float2 u1 = scr[b & (N - 1)];
-            const float2 u2 = cconj(scr[(N - b) & (N - 1)]);
+            const float2 u1 = scr[sw(b & (N - 1))];
+            const float2 u2 = cconj(scr[sw((N - b) & (N - 1))]);
             // al u1 + be u2 with al = (1 - j t)/2, be = (1 + j t)/2
             const float2 jt = make_float2(-t.y, t.x);
             float2 x = cscale(cadd(cadd(u1, u2), cmul(jt, csub(u2, u1))), 0.5f);
@@ -119,7 +125,7 @@ __device__ __forceinline__ void phasor_wave_body(const PhasorArgs& a, int bx) {
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 int q;
-                scr[W::perm_k(lane, h, d, q)] = v[h * 8 + d];
+                scr[sw(W::perm_k(lane, h, d, q))] = v[h * 8 + d];
             }
     };
     int r = wave;

@@ -100,46 +100,50 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
                            : rsd_kernel(fma(rx, rx, fma(ry, ry, z * z)), foc);
     }
     __syncthreads();
-    float2 v[F::NV];
+    // Waves whose rows all lie past M/2 (the tail of the last block) skip
+    // the work but still meet the block barriers.
+    if (my0 + wave * LPW <= H) {
+        float2 v[F::NV];
 #pragma unroll
-    for (int q = 0; q < LPW; ++q) {
-        const int my = my0 + wave * LPW + q;
-        const double ry = (my <= H ? my : 0) * py;
-        const double ryz = fma(ry, ry, z * z);
+        for (int q = 0; q < LPW; ++q) {
+            const int my = my0 + wave * LPW + q;
+            const double ry = (my <= H ? my : 0) * py;
+            const double ryz = fma(ry, ry, z * z);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int n = lane + 64 * e;
-            v[q * E + e] = make_float2(0.f, 0.f);
-            if (NYQ_LDS && 64 * e == H) {
-                if (lane == 0 && my <= H) v[q * E + e] = nyq[wave * LPW + q];
-            } else if (my <= H && n <= H) {
-                const double rx = n * px;
-                v[q * E + e] = a.plain ? rsd_kernel_plain(fma(rx, rx, ryz), foc) : rsd_kernel(fma(rx, rx, ryz), foc);
+            for (int e = 0; e < E; ++e) {
+                const int n = lane + 64 * e;
+                v[q * E + e] = make_float2(0.f, 0.f);
+                if (NYQ_LDS && 64 * e == H) {
+                    if (lane == 0 && my <= H) v[q * E + e] = nyq[wave * LPW + q];
+                } else if (my <= H && n <= H) {
+                    const double rx = n * px;
+                    v[q * E + e] = a.plain ? rsd_kernel_plain(fma(rx, rx, ryz), foc) : rsd_kernel(fma(rx, rx, ryz), foc);
+                }
+            }
+            // even extension: x[n] = x[M - n] for n > M/2, taken from the lane
+            // that computed M - n (same wave)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (64 * e + 63 <= H) continue;             // no slot of this e exceeds H
+                const int n = lane + 64 * e;
+                const float2 src = v[q * E + (E - 1 - e >= 0 ? E - 1 - e : 0)];
+                float2 t;
+                t.x = __shfl(src.x, (64 - lane) & 63);
+                t.y = __shfl(src.y, (64 - lane) & 63);
+                if (n > H) v[q * E + e] = (lane == 0) ? v[q * E + (E - e < E ? E - e : 0)] : t;
             }
         }
-        // even extension: x[n] = x[M - n] for n > M/2, taken from the lane
-        // that computed M - n (same wave)
+        float2* scr = sm + wave * SCRP;
+        F::template nat_to_perm<false>(v, scr, tws, lane);
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            if (64 * e + 63 <= H) continue;             // no slot of this e exceeds H
-            const int n = lane + 64 * e;
-            const float2 src = v[q * E + (E - 1 - e >= 0 ? E - 1 - e : 0)];
-            float2 t;
-            t.x = __shfl(src.x, (64 - lane) & 63);
-            t.y = __shfl(src.y, (64 - lane) & 63);
-            if (n > H) v[q * E + e] = (lane == 0) ? v[q * E + (E - e < E ? E - e : 0)] : t;
-        }
+        for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+            for (int d = 0; d < 8; ++d) {
+                int q;
+                const int k = F::perm_k(lane, h, d, q);
+                if (k <= H) scr[q * (H + 1) + k] = v[h * 8 + d];
+            }
     }
-    float2* scr = sm + wave * SCRP;
-    F::template nat_to_perm<false>(v, scr, tws, lane);
-#pragma unroll
-    for (int h = 0; h < F::GPL; ++h)
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-            int q;
-            const int k = F::perm_k(lane, h, d, q);
-            if (k <= H) scr[q * (H + 1) + k] = v[h * 8 + d];
-        }
     __syncthreads();
     float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
     for (int i = tid; i < (H + 1) * LB; i += kP1Waves * 64) {
@@ -159,17 +163,16 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
     extern __shared__ float2 sm[];      // [kP2Waves][SCR], then twiddles [M]
     float2* tws = sm + kP2Waves * F::SCR;
-    for (int i = threadIdx.x; i < M; i += kP2Waves * 64) tws[i] = a.tw[i];
-    __syncthreads();
     const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int kx0 = (bx * kP2Waves + wave) * LPW;
-    if (kx0 > H) return;                // wave-uniform; no block barriers below
     float2* scr = sm + wave * F::SCR;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
     float2 v[F::NV], g[F::NV];
+    // The kernel lines are requested before the twiddle table is staged, so
+    // that both global reads are in flight across the block barrier.
 #pragma unroll
     for (int q = 0; q < LPW; ++q) {
         const int kx = kx0 + q;
@@ -180,10 +183,13 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
             v[q * E + e] = kx <= H ? Bt[(size_t)kx * a.BS + dd] : make_float2(0.f, 0.f);
         }
     }
+    for (int i = threadIdx.x; i < M; i += kP2Waves * 64) tws[i] = a.tw[i];
+    __syncthreads();
+    if (kx0 > H) return;                // wave-uniform; no block barriers below
+    const float2* Ub = a.U + (size_t)b * M * M;
     F::template nat_to_perm<false>(v, scr, tws, lane);
 #pragma unroll
     for (int i = 0; i < F::NV; ++i) g[i] = v[i];
-    const float2* Ub = a.U + (size_t)b * M * M;
     float2* Yp = a.Yt + (size_t)p * M * a.ny;
     const int half = a.ny / 2;
 #pragma unroll
@@ -204,11 +210,16 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
             const int kx = kx0 + q;
             const int s = side ? ((M - kx) & (M - 1)) : kx;
             if (kx > H || (side && s == kx)) continue;
+            // One row base per line; slot e sits at offset 64 e, or 64 e - M
+            // past the centre, which is a constant when M/2 is a multiple of
+            // 64, so the stores take immediate offsets.
+            float2* row = Yp + (size_t)s * a.ny + half + lane;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int n = lane + 64 * e;
-                const int iy = (n < H ? n : n - M) + half;
-                if (iy >= 0 && iy < a.ny) Yp[(size_t)s * a.ny + iy] = v[q * E + e];
+                const bool lower = H % 64 == 0 ? 64 * e < H : lane + 64 * e < H;
+                const int off = lower ? 64 * e : 64 * e - M;
+                const int iy = lane + off + half;
+                if (iy >= 0 && iy < a.ny) row[off] = v[q * E + e];
             }
         }
     }
@@ -285,16 +296,18 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
             }
         }
     // This thread's share of the block's column tile: entry i = tid + r * NW * 64
-    // holds column s = i / RB of output row iy0 + i % RB.
+    // holds column s = i / RB of output row iy0 + i % RB.  Since NW * 64 is a
+    // multiple of RB, the row is tid % RB for every r and the column steps by
+    // 64 / LPW.  Rows past ny (ragged last block) load row ny - 1 instead:
+    // their transforms are never stored, and the loads need no branch.
     float2 pre[NPRE];
     const float2* Yb = a.Yt + (size_t)zl * M * ny;
     const size_t fstride = (size_t)a.g.nzc * M * ny;  // next frequency, same plane
+    static_assert((NW * 64) % RB == 0, "tile rows repeat with period RB");
+    const unsigned toff = (unsigned)((tid / RB) * ny + min(iy0 + tid % RB, ny - 1));
+    const unsigned tstep = (unsigned)((64 / LPW) * ny);
 #pragma unroll
-    for (int r = 0; r < NPRE; ++r) {
-        const int i = tid + r * NW * 64;
-        const int iy = iy0 + i % RB;
-        pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
-    }
+    for (int r = 0; r < NPRE; ++r) pre[r] = Yb[toff + r * tstep];
     // Two tiles alternate: while the waves transform their rows of frequency b
     // (each wave uses its own row of the tile as FFT scratch), frequency b+1 is
     // stored into the other tile and b+2 is loaded, with one barrier per step.
@@ -309,11 +322,7 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     auto load_tile = [&]() {
         Yb += fstride;
 #pragma unroll
-        for (int r = 0; r < NPRE; ++r) {
-            const int i = tid + r * NW * 64;
-            const int iy = iy0 + i % RB;
-            pre[r] = iy < ny ? Yb[(size_t)(i / RB) * ny + iy] : make_float2(0.f, 0.f);
-        }
+        for (int r = 0; r < NPRE; ++r) pre[r] = Yb[toff + r * tstep];
     };
     store_tile(sm);
     if (a.g.b0 + 1 < b_end) load_tile();

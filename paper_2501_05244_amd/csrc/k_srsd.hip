@@ -247,22 +247,23 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
     const int p = blockIdx.y;
     const int iz = a.g.z0 + p % a.g.nzc;
     const float2* hh = a.hhat + (size_t)iz * 2 * M;     // read through the caches (LDS is the occupancy limit)
-    for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
-    __syncthreads();
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int kx = blockIdx.x * kChirpColWaves + wave;
-    if (kx > H) return;
     const int N = a.N;
     float2* scr = sm + wave * SCRP;
     float2* line = lines + wave * M;
-    // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows
+    // kernel spectrum line Ghat'[kx][ky] (permuted), from the quadrant rows;
+    // requested before the twiddle table is staged so both reads overlap
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
     float2 g[F::NV];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int n = lane + 64 * e;
-        g[e] = load_last(&Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)]);
+        g[e] = kx <= H ? load_last(&Bt[(size_t)kx * a.BS + (n <= H ? n : M - n)]) : make_float2(0.f, 0.f);
     }
+    for (int i = threadIdx.x; i < M; i += kChirpColWaves * 64) tws_m[i] = a.tw_m[i];
+    __syncthreads();
+    if (kx > H) return;                      // wave-uniform; no block barriers below
     F::template nat_to_perm<false>(g, scr, tws_m, lane);
     // fold the output chirp c[ky] into the kernel line
     const float2* cz = a.chirp + (size_t)iz * M;
@@ -282,11 +283,11 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
         const int s = side ? ((M - kx) & (M - 1)) : kx;
         if (side && s == kx) break;
         float2 v[F::NV];
+        const float2* srow = S1 + (size_t)s * N + lane;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = load_last(&S1[(size_t)s * N + n]);
+            if (lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
         }
         // scaled spectrum column S[s][ky] / c[ky], in FFT order in LDS
         bluestein_halves_to<M>(v, scr, tws_m, hh, line, lane);
@@ -302,11 +303,14 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
             }
         NURSD_WAVE_SYNC();
         F::template perm_to_nat<true>(x, scr, tws_m, lane);
+        // slot e at a constant offset from one row base (64 e, or 64 e - M
+        // past the centre)
+        float2* row = Yp + (size_t)s * a.ny + half + lane;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            const int n = lane + 64 * e;
-            const int iyo = (n < H ? n : n - M) + half;
-            if (iyo >= 0 && iyo < a.ny) Yp[(size_t)s * a.ny + iyo] = x[e];
+            const int off = 64 * e < H ? 64 * e : 64 * e - M;
+            const int iyo = lane + off + half;
+            if (iyo >= 0 && iyo < a.ny) row[off] = x[e];
         }
     }
 }
@@ -365,11 +369,11 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
         const int s = side ? ((M - kx) & (M - 1)) : kx;
         if (side && s == kx) break;
         float2 v[B::NV];
+        const float2* srow = S1 + (size_t)s * N + lane;
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
-            const int n = lane + 64 * e;
             v[e] = make_float2(0.f, 0.f);
-            if (n < N) v[e] = load_last(&S1[(size_t)s * N + n]);
+            if (lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
         }
         bluestein_halves<M>(v, scr, tws_m, hh, lane);
         // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
@@ -406,13 +410,14 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
 #pragma unroll
         for (int e = 0; e < EB; ++e) v[e] = scr[lane + 64 * e];
         B::template nat_to_perm<true>(v, scr, tws_lb, lane);
+        float2* trow = T2 + (size_t)s * MF;
 #pragma unroll
         for (int h = 0; h < B::GPL; ++h)
 #pragma unroll
             for (int d = 0; d < 8; ++d) {
                 int q;
                 const int jy = B::perm_k(lane, h, d, q);
-                if (type2_row_stored(jy, lo, hi, MF)) T2[(size_t)s * MF + jy] = v[h * 8 + d];
+                if (type2_row_stored(jy, lo, hi, MF)) trow[jy] = v[h * 8 + d];
             }
     }
 }

@@ -145,6 +145,29 @@ def test_forward_ragged_grid_and_chunks(device, chunks):
     assert rel(I.cpu().numpy(), np.abs(Vref)) < TOL
 
 
+@pytest.mark.parametrize("L,F,nz,nx,ny", [(1, 1, 1, 1, 1), (1, 2, 2, 3, 1), (7, 1, 1, 33, 2), (65, 3, 1, 1, 40)])
+def test_forward_degenerate_sizes(device, L, F, nz, nx, ny):
+    """A single relay, a single frequency or plane, and one-pixel-wide
+    windows: every tile of every pass is ragged (transform sizes 64 and 128)."""
+    print("case: degenerate", L, F, nz, nx, ny, flush=True)
+    rng = np.random.default_rng(L * 100 + nx)
+    dx = 0.02
+    g = scenes.Grid(x0=-0.19, y0=-0.13, dx=dx, dy=dx, nx=nx, ny=ny, z=np.linspace(0.25, 0.5, nz))
+    xy = np.stack([rng.uniform(-0.18, 0.18, L), rng.uniform(-0.12, 0.12, L)], 1).astype(np.float32)
+    wl = scenes.Wavelet(lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=F, bins=np.array([13, 19, 26])[:F])
+    w = scenes.Workload("degenerate", xy, np.array([0.01, -0.02, 0.0]), wl, g)
+    P = (rng.normal(size=(F, L)) + 1j * rng.normal(size=(F, L))).astype(np.complex64)
+    plan = plan_for(w, device)
+    fr = o.frame_for_workload(w)
+    assert plan.info["M"] == fr.M
+    V, I = plan.forward_phasor(torch.from_numpy(P).to(device))
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, F, w.wavelet.bins)
+    Vref = o.nursd_grid(P.astype(np.complex128), xy.astype(np.float64), f, fr, g, w.xp)
+    assert V.shape == Vref.shape
+    assert rel(V.cpu().numpy(), Vref) < TOL
+    assert rel(I.cpu().numpy(), np.abs(Vref)) < TOL
+
+
 def test_forward_incoherent(device):
     w, P = ragged_case(seed=6)
     plan = plan_for(w, device, coherent=False)
@@ -186,6 +209,9 @@ def test_errors_are_reported(device):
     with pytest.raises(RuntimeError, match="UNSUPPORTED_SIZE"):
         Plan(xy, lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=3, z=[0.2], x0=-0.19, y0=-0.13,
              dx=0.02, dy=0.02, nx=20, ny=13, M=96)
+    with pytest.raises(RuntimeError, match="ARG"):
+        Plan(xy[:0], lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=3, z=[0.2], x0=-0.19, y0=-0.13,
+             dx=0.02, dy=0.02, nx=20, ny=13)
     far = xy.clone()
     far[0, 0] = 5.0
     with pytest.raises(RuntimeError, match="GEOMETRY"):
