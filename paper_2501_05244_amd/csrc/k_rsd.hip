@@ -69,7 +69,11 @@ __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int&
 }
 
 // P1: one wavefront per kernel row my (LPW rows per wave for M < 512).
-constexpr int kP1Waves = 16;
+// Waves per block (compile-time knob; 8 measured fastest, 16 and 4 slower).
+#ifndef NURSD_P1_WAVES
+#define NURSD_P1_WAVES 8
+#endif
+constexpr int kP1Waves = NURSD_P1_WAVES;
 
 template <int M>
 __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
@@ -155,7 +159,12 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
 
 // P2: one wavefront per kx line (LPW lines for M < 512): Ghat along y,
 // times U[+kx] and U[-kx], inverse along y, window rows -> Yt[p][s][iy].
-constexpr int kP2Waves = 8;
+// Waves per block (compile-time knob): 4 measured fastest (the tail of each
+// plane's M/2 + 1 lines wastes less, more blocks fit a CU); 2, 8, 16 slower.
+#ifndef NURSD_P2_WAVES
+#define NURSD_P2_WAVES 4
+#endif
+constexpr int kP2Waves = NURSD_P2_WAVES;
 
 template <int M>
 __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
