@@ -30,7 +30,9 @@ hipError_t launch_modulate(const ModulateArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-constexpr int kS1Waves = 8;
+// Four waves per block: measured 12 % faster than eight for the reduction
+// (more blocks per CU over the (M/2+1)/LPW lines of a frequency).
+constexpr int kS1Waves = 4;
 
 template <int M>
 __global__ __launch_bounds__(kS1Waves * 64) void k_stage1_reduce(Stage1Args a) {
