@@ -253,10 +253,14 @@ constexpr int p3_waves() { return (M >= 1024 || !HALF) ? 8 : NURSD_P3_WAVES; }
 // With nx <= M/2 (zero padding >= 2) only permuted slots d in {0, 1, 6, 7}
 // of each 8-point group can fall inside the window (|m'| < M/4); HALF keeps
 // per-voxel state for those four slots only.
-template <int M, bool HALF>
+// The persistent (grouped) launches run 8 waves per block at every size: with
+// the work-queue loop around the body, 16 waves (128 VGPRs each) spill.
+constexpr int kP3GroupWaves = 8;
+
+template <int M, bool HALF, int NW = p3_waves<M, HALF>()>
 __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
     using F = WaveFFT<M>;
-    constexpr int H = M / 2, E = F::E, LPW = F::LPW, NW = p3_waves<M, HALF>();
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW;
     constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
     constexpr int RB = NW * LPW;
     constexpr int NPRE = M * RB / (NW * 64);     // tile values per thread
@@ -400,7 +404,7 @@ __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
     propagate_cols_body<M>(a, v % gridDim.x, v / gridDim.x);
 }
 template <int M>
-__global__ __launch_bounds__(kP2Waves * 64, 6) void k_propagate_cols_grouped(Group<P2Args> g) {
+__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
     persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M>(a, bx, by); });
 }
 template <int M, bool HALF>
@@ -409,8 +413,8 @@ __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P
     propagate_rows_body<M, HALF>(a, v % gridDim.x, v / gridDim.x);
 }
 template <int M, bool HALF>
-__global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows_grouped(Group<P3Args> g) {
-    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF>(a, bx, by); });
+__global__ __launch_bounds__(kP3GroupWaves * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
+    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF, kP3GroupWaves>(a, bx, by); });
 }
 
 template <typename Args>
@@ -518,12 +522,10 @@ hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& 
     NURSD_SWITCH_M(M, {
         using F = WaveFFT<MM>;
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
-        if (half) {
-            constexpr int NW = (p3_waves<MM, true>());
+        constexpr int NW = kP3GroupWaves;
+        if (half)
             return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64,
                                   (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
-        }
-        constexpr int NW = (p3_waves<MM, false>());
         return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64,
                               (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
     })
@@ -542,9 +544,9 @@ int grid_x_propagate_cols(int M) {
     const int lpw = M >= 512 ? 1 : 512 / M;
     return (M / 2 + 1 + kP2Waves * lpw - 1) / (kP2Waves * lpw);
 }
-int rows_per_block_propagate(int M, bool half) {
+int rows_per_block_propagate(int M, bool) {
     const int lpw = M >= 512 ? 1 : 512 / M;
-    return ((M >= 1024 || !half) ? 8 : NURSD_P3_WAVES) * lpw;
+    return kP3GroupWaves * lpw;
 }
 
 }  // namespace nursd
