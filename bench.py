@@ -11,9 +11,11 @@ propagation of every (frequency, plane) pair, coherent volume and
 intensity.  The metric is voxel-frequency propagations per second
 (256*256*128*96 per step).
 
-Prints one JSON line.  The roofline object describes the dominant kernel,
-timed live with HIP events inside the timed region; cpu_baseline times the
-FP64 oracle on a bounded sample of the same workload on the host cores.
+Prints one JSON line.  The timed steps run without instrumentation; the
+roofline object describes the dominant kernel, whose launches are timed with
+HIP events on their stream during as many further steps run right after the
+timed ones.  cpu_baseline times the FP64 oracle on a bounded sample of the
+same workload on the host cores.
 """
 from __future__ import annotations
 
@@ -292,7 +294,7 @@ def main():
                     help="only run the plain copy used to scale rocprofv3 byte counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the reconstruction would shard "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the reconstruction would shard "
               "by depth plane with no exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch

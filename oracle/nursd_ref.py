@@ -14,7 +14,7 @@ definition, evaluated in float64 / complex128:
 There is no spreading kernel, no FFT and no chirp factorisation in this file.
 A matrix product is used as a primitive to evaluate the separable sums.
 
-Conventions (readings of the paper, listed with reasons in the design doc):
+Conventions (readings of the paper where its text is ambiguous or silent):
   * temporal transform e^{-j 2 pi f t}; back-propagation multiplies by
     e^{+j k r} for both the relay->voxel kernel and the illumination term,
     with k = 2 pi f / c;
