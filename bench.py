@@ -238,7 +238,7 @@ def secondary(w_spad, dev) -> dict:
     return out
 
 
-KERNEL_SOURCES = ("k_rsd.hip", "k_nufft.hip", "k_phasor.hip", "kernels.hpp", "wavefft.hpp", "persistent.hpp")
+KERNEL_SOURCES = ("k_rsd.hip", "k_nufft.hip", "k_phasor.hip", "kernels.hpp", "wavefft.hpp", "fft.hpp", "persistent.hpp")
 
 
 def kernel_source_hash() -> str:
