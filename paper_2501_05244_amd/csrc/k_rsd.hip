@@ -342,10 +342,6 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     for (int b = a.g.b0; b < b_end; ++b) {
         __syncthreads();
         float2* cur = sm + ((b - a.g.b0) & 1) * NW * SCRP;
-        if (b + 1 < b_end) {
-            store_tile(sm + ((b + 1 - a.g.b0) & 1) * NW * SCRP);
-            if (b + 2 < b_end) load_tile();
-        }
         float2* rows = cur + wave * SCRP;
         float2 v[F::NV];
 #pragma unroll
@@ -353,6 +349,13 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
 #pragma unroll
             for (int e = 0; e < E; ++e) v[q * E + e] = rows[q * M + lane + 64 * e];
         F::template nat_to_perm<true>(v, rows, tws, lane);
+        // The other tile is free since the barrier: the next frequency's tile
+        // is stored after this wave's transform (so the waves' LDS writes
+        // spread over the others' FFTs) and the one after is requested.
+        if (b + 1 < b_end) {
+            store_tile(sm + ((b + 1 - a.g.b0) & 1) * NW * SCRP);
+            if (b + 2 < b_end) load_tile();
+        }
 #pragma unroll
         for (int h = 0; h < F::GPL; ++h)
 #pragma unroll
