@@ -100,7 +100,7 @@ struct P2Args {
     ChunkGeom g;
     const float2* Bt;   // [planes][M/2+1][BS]
     const float2* U;    // [F][M][M]
-    float2* Yt;         // [planes][ny][M]
+    float2* Yt;         // [planes][M][ny]: kx line s, then window row iy
     int M, BS, ny;
     const float2* tw;
 };
@@ -108,7 +108,7 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s);
 
 struct P3Args {
     ChunkGeom g;
-    const float2* Yt;   // [planes][ny][M]
+    const float2* Yt;   // [planes][M][ny]: kx line s, then window row iy
     float2* V;          // [Z][ny][nx] (may be NULL for incoherent)
     float* I;           // [Z][ny][nx] or NULL
     int M, nx, ny;
