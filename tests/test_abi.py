@@ -52,3 +52,20 @@ def test_struct_layouts_match_header(tmp_path):
 
 def test_last_error_is_a_string():
     assert isinstance(_lib.load().nursd_last_error(), bytes)
+
+
+def test_missing_library_fails_loudly():
+    """Without the built library the package raises instead of falling back
+    to any CPU path (checked in a fresh interpreter)."""
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2501_05244_amd import _lib\n"
+            "_lib.LIB_PATH = '/nonexistent/libnursd.so'\n"
+            "try:\n"
+            "    _lib.load()\n"
+            "except ImportError as e:\n"
+            "    print('raised', e)\n"
+            "    sys.exit(0)\n"
+            "sys.exit(1)\n") % ROOT
+    r = subprocess.run(["python3", "-c", code], capture_output=True, text=True)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "is missing" in r.stdout
