@@ -19,7 +19,13 @@ Conventions (readings of the paper where its text is ambiguous or silent):
     e^{+j k r} for both the relay->voxel kernel and the illumination term,
     with k = 2 pi f / c;
   * RSD kernel G(p, z) = e^{+j k r} / r, r = sqrt(|p|^2 + z^2) (standard RSD
-    section, kernel of the plane-to-plane convolution);
+    section, kernel of the plane-to-plane convolution); inv_r=False drops the
+    1/r, the unit-amplitude phase of eq. PF_RSD_Defn;
+  * the frame is sampled at pitch (voxel pitch) / q, q = upsample_q >= 1
+    (q = 1: the kernel sampled at the relay/voxel rate, standard RSD
+    section); voxel i of a window of n is grid index i q - (n q)//2;
+  * optional per-sample weights w_l multiply the phasors (no density
+    compensation unless weights are given);
   * Gaussian band-pass weight exp(-(f - f_c)^2 / (2 sigma_f^2)),
     sigma_f = 0.2 f_c, on F consecutive DFT bins centred on round(f_c / df);
   * coherent sum over frequencies, intensity = |V|;
@@ -91,6 +97,7 @@ class Frame:
     dy: float
     cx: float        # grid point with index 0 [m]
     cy: float
+    q: int = 1       # grid points per voxel pitch (uniform-grid modes)
 
     @property
     def Lx(self) -> float:
@@ -119,18 +126,20 @@ def _fits(M, dx, dy, cx, cy, relay_xy, vox_lo, vox_hi):
 
 
 def choose_frame(mode: str, relay_xy, *, x0=0.0, y0=0.0, dx=1.0, dy=1.0, nx=0, ny=0,
-                 voxel_xy=None, pad: float = 2.0, sizes=SUPPORTED_M) -> Frame:
+                 voxel_xy=None, pad: float = 2.0, sizes=SUPPORTED_M, q: int = 1) -> Frame:
     """Frame rule (zero padding of the standard RSD section):
-      grid / srsd: pitch = voxel pitch, index 0 at voxel (nx//2, ny//2), M the
-                   smallest supported size >= pad * max(nx, ny) that passes _fits;
-      points:      pitch = dx, index 0 at the centre of the joint bounding box of
-                   relays and voxels, M the smallest supported size passing _fits."""
+      grid / srsd: pitch = voxel pitch / q, index 0 at grid point
+                   x0 + ((nx q)//2) pitch (voxel (nx//2, ny//2) when q = 1), M the
+                   smallest supported size >= pad * q * max(nx, ny) that passes _fits;
+      points:      pitch = dx / q, index 0 at the centre of the joint bounding box
+                   of relays and voxels, M the smallest supported size passing _fits."""
     if mode in ("grid", "srsd"):
-        cx = x0 + (nx // 2) * dx
-        cy = y0 + (ny // 2) * dy
+        gx, gy = dx / q, dy / q
+        cx = x0 + ((nx * q) // 2) * gx
+        cy = y0 + ((ny * q) // 2) * gy
         lo = (x0, y0)
         hi = (x0 + (nx - 1) * dx, y0 + (ny - 1) * dy)
-        mmin = pad * max(nx, ny)
+        mmin = pad * max(nx, ny) * q
     elif mode == "points":
         r = np.asarray(relay_xy, dtype=np.float64)
         v = np.asarray(voxel_xy, dtype=np.float64)
@@ -138,13 +147,20 @@ def choose_frame(mode: str, relay_xy, *, x0=0.0, y0=0.0, dx=1.0, dy=1.0, nx=0, n
         hi = (v[:, 0].max(), v[:, 1].max())
         cx = 0.5 * (min(lo[0], r[:, 0].min()) + max(hi[0], r[:, 0].max()))
         cy = 0.5 * (min(lo[1], r[:, 1].min()) + max(hi[1], r[:, 1].max()))
+        gx, gy = dx / q, dy / q
         mmin = 0
     else:
         raise ValueError(mode)
     for M in sizes:
-        if M >= mmin and _fits(M, dx, dy, cx, cy, relay_xy, lo, hi):
-            return Frame(M, dx, dy, cx, cy)
+        if M >= mmin and _fits(M, gx, gy, cx, cy, relay_xy, lo, hi):
+            return Frame(M, gx, gy, cx, cy, q)
     raise ValueError("no supported transform size fits the geometry")
+
+
+def window_index(n: int, q: int = 1) -> np.ndarray:
+    """Grid indices (around the frame centre) of the n voxels of a window:
+    i q - (n q)//2 for i = 0 .. n-1 (every q-th grid point)."""
+    return np.arange(n) * q - (n * q) // 2
 
 
 def rescale(x: np.ndarray, c: float, period: float) -> np.ndarray:
@@ -180,13 +196,15 @@ def nudft2(U: np.ndarray, xt: np.ndarray, yt: np.ndarray) -> np.ndarray:
 # Steps 4-5: RSD kernel spectrum and inverse transform (eq. RSD_conv,
 # eq. Discrete_RSD_Conv and eq. NURSD1).
 # ---------------------------------------------------------------------------
-def kernel_samples(f: float, z: float, M: int, dx: float, dy: float) -> np.ndarray:
-    """G(m dx, n dy, z) = e^{+j 2 pi f r / c} / r for (m, n) in I_M^2; [m][n]."""
+def kernel_samples(f: float, z: float, M: int, dx: float, dy: float, inv_r: bool = True) -> np.ndarray:
+    """G(m dx, n dy, z) = e^{+j 2 pi f r / c} / r (or without the 1/r when
+    inv_r is False) for (m, n) in I_M^2; [m][n]."""
     m = centered(M).astype(np.float64)
     X = (m * dx)[:, None]
     Y = (m * dy)[None, :]
     r = np.sqrt(X * X + Y * Y + z * z)
-    return np.exp(2j * np.pi * f * r / C_LIGHT) / r
+    g = np.exp(2j * np.pi * f * r / C_LIGHT)
+    return g / r if inv_r else g
 
 
 def dft_matrix(M: int, sign: float = -1.0, rows=None, cols=None) -> np.ndarray:
@@ -216,14 +234,19 @@ def illumination_phase(f: float, x, y, z, xp) -> np.ndarray:
     return np.exp(2j * np.pi * f * d / C_LIGHT)
 
 
-def nursd_grid(P, relay_xy, f, frame: Frame, grid, xp, coherent=True, intensity=False):
+def nursd_grid(P, relay_xy, f, frame: Frame, grid, xp, coherent=True, intensity=False, inv_r=True,
+               weights=None):
     """NURSD-1 onto a uniform voxel grid (eq. NURSD1, volume formation of
-    eq. PF_RSD_Defn).  P: [F][L]; returns V complex [Z][ny][nx] (coherent) or
-    sum_b |F_b| (incoherent)."""
+    eq. PF_RSD_Defn).  P: [F][L]; weights: optional [L] factors w_l applied to
+    every P[b][l]; the voxels are every q-th point of the frame
+    (window_index).  Returns V complex [Z][ny][nx] (coherent) or sum_b |F_b|
+    (incoherent)."""
+    if weights is not None:
+        P = np.asarray(P) * np.asarray(weights, dtype=np.float64)[None, :]
     xt = rescale(relay_xy[:, 0], frame.cx, frame.Lx)
     yt = rescale(relay_xy[:, 1], frame.cy, frame.Ly)
-    mx = np.arange(grid.nx) - grid.nx // 2
-    my = np.arange(grid.ny) - grid.ny // 2
+    mx = window_index(grid.nx, frame.q)
+    my = window_index(grid.ny, frame.q)
     xs = frame.cx + mx * frame.dx
     ys = frame.cy + my * frame.dy
     z = np.asarray(grid.z, dtype=np.float64)
@@ -231,7 +254,7 @@ def nursd_grid(P, relay_xy, f, frame: Frame, grid, xp, coherent=True, intensity=
     for b, fb in enumerate(f):
         U = nudft1(P[b], xt, yt, frame.M)
         for iz, zz in enumerate(z):
-            Gh = dft2(kernel_samples(fb, zz, frame.M, frame.dx, frame.dy))
+            Gh = dft2(kernel_samples(fb, zz, frame.M, frame.dx, frame.dy, inv_r))
             Fz = idft2_at(U * Gh, mx, my).T                    # [ny][nx]
             if coherent:
                 ph = illumination_phase(fb, xs[None, :], ys[:, None], zz, xp)
@@ -241,7 +264,7 @@ def nursd_grid(P, relay_xy, f, frame: Frame, grid, xp, coherent=True, intensity=
     return np.abs(out) if (coherent and intensity) else out
 
 
-def nursd_points(P, relay_xy, f, frame: Frame, z, plane_ptr, voxel_xy, xp):
+def nursd_points(P, relay_xy, f, frame: Frame, z, plane_ptr, voxel_xy, xp, inv_r=True):
     """NURSD-3: NUDFT-1 in, NUDFT-2 out at per-plane voxel lists (eq. NURSD3,
     which reduces to eq. NURSD2 for on-grid relays).  Returns V complex [V]."""
     xt = rescale(relay_xy[:, 0], frame.cx, frame.Lx)
@@ -256,7 +279,7 @@ def nursd_points(P, relay_xy, f, frame: Frame, z, plane_ptr, voxel_xy, xp):
             a, e = int(plane_ptr[iz]), int(plane_ptr[iz + 1])
             if a == e:
                 continue
-            Gh = dft2(kernel_samples(fb, zz, M, frame.dx, frame.dy))
+            Gh = dft2(kernel_samples(fb, zz, M, frame.dx, frame.dy, inv_r))
             vals = nudft2(U * Gh, rescale(vx[a:e], frame.cx, frame.Lx),
                           rescale(vy[a:e], frame.cy, frame.Ly)) / (M * M)
             out[a:e] += illumination_phase(fb, vx[a:e], vy[a:e], zz, xp) * vals
@@ -286,7 +309,7 @@ def srsd_alpha(z, zref):
     return np.asarray(zref / np.asarray(z, dtype=np.float64))
 
 
-def srsd(P, relay_xy, f, frame: Frame, grid, xp, alphas):
+def srsd(P, relay_xy, f, frame: Frame, grid, xp, alphas, inv_r=True):
     """Scaled RSD on the frustum: per plane, scaled DFT of the uniform relay
     grid u (pitch dx), times the DFT of G sampled at pitch dx / alpha, inverse
     DFT onto the N x N window; voxel (ix, iy) of plane z sits at
@@ -305,7 +328,7 @@ def srsd(P, relay_xy, f, frame: Frame, grid, xp, alphas):
         for iz, zz in enumerate(z):
             a = float(alphas[iz])
             S = scaled_dft(scaled_dft(u, a, M).T, a, M).T     # rows then columns
-            Gh = dft2(kernel_samples(fb, zz, M, frame.dx / a, frame.dy / a))
+            Gh = dft2(kernel_samples(fb, zz, M, frame.dx / a, frame.dy / a, inv_r))
             Fz = idft2_at(S * Gh, m, m).T
             xs = frame.cx + m * frame.dx / a
             ys = frame.cy + m * frame.dy / a
@@ -313,7 +336,7 @@ def srsd(P, relay_xy, f, frame: Frame, grid, xp, alphas):
     return out
 
 
-def srsd_points(P, relay_xy, f, frame: Frame, N, z, alphas, plane_ptr, voxel_xy, xp):
+def srsd_points(P, relay_xy, f, frame: Frame, N, z, alphas, plane_ptr, voxel_xy, xp, inv_r=True):
     """Fusion of the scaled RSD with NURSD-2 (eq. NURSD2_SRSD): per plane, the
     scaled spectrum S of the uniform relay grid u (as in srsd) times the DFT
     of G sampled at pitch dx / alpha, evaluated at the plane's voxel list by a
@@ -335,7 +358,7 @@ def srsd_points(P, relay_xy, f, frame: Frame, N, z, alphas, plane_ptr, voxel_xy,
                 continue
             a = float(alphas[iz])
             S = scaled_dft(scaled_dft(u, a, M).T, a, M).T
-            Gh = dft2(kernel_samples(fb, zz, M, frame.dx / a, frame.dy / a))
+            Gh = dft2(kernel_samples(fb, zz, M, frame.dx / a, frame.dy / a, inv_r))
             vals = nudft2(S * Gh, rescale(vx[a0:e0], frame.cx, frame.Lx / a),
                           rescale(vy[a0:e0], frame.cy, frame.Ly / a)) / (M * M)
             out[a0:e0] += illumination_phase(fb, vx[a0:e0], vy[a0:e0], zz, xp) * vals
@@ -424,13 +447,13 @@ def nursd3d_stage1(Pb, relay_xyz, fb, frame: Frame, z0: float, dz: float, Mz: in
     return (U3 * Gh3).sum(axis=0) / Mz
 
 
-def nursd3d_grid(P, relay_xyz, f, frame: Frame, grid, xp, z0: float, dz: float, Mz: int):
+def nursd3d_grid(P, relay_xyz, f, frame: Frame, grid, xp, z0: float, dz: float, Mz: int, inv_r=True):
     """3D NURSD onto a uniform voxel grid: stage 1 (nursd3d_stage1) to the
     plane z0, then NURSD-1's plane-to-plane propagation with G = e^{+jkr}/r
     at distance z_v - z0 and the volume formation of eq. PF_RSD_Defn.
     grid.z are the voxel depths, all > z0.  Returns V complex [Z][ny][nx]."""
-    mx = np.arange(grid.nx) - grid.nx // 2
-    my = np.arange(grid.ny) - grid.ny // 2
+    mx = window_index(grid.nx, frame.q)
+    my = window_index(grid.ny, frame.q)
     xs = frame.cx + mx * frame.dx
     ys = frame.cy + my * frame.dy
     z = np.asarray(grid.z, dtype=np.float64)
@@ -438,7 +461,7 @@ def nursd3d_grid(P, relay_xyz, f, frame: Frame, grid, xp, z0: float, dz: float, 
     for b, fb in enumerate(f):
         U0 = nursd3d_stage1(P[b], relay_xyz, fb, frame, z0, dz, Mz)
         for iz, zz in enumerate(z):
-            Gh = dft2(kernel_samples(fb, zz - z0, frame.M, frame.dx, frame.dy))
+            Gh = dft2(kernel_samples(fb, zz - z0, frame.M, frame.dx, frame.dy, inv_r))
             Fz = idft2_at(U0 * Gh, mx, my).T
             out[iz] += illumination_phase(fb, xs[None, :], ys[:, None], zz, xp) * Fz
     return out
@@ -447,18 +470,20 @@ def nursd3d_grid(P, relay_xyz, f, frame: Frame, grid, xp, z0: float, dz: float, 
 # ---------------------------------------------------------------------------
 # Step 8: adjoint of the uniform-grid operator and the loss gradients.
 # ---------------------------------------------------------------------------
-def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None):
+def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None, inv_r=True, weights=None):
     """Conjugate transpose of P -> V (nursd_grid, coherent) applied to gV
     [Z][ny][nx].  Returns grad_P [F][L] and, when P is given, the position
     gradient grad_xy [L][2] = Re sum_b conj(P_bl) dV/dx_l contracted with gV,
     i.e. for a real loss with PyTorch-style upstream gradient gV
     (dL/dRe V + j dL/dIm V): grad_P = A^H gV and
-    grad_x_l = Re sum_b conj(P_bl) sum_k S_b[k] (j 2 pi kx / Lx) e^{+j k.x~_l}."""
+    grad_x_l = Re sum_b conj(P_bl) sum_k S_b[k] (j 2 pi kx / Lx) e^{+j k.x~_l}.
+    With weights w_l (the forward map is P -> V(w P)), both gradients carry
+    the factor w_l."""
     xt = rescale(relay_xy[:, 0], frame.cx, frame.Lx)
     yt = rescale(relay_xy[:, 1], frame.cy, frame.Ly)
     M = frame.M
-    mx = np.arange(grid.nx) - grid.nx // 2
-    my = np.arange(grid.ny) - grid.ny // 2
+    mx = window_index(grid.nx, frame.q)
+    my = window_index(grid.ny, frame.q)
     xs = frame.cx + mx * frame.dx
     ys = frame.cy + my * frame.dy
     k = centered(M).astype(np.float64)
@@ -474,7 +499,7 @@ def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None):
             ph = illumination_phase(fb, xs[None, :], ys[:, None], zz, xp)
             r = (np.conj(ph) * gV[iz]).T                       # [nx][ny]
             R = Dx @ r @ Dy.T / (M * M)
-            Gh = dft2(kernel_samples(fb, zz, M, frame.dx, frame.dy))
+            Gh = dft2(kernel_samples(fb, zz, M, frame.dx, frame.dy, inv_r))
             S += np.conj(Gh) * R
         gP[b] = nudft2(S, xt, yt)
         if P is not None:
@@ -482,6 +507,10 @@ def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None):
             Sy = S * (1j * 2 * np.pi * k / frame.Ly)[None, :]
             gxy[:, 0] += np.real(np.conj(P[b]) * nudft2(Sx, xt, yt))
             gxy[:, 1] += np.real(np.conj(P[b]) * nudft2(Sy, xt, yt))
+    if weights is not None:
+        w = np.asarray(weights, dtype=np.float64)
+        gP = gP * w[None, :]
+        gxy = gxy * w[:, None]
     return gP, gxy
 
 
@@ -489,9 +518,10 @@ def nursd_grid_adjoint(gV, relay_xy, f, frame: Frame, grid, xp, P=None):
 # Physics reference: the RSD integral evaluated sample by sample (eq.
 # PF_RSD_Defn with the kernel of eq. RSD_conv, i.e. filtered back-projection).
 # ---------------------------------------------------------------------------
-def rsd_direct(P, relay_xy, f, vox_xyz, xp, chunk: int = 4096):
-    """V(x_v) = sum_b e^{+j k_b |x_v - x_p|} sum_l P[b][l] e^{+j k_b r_lv} / r_lv,
-    relay at z = 0.  vox_xyz: [V][3]; returns complex [V]."""
+def rsd_direct(P, relay_xy, f, vox_xyz, xp, chunk: int = 4096, inv_r: bool = True):
+    """V(x_v) = sum_b e^{+j k_b |x_v - x_p|} sum_l P[b][l] e^{+j k_b r_lv} / r_lv
+    (no 1/r_lv when inv_r is False), relay at z = 0.  vox_xyz: [V][3];
+    returns complex [V]."""
     r = np.asarray(relay_xy, dtype=np.float64)
     v = np.asarray(vox_xyz, dtype=np.float64)
     out = np.zeros(v.shape[0], dtype=np.complex128)
@@ -500,7 +530,9 @@ def rsd_direct(P, relay_xy, f, vox_xyz, xp, chunk: int = 4096):
         d = np.sqrt((v[a:e, None, 0] - r[None, :, 0]) ** 2 + (v[a:e, None, 1] - r[None, :, 1]) ** 2
                     + v[a:e, None, 2] ** 2)
         for b, fb in enumerate(f):
-            Gk = np.exp(2j * np.pi * fb * d / C_LIGHT) / d
+            Gk = np.exp(2j * np.pi * fb * d / C_LIGHT)
+            if inv_r:
+                Gk = Gk / d
             ph = illumination_phase(fb, v[a:e, 0], v[a:e, 1], v[a:e, 2], xp)
             out[a:e] += ph * (Gk @ np.asarray(P[b], dtype=np.complex128))
     return out
@@ -549,12 +581,12 @@ def phasors_from_workload(w, hist=None):
     return temporal_phasor(h, bins, wts), f
 
 
-def frame_for_workload(w) -> Frame:
+def frame_for_workload(w, q: int = 1) -> Frame:
     g = w.grid
     if w.mode == "points":
-        return choose_frame("points", w.relay_xy, dx=g.dx, dy=g.dy, voxel_xy=w.voxel_xy, pad=w.pad)
+        return choose_frame("points", w.relay_xy, dx=g.dx, dy=g.dy, voxel_xy=w.voxel_xy, pad=w.pad, q=q)
     # the scaled RSD at voxel lists keeps the scaled RSD's frame (relay grid);
     # the 3D NURSD keeps the uniform grid's lateral frame
     mode = {"srsd_points": "srsd", "grid3d": "grid"}.get(w.mode, w.mode)
     return choose_frame(mode, w.relay_xy, x0=g.x0, y0=g.y0, dx=g.dx, dy=g.dy, nx=g.nx,
-                        ny=g.ny, pad=w.pad)
+                        ny=g.ny, pad=w.pad, q=q)

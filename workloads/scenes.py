@@ -334,6 +334,20 @@ def config_batch(render: bool = True, n_scenes: int = 64, seed: int = 41) -> lis
     return out
 
 
+def tone_histograms(n_relay: int, n_time: int, bins, seed: int) -> np.ndarray:
+    """Histograms that are sums of sinusoids at the given DFT bins:
+    H[l][t] = sum_j Re(A_lj e^{+2 pi i b_j t / T}) with A_lj complex normal
+    (seeded), float32 [L][T].  Their temporal spectrum vanishes outside the
+    bins +-b_j, which restricts a reconstruction to those frequencies while
+    the input keeps the shape of a full measurement."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    bins = np.asarray(bins, dtype=np.int64)
+    A = rng.normal(size=(n_relay, len(bins))) + 1j * rng.normal(size=(n_relay, len(bins)))
+    t = np.arange(n_time, dtype=np.float64)
+    E = np.exp(2j * np.pi * np.outer(bins, t) / n_time)          # [J][T]
+    return np.ascontiguousarray((A @ E).real.astype(np.float32))
+
+
 def work_units(w: Workload) -> int:
     """Voxel-frequency propagations of one reconstruction."""
     if w.mode in ("points", "srsd_points"):
