@@ -87,27 +87,59 @@ def path_model_bytes(info: dict, w) -> float:
     return F * len(g.z) * (24.0 * M * M + 16.0 * M * N + 16.0 * N * N) + w.relay_xy.shape[0] * w.wavelet.n_time * 4.0
 
 
-def cpu_baseline(w, hist, threads: int) -> dict:
-    """Oracle (FP64, numpy) on 8 of the 96 frequencies and 8 of the 128 planes,
-    full 256x256 lateral window, phasor transform included."""
+def host_cpu() -> dict:
+    """CPU model, logical CPUs visible to this process, and the threads
+    numpy's BLAS (the oracle's matrix products) runs with."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        visible = len(os.sched_getaffinity(0))
+    except AttributeError:
+        visible = os.cpu_count() or 1
+    blas = None
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((p["num_threads"] for p in threadpool_info() if p.get("user_api") == "blas"), default=None)
+    except Exception:
+        blas = None
+    return {"model": model, "nproc": visible, "blas_threads": blas}
+
+
+def cpu_baseline(w, hist, reps: int = 3) -> dict:
+    """Oracle (FP64, numpy) on 4 of the 96 frequencies and 8 of the 128 planes,
+    full 256x256 lateral window, phasor transform included; median of `reps`
+    runs."""
     from oracle import nursd_ref as o
     from workloads import scenes
     wl = w.wavelet
     bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
-    sel_b = np.arange(4, 96, 12)[:8]
+    sel_b = np.array([10, 34, 58, 82])
     sel_z = np.arange(0, 128, 16)[:8]
     g = w.grid
     sub = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[sel_z])
     fr = o.frame_for_workload(w)
-    t = time.perf_counter()
-    wts = o.phasor_weights(f[sel_b], wl.lambda_c, wl.sigma_rel, wl.t0)
-    P = o.temporal_phasor(hist, bins[sel_b], wts)
-    o.nursd_grid(P, w.relay_xy.astype(np.float64), f[sel_b], fr, sub, w.xp)
-    dt = time.perf_counter() - t
+    times = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        wts = o.phasor_weights(f[sel_b], wl.lambda_c, wl.sigma_rel, wl.t0)
+        P = o.temporal_phasor(hist, bins[sel_b], wts)
+        o.nursd_grid(P, w.relay_xy.astype(np.float64), f[sel_b], fr, sub, w.xp)
+        times.append(time.perf_counter() - t)
+    dt = float(np.median(times))
     units = g.nx * g.ny * len(sel_z) * len(sel_b)
-    return {"value": units / dt, "unit": "voxel*freq/s", "cores": threads, "kind": "oracle",
+    cpu = host_cpu()
+    return {"value": units / dt, "unit": "voxel*freq/s", "cores": cpu["blas_threads"] or cpu["nproc"],
+            "kind": "oracle", "cpu_model": cpu["model"], "nproc": cpu["nproc"],
             "sample": f"{len(sel_b)} of 96 frequencies x {len(sel_z)} of 128 planes, full 256x256 window; "
-                      f"phasor DFT + direct NUDFT-1 + direct 2D DFTs in float64; {dt:.1f} s"}
+                      f"phasor DFT + direct NUDFT-1 + direct 2D DFTs in float64; median of {reps} runs "
+                      f"({', '.join(f'{x:.2f}' for x in times)} s)"}
 
 
 def time_ms(fn, reps: int) -> float:
@@ -234,7 +266,8 @@ def secondary(w_spad, dev) -> dict:
                       "plain_ms": round(t_plain, 3), "batched_ms": round(t_batch, 3),
                       "speedup": round(t_plain / t_batch, 4), "max_rel_l2_batched_vs_plain": err,
                       "voxel*freq/s": units / (t_batch * 1e-3),
-                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial")}}
+                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial")},
+                      "workspace_bytes": info["workspace_bytes"]}
     return out
 
 
@@ -252,11 +285,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()
 
 
-def load_traffic(stage: str):
-    """HBM bytes per launch of `stage` from the committed rocprofv3 counter
-    summary, if one exists and was taken on the current kernel sources
-    (else None)."""
-    path = os.path.join(ROOT, "profiles", f"{stage}_spad_counters.json")
+def load_counters(name: str):
+    """A committed rocprofv3 counter summary (profiles/<name>.json), if it
+    exists and was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{name}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -266,7 +298,14 @@ def load_traffic(stage: str):
         return None
     if d.get("kernel_source_sha256") != kernel_source_hash():
         return None
-    return d.get("hbm_bytes_per_launch")
+    return d
+
+
+def load_traffic(stage: str):
+    """HBM bytes per launch of `stage` (FETCH_SIZE and WRITE_SIZE, scaled by
+    the copy calibration), or None."""
+    d = load_counters(f"{stage}_spad_counters")
+    return None if d is None else d.get("hbm_bytes_per_launch")
 
 
 def copy_calibration(dev) -> None:
@@ -363,9 +402,20 @@ def main():
                              f"{args.steps} further steps run right after the timed ones")
     roof["algorithmic_per_launch"] = {"flop": flops / launches_per_step, "bytes": nbytes / launches_per_step}
     roof["other_bound"] = other
-    model = path_model_bytes(plan.info, w)
-    path = {"model_bytes_per_step": model, "effective_GBs": round(model / (ms * 1e-3) / 1e9, 1),
-            "frac_of_hbm": round(model / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+    # Whole-forward HBM traffic measured by rocprofv3 (sum over every
+    # dispatch of one forward), from the committed counter summary.
+    fwd = load_counters("spad_forward_hbm")
+    measured = None
+    if fwd is not None:
+        b = float(fwd["hbm_bytes_per_forward"])
+        measured = {"bytes_per_step": b, "GBs": round(b / (ms * 1e-3) / 1e9, 1),
+                    "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                    "source": "profiles/spad_forward_hbm_counters.md"}
+    # The survey's streaming model of the propagation (a figure of the model,
+    # not of the bytes this design moves: it counts a full M^2 kernel spectrum
+    # per plane where only the quadrant is stored).
+    model = {"bytes_per_step": path_model_bytes(plan.info, w),
+             "note": "streaming-model bytes (24M^2+16MN+16N^2 per plane + histogram); not measured traffic"}
 
     out = {
         "metric": "NURSD voxel*freq propagations/s at rel-L2<=1e-4; batched vs plain speedup",
@@ -386,7 +436,8 @@ def main():
                    "fft_size": plan.M, "complex": "c64 data, f64 phase arguments"},
         "stage_ms_per_step": {k: round(v[0], 4) for k, v in stages.items()},
         "roofline": roof,
-        "path_model_bandwidth": path,
+        "measured_hbm_whole_forward": measured,
+        "streaming_model": model,
     }
     if not args.no_secondary:
         del V, I
@@ -395,8 +446,7 @@ def main():
         out["batched_vs_plain_speedup"] = sec["batched"]["speedup"]
         out["secondary"] = sec
     if not args.no_cpu_baseline:
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        out["cpu_baseline"] = cpu_baseline(w, w.hist, threads)
+        out["cpu_baseline"] = cpu_baseline(w, w.hist)
     print(json.dumps(out), flush=True)
 
 

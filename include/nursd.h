@@ -70,6 +70,11 @@ typedef struct {
     double t0;            /* time of bin 0 [s]                                   */
     const int32_t* bins;  /* host array of F bins, or NULL for the centred band  */
     int32_t coherent;     /* 1: V = sum_b (...), I = |V|;  0: I = sum_b |F_b|     */
+    int32_t kernel_inv_r; /* 1: plane-to-plane kernel G = e^{+jkr} / r, as printed
+                             after eq. RSD_conv (nursd_default_options sets 1);
+                             0: G = e^{+jkr}, the unit-amplitude phase of
+                             eq. PF_RSD_Defn.  The illumination term has unit
+                             amplitude either way.                              */
 } nursd_wavelet;
 
 /* Output sampling.
@@ -128,6 +133,20 @@ typedef struct {
     int32_t M;           /* transform size, 0 = smallest that fits              */
     int32_t freq_chunk;  /* frequencies per propagation chunk, 0 = auto         */
     int32_t plane_chunk; /* planes per propagation chunk, 0 = auto              */
+    /* Internal grid pitch dx / q (q >= 1; 0 or 1 = the voxel pitch).  The
+     * standard RSD section samples the kernel at the relay rate; q > 1
+     * samples the relay frame and the kernel q times finer than the voxels
+     * (GRID, GRID3D: M >= pad * q * max(nx, ny); voxel (ix, iy) is grid point
+     * (ix q - (nx q)/2, iy q - (ny q)/2) around the frame centre
+     * c = (x0 + ((nx q)/2) dx / q, y0 + ((ny q)/2) dy / q); POINTS: FFT pitch
+     * dx / q).  SRSD modes need q = 1 (else UNSUPPORTED_SIZE).               */
+    int32_t upsample_q;
+    /* Optional per-sample weights w_l (device [L] float, e.g. quadrature or
+     * Voronoi areas; NULL = 1): every computation uses w_l P_l in place of
+     * P_l (eq. NURSD1 applies the type-1 sum to the weighted samples).  The
+     * weights are copied at plan creation; gradients (nursd_adjoint) are
+     * taken with respect to the unweighted P and positions. */
+    const float* weights_dev;
 } nursd_options;
 
 typedef struct nursd_plan nursd_plan;
@@ -149,27 +168,39 @@ typedef struct {
     int32_t freq_chunk;   /* frequencies per propagation launch               */
     int32_t plane_chunk;  /* depth planes per propagation launch              */
     int32_t depth3d;      /* depth size of the GRID3D stage-1 grid (else 0)   */
+    int32_t upsample_q;   /* internal grid pitch = voxel pitch / upsample_q   */
 } nursd_plan_info_t;
 
 /* Fill the structs with defaults (pad 2, sigma_os 2, tol 1e-6, coherent,
- * sigma_rel 0.2).  Never fails for non-NULL arguments. */
+ * kernel 1/r, sigma_rel 0.2, upsample_q 1, no weights).  Never fails for
+ * non-NULL arguments. */
 void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options* opt);
 
-/* Create a plan: validates the geometry, chooses the frame (smallest
- * supported M >= pad * max(nx, ny) with every relay and voxel inside the
- * period and every relay-voxel offset inside half a period), bins the relay
- * samples for spreading and builds the device tables.  relay_xy_dev: device
- * [L][2] float (metres).  Synchronises `stream` once to read the positions.
+/* Create a plan: validates the geometry, chooses the periodic frame, bins
+ * the relay samples for spreading and builds the device tables.
+ * The frame follows the standard RSD section (the FFT convolution is
+ * circular and needs zero padding, eq. Discrete_RSD_Conv) and the NUFFT
+ * rescaling of the Non-Uniform RSD section (x~ = 2 pi (x - c) / (M dx) in
+ * [-pi, pi)): M is the smallest supported size >= pad * q * max(nx, ny) with
+ * every relay and voxel inside the period and every relay-voxel offset
+ * strictly inside half a period.  The frequency bins follow the Gaussian
+ * band of eq. PFPacket_Omega_Supp.  relay_xy_dev: device [L][2] float
+ * (metres).  Synchronises `stream` once to read the positions (and weights).
  * Errors: ARG, GEOMETRY, UNSUPPORTED_SIZE, HIP. */
 int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo,
                       const nursd_options* opt, const float* relay_xy_dev,
                       void* stream, nursd_plan** out);
 
 /* Replace the relay positions (same L); re-bins them.  Fails with GEOMETRY
- * if a point leaves the plan's frame.  Synchronises `stream`. */
+ * (and keeps the previous positions) if a point leaves the plan's period or
+ * a relay-voxel offset reaches half a period, the frame rule of plan
+ * creation.  Synchronises `stream`. */
 int nursd_plan_set_points(nursd_plan* plan, const float* relay_xy_dev, void* stream);
 
+/* Facts of the frame and chunking chosen by nursd_plan_create. */
 int nursd_plan_info(const nursd_plan* plan, nursd_plan_info_t* info);
+/* Device workspace the compute calls of this plan need (bytes, to be
+ * 256-byte aligned); the caller allocates and owns it. */
 int nursd_workspace_size(const nursd_plan* plan, size_t* bytes);
 void nursd_plan_destroy(nursd_plan* plan);
 
@@ -243,35 +274,54 @@ int nursd_forward_multi(nursd_plan* plan, const void* P_dev, int32_t K, const do
 int nursd_subsample_nearest(const void* in_dev, void* out_dev, int32_t F, int32_t ny, int32_t nx, int32_t D,
                             void* stream);
 
-/* Batched serving of many reconstructions of uneven size (the plans may
- * differ in relay count, grid, frequency count, wavelength and transform
- * size).  All n plans (coherent GRID mode, T a power of two, evenly spaced
- * frequency bins) run as one HIP
- * graph of grouped persistent kernels: each launch serves every plan of one
- * kernel type and size class, pulling work items from a device queue.
- * nursd_batch_create copies nothing and launches nothing; the plans must
- * outlive the batch.  The temporal transform, spreading and fine-grid
- * passes of all plans are grouped launches; plans with a transform size
- * below a threshold are also propagated by grouped launches, in R rounds
- * each covering about 1/R of every such plan's planes, while larger plans
- * are propagated chunk by chunk with ordinary launches inside the graph.
- * Grouped launches run in one of three schedules: persistent workgroups fed
- * by a device work queue, persistent workgroups with a static stride, or
- * one workgroup per work block.  With autotune = 1 the first
- * nursd_batch_forward times (threshold, schedule, R) candidates on the real
- * inputs and keeps the fastest; otherwise the work-queue schedule, threshold
- * 512 and the smallest R whose scratch fits 24 GiB are used.
+/* Batched serving of many reconstructions of uneven size (not in the
+ * paper: many phasor-field reconstructions, each eq. NURSD1 with the volume
+ * of eq. PF_RSD_Defn, served together).  The plans may differ in relay
+ * count, grid, frequency count, wavelength and transform size; all n plans
+ * must be coherent GRID plans with T a power of two and evenly spaced
+ * frequency bins.  Their reconstructions run as one HIP graph of grouped
+ * persistent kernels: each grouped launch serves every plan of one kernel
+ * type and size class, pulling work items from a device queue.  The
+ * temporal transform, spreading and fine-grid passes of all plans are
+ * grouped launches; plans with a transform size below a threshold are also
+ * propagated by grouped launches, in R rounds each covering about 1/R of
+ * every such plan's planes, while larger plans are propagated chunk by
+ * chunk with ordinary launches inside the graph.  Grouped launches run in
+ * one of three schedules: persistent workgroups fed by a device work queue,
+ * persistent workgroups with a static stride, or one workgroup per work
+ * block.
+ *
+ * nursd_batch_create validates the plans, picks the default configuration
+ * (work queue, threshold 512, the fewest rounds whose propagation scratch
+ * fits 24 GiB) and allocates the batch's small device tables (work-item
+ * tables sized for every configuration it may use, one queue counter per
+ * grouped launch) and a pinned staging buffer; it launches nothing.  The
+ * plans must outlive the batch.
+ * nursd_batch_workspace_size: device workspace (256-byte aligned, owned by
+ * the caller) that nursd_batch_forward and nursd_batch_autotune need; it
+ * holds every plan's intermediates at once and, for a batch created with
+ * autotune = 1, covers every configuration the tuner may pick.
+ * nursd_batch_autotune (autotune = 1 batches only): times every candidate
+ * configuration (threshold 256 / 512 / none x schedule x the two fewest
+ * rounds whose grouped scratch fits 32 GiB) on the given inputs and keeps
+ * the fastest.  It synchronises `stream`, like plan creation.
  * nursd_batch_forward: hist_dev[i] = [L_i][T_i] histograms of plan i,
- * I_dev[i] = [nz][ny][nx] intensity of plan i (float).  The first call
- * builds the workspace (owned by the batch), captures the graph and
- * synchronises `stream`; later calls with the same pointers launch the graph
- * only, new pointers re-upload the work tables (one synchronising copy).
- * The batch workspace holds every plan's intermediates at once. */
+ * I_dev[i] = [nz][ny][nx] intensity of plan i (float).  It allocates
+ * nothing and does not synchronise: when the histogram, output or
+ * workspace pointers differ from the previous call's, it rebuilds the work
+ * tables on the host, copies them to the batch's table buffer on `stream`
+ * (waiting only until this batch's previous table copy has left the pinned
+ * staging buffer) and captures a new graph; then it launches the graph on
+ * `stream`.  Calls on one batch must be ordered (one stream, or ordered by
+ * the caller), since they share its table buffer and queue counters. */
 int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream,
                        nursd_batch** out);
-int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev,
-                        void* stream);
-/* Chosen configuration (R + 1000 * schedule + 10000 * threshold code;
+int nursd_batch_workspace_size(const nursd_batch* batch, size_t* bytes);
+int nursd_batch_autotune(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev, void* ws_dev,
+                         size_t ws_bytes, void* stream);
+int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev, void* ws_dev,
+                        size_t ws_bytes, void* stream);
+/* Configuration in use (R + 1000 * schedule + 10000 * threshold code;
  * schedule 0 = work queue, 1 = static stride, 2 = one workgroup per block;
  * threshold code 0 = none chunk by chunk, 1 = M >= 256, 2 = M >= 512),
  * number of launch records in the graph, the autotuner's candidates (same

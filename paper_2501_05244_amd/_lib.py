@@ -31,6 +31,7 @@ class Wavelet(ctypes.Structure):
     _fields_ = [
         ("lambda_c", c_double), ("sigma_rel", c_double), ("n_freq", c_int32), ("n_time", c_int32),
         ("dt", c_double), ("t0", c_double), ("bins", POINTER(c_int32)), ("coherent", c_int32),
+        ("kernel_inv_r", c_int32),
     ]
 
 
@@ -48,6 +49,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("n_relay", c_int32), ("pad", c_double), ("sigma_os", c_double), ("tol", c_double),
         ("M", c_int32), ("freq_chunk", c_int32), ("plane_chunk", c_int32),
+        ("upsample_q", c_int32), ("weights_dev", c_void_p),
     ]
 
 
@@ -57,6 +59,7 @@ class PlanInfo(ctypes.Structure):
         ("kernel_width", c_int32), ("n_voxels", c_int32), ("dx", c_double), ("dy", c_double),
         ("cx", c_double), ("cy", c_double), ("beta", c_double), ("workspace_bytes", c_size_t),
         ("freq_chunk", c_int32), ("plane_chunk", c_int32), ("depth3d", c_int32),
+        ("upsample_q", c_int32),
     ]
 
 
@@ -83,7 +86,11 @@ SIGNATURES = {
                                       c_size_t, c_void_p]),
     "nursd_subsample_nearest": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, c_int32, c_void_p]),
     "nursd_batch_create": (c_int32, [POINTER(c_void_p), c_int32, c_int32, c_void_p, POINTER(c_void_p)]),
-    "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]),
+    "nursd_batch_workspace_size": (c_int32, [c_void_p, POINTER(c_size_t)]),
+    "nursd_batch_autotune": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t,
+                                       c_void_p]),
+    "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t,
+                                      c_void_p]),
     "nursd_batch_destroy": (None, [c_void_p]),
     "nursd_batch_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_float), POINTER(c_size_t)]),

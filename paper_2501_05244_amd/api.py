@@ -45,7 +45,7 @@ class Plan:
                  bins=None, coherent=True, sigma_rel=0.2, pad=2.0, tol=1e-6, M=0, freq_chunk=0,
                  plane_chunk=0, xp=(0.0, 0.0, 0.0), zref=0.0, alpha=None, plane_ptr=None,
                  voxel_xy: torch.Tensor | None = None, relay_z: torch.Tensor | None = None, z_mid=0.0, dz3=0.0,
-                 mz3=0, stream=None):
+                 mz3=0, kernel_inv_r=True, upsample_q=1, weights: torch.Tensor | None = None, stream=None):
         self._lib = _lib.load()
         self.handle = None
         L = relay_xy.shape[0]
@@ -60,6 +60,7 @@ class Plan:
         wl.lambda_c, wl.n_time, wl.dt, wl.t0, wl.n_freq = lambda_c, n_time, dt, t0, n_freq
         wl.sigma_rel = sigma_rel
         wl.coherent = 1 if coherent else 0
+        wl.kernel_inv_r = 1 if kernel_inv_r else 0
         self._keep = []
         if bins is not None:
             b = np.ascontiguousarray(bins, dtype=np.int32)
@@ -95,6 +96,10 @@ class Plan:
         opt.n_relay = L
         opt.pad, opt.tol, opt.M = pad, tol, M
         opt.freq_chunk, opt.plane_chunk = freq_chunk, plane_chunk
+        opt.upsample_q = int(upsample_q)
+        if weights is not None:
+            _need(weights, torch.float32, (L,), "weights")
+            opt.weights_dev = weights.data_ptr()      # copied by nursd_plan_create
         h = c_void_p()
         check(self._lib.nursd_plan_create(byref(wl), byref(geo), byref(opt), _ptr(relay_xy), _stream(stream),
                                           byref(h)), "nursd_plan_create")
@@ -146,8 +151,21 @@ class Plan:
     # ------------------------------------------------------------ entry points
     def set_points(self, relay_xy: torch.Tensor, stream=None):
         _need(relay_xy, torch.float32, (self.L, 2), "relay_xy")
+        # whatever tensor autograd bound before no longer describes the plan
+        self._bound_xy = None
         check(self._lib.nursd_plan_set_points(self.handle, _ptr(relay_xy), _stream(stream)),
               "nursd_plan_set_points")
+
+    def bind_points(self, relay_xy: torch.Tensor, stream=None):
+        """Make the plan use the positions held in `relay_xy` (a [L][2]
+        float tensor, any device-resident layout), re-binning only when the
+        plan is not already bound to this very tensor at its current version
+        (autograd calls this for every forward and backward)."""
+        bound = getattr(self, "_bound_xy", None)
+        if bound is not None and bound[0] is relay_xy and bound[1] == relay_xy._version:
+            return
+        self.set_points(relay_xy.detach().contiguous(), stream)
+        self._bound_xy = (relay_xy, relay_xy._version)
 
     def phasor(self, hist: torch.Tensor, stream=None) -> torch.Tensor:
         _need(hist, torch.float32, (self.L, self.n_time), "hist")
@@ -253,16 +271,27 @@ def subsample_nearest(P: torch.Tensor, D: int, stream=None) -> torch.Tensor:
 
 class Batch:
     """Many GRID plans served by one captured graph of grouped persistent
-    kernels (C handle nursd_batch)."""
+    kernels (C handle nursd_batch).  The workspace is a torch allocation
+    owned by this object; with autotune the first forward first times the
+    candidate configurations (nursd_batch_autotune, which synchronises)."""
 
     def __init__(self, plans: list[Plan], autotune: bool = True, stream=None):
         self._lib = _lib.load()
         self.plans = list(plans)
+        self.autotune = bool(autotune)
+        self._tuned = False
         arr = (c_void_p * len(plans))(*[p.handle.value for p in plans])
         h = c_void_p()
         check(self._lib.nursd_batch_create(arr, len(plans), 1 if autotune else 0, _stream(stream), byref(h)),
               "nursd_batch_create")
         self.handle = h
+        n = c_size_t()
+        check(self._lib.nursd_batch_workspace_size(self.handle, byref(n)), "nursd_batch_workspace_size")
+        self.workspace_bytes = n.value
+        dev = plans[0].device
+        self._ws = torch.empty(self.workspace_bytes + 256, dtype=torch.uint8, device=dev)
+        base = self._ws.data_ptr()
+        self._ws_ptr = base + (-base) % 256
 
     def __del__(self):
         if getattr(self, "handle", None):
@@ -280,7 +309,11 @@ class Batch:
         self._keep = (list(hists), list(outs))
         hp = (c_void_p * len(hists))(*[h.data_ptr() for h in hists])
         op = (c_void_p * len(outs))(*[o.data_ptr() for o in outs])
-        check(self._lib.nursd_batch_forward(self.handle, hp, op, _stream(stream)), "nursd_batch_forward")
+        ws, n = c_void_p(self._ws_ptr), c_size_t(self.workspace_bytes)
+        if self.autotune and not self._tuned:
+            check(self._lib.nursd_batch_autotune(self.handle, hp, op, ws, n, _stream(stream)), "nursd_batch_autotune")
+            self._tuned = True
+        check(self._lib.nursd_batch_forward(self.handle, hp, op, ws, n, _stream(stream)), "nursd_batch_forward")
         return outs
 
     def info(self) -> dict:

@@ -6,6 +6,14 @@ The backward calls nursd_adjoint, which recomputes every per-frequency
 quantity (no forward state is kept besides P and the positions): it returns
 the gradient with respect to the complex phasors P and, when relay_xy
 requires grad, with respect to the relay positions.
+
+The plan holds one set of relay positions at a time.  Each forward binds
+the positions it was given, and each backward binds the positions saved by
+its own forward; a plan that already holds that very tensor at its current
+version is not re-binned.  Interleaved forwards with different positions
+are therefore each differentiated at their own positions, and autograd's
+saved-tensor version check rejects positions changed in place between a
+forward and its backward.
 """
 from __future__ import annotations
 
@@ -17,10 +25,7 @@ from .api import Plan
 class NURSDFunction(torch.autograd.Function):
     @staticmethod
     def forward(ctx, P: torch.Tensor, relay_xy: torch.Tensor, plan: Plan):
-        key = (relay_xy.data_ptr(), relay_xy._version)
-        if getattr(plan, "_points_key", None) != key:
-            plan.set_points(relay_xy.detach().contiguous())
-            plan._points_key = key
+        plan.bind_points(relay_xy)
         V, _ = plan.forward_phasor(P.detach().contiguous(), intensity=False)
         ctx.save_for_backward(P, relay_xy)
         ctx.plan = plan
@@ -29,6 +34,7 @@ class NURSDFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gV: torch.Tensor):
         P, relay_xy = ctx.saved_tensors
+        ctx.plan.bind_points(relay_xy)
         want_xy = ctx.needs_input_grad[1]
         gP, gxy = ctx.plan.adjoint(gV.contiguous(), P.detach().contiguous() if want_xy else None)
         return (gP if ctx.needs_input_grad[0] else None), (gxy if want_xy else None), None

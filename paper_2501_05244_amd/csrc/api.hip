@@ -94,6 +94,7 @@ double es_psi(double z, double beta) {
 struct nursd_plan {
     // wavelet
     int F = 0, T = 0, coherent = 1;
+    int kernel_inv_r = 1;           // G = e^{jkr}/r (1) or e^{jkr} (0)
     double lambda_c = 0, sigma_rel = 0.2, dt = 0, t0 = 0;
     std::vector<int> bins;
     std::vector<double> freqs;
@@ -113,6 +114,9 @@ struct nursd_plan {
     int w = 7;
     double beta = 0;
     double pad = 2.0;
+    int q = 1;                      // internal grid pitch = voxel pitch / q
+    double vlo[2] = {0, 0}, vhi[2] = {0, 0};   // voxel bounds (frame rule of set_points)
+    float* d_w = nullptr;           // [L] per-sample weights or NULL
     // chunking
     int FC = 8, ZC = 16, FCn = 16;
     int BS = 0;
@@ -465,6 +469,19 @@ ChunkGeom chunk_geom(const nursd_plan* p, int b0, int nb, int z0, int nzc) {
     return g;
 }
 
+// Argument blocks of the three propagation passes.
+P1Args kernel_args(const nursd_plan* p, const ChunkGeom& g, float2* Bt) {
+    P1Args a{g, Bt, p->M, p->BS, p->tw(p->M)};
+    a.plain = p->kernel_inv_r ? 0 : 1;
+    return a;
+}
+
+P2Args cols_args(const nursd_plan* p, const ChunkGeom& g, const float2* Bt, const float2* U, float2* Yt) {
+    P2Args a{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+    a.q = p->q;
+    return a;
+}
+
 // Type-1 NUFFT of n rows of P ([n][L], n = F by default) -> U [n][M][M].
 int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_t s, int n = -1) {
     if (n < 0) n = p->F;
@@ -472,6 +489,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
         const int nb = std::min(p->FCn, n - b0);
         SpreadArgs sa{};
         sa.P = P;
+        sa.wts = p->d_w;
         sa.ent = p->d_ent;
         sa.band_ptr = p->d_band_ptr;
         sa.wave_rng = p->d_wave_rng;
@@ -511,9 +529,9 @@ int run_grid_propagation(nursd_plan* p, const float2* U, float2* V, float* I, ch
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
-            P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+            P2Args a2 = cols_args(p, g, Bt, U, Yt);
             LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
             P3Args a3 = rows_args(p, g, Yt, V, I, b0, nb);
             LAUNCH(p, NURSD_STAGE_PROPAGATE_ROWS, P3Args, launch_propagate_rows, a3, s);
@@ -540,6 +558,7 @@ P3Args rows_args(const nursd_plan* p, const ChunkGeom& g, const float2* Yt, floa
     a3.last = b0 + nb >= p->F;
     a3.coherent = p->coherent;
     a3.tw = p->tw(p->M);
+    a3.q = p->q;
     return a3;
 }
 
@@ -562,7 +581,7 @@ int run_srsd(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hipS
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             ChirpArgs ca{};
             ca.g = g;
@@ -598,7 +617,7 @@ int run_points(nursd_plan* p, const float2* U, float2* V, float* I, char* ws, hi
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             Type2Args t = type2_args(p, g, Bt, U, V, I, ws, b0, nb);
             LAUNCH(p, NURSD_STAGE_TYPE2, Type2Args, launch_type2, t, s);
@@ -667,7 +686,7 @@ int run_srsd_points(nursd_plan* p, const float2* U, float2* V, float* I, char* w
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             ChirpArgs ca{};
             ca.g = g;
@@ -710,8 +729,8 @@ int run_stage1_3d(nursd_plan* p, const float2* P, float2* U0, char* ws, hipStrea
         ChunkGeom g = chunk_geom(p, b0, nb, 0, p->Mz3);
         g.z = p->d_zk3;
         g.pitch_x = g.pitch_y = nullptr;
-        P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
-        a1.plain = 1;
+        P1Args a1 = kernel_args(p, g, Bt);
+        a1.plain = 1;                      // the 3D-RSD kernel e^{+jkr} (no 1/r)
         LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
         Stage1Args sa{g, Bt, Ut, U0, p->M, p->BS, p->Mz3, p->tw(p->M)};
         LAUNCH(p, NURSD_STAGE_NURSD3D, Stage1Args, launch_stage1_reduce, sa, s);
@@ -752,6 +771,17 @@ hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
 
 enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL };
 
+// One configuration of the batched launch sequence.
+struct BatchConfig {
+    int rounds = 4;            // propagation rounds R of the grouped scenes
+    int sched = kQueue;        // grouped-launch schedule (kQueue, kStatic, kFlat)
+    int serial_min_m = 512;    // scenes with M >= this are propagated chunk by chunk
+};
+
+int config_code(const BatchConfig& c) {
+    return c.rounds + 1000 * c.sched + 10000 * (c.serial_min_m == 256 ? 1 : c.serial_min_m == 512 ? 2 : 0);
+}
+
 struct BatchScene {
     nursd_plan* p = nullptr;
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0;
@@ -764,38 +794,42 @@ struct BatchLaunch {
     int half = 0;                                    // row pass: every window within M/2
     int scene = -1;                                  // BK_SERIAL: scene propagated with ordinary launches
     size_t items = 0, prefix = 0, gridx = 0, item_of = 0;   // byte offsets in the table buffer
-    int n = 0, total = 0, counter = 0;
+    int n = 0, total = 0, counter = -1;
 };
 
 struct nursd_batch {
     std::vector<BatchScene> sc;
     int autotune = 0;
-    int budget = 0;                 // propagation rounds R (0 = not chosen yet)
-    int sched = kFlat;              // grouped-launch schedule (kQueue, kStatic, kFlat)
-    int serial_min_m = 512;         // scenes with M >= this are propagated chunk by chunk
-    size_t off_serial_Bt = 0, off_serial_Yt = 0;
-    std::vector<int> tried;         // candidate budgets and their times
+    BatchConfig cfg;                 // configuration in use
+    std::vector<BatchConfig> cands;  // configurations the tuner times
+    std::vector<int> tried;          // timed candidates (config_code) and their times
     std::vector<float> tried_ms;
-    char* ws = nullptr;
-    size_t ws_bytes = 0;
+    size_t ws_need = 0;              // caller workspace: covers every candidate
+    size_t off_serial_Bt = 0, off_serial_Yt = 0;
+    // pointers the captured graph was built for
+    bool ready = false;
+    const char* ws = nullptr;
+    std::vector<const float*> hist;
+    std::vector<float*> I;
+    // small device tables owned by the batch, sized at creation for every candidate
     char* d_tab = nullptr;
     size_t tab_cap = 0;
-    void* pinned = nullptr;
-    size_t pinned_cap = 0;
+    void* pinned = nullptr;          // staging buffer of the table upload
+    hipEvent_t upload_done = nullptr;
+    bool upload_pending = false;
     std::vector<char> tab;
     int* d_counters = nullptr;
     int counters_cap = 0;
+    int n_counters = 0;              // work-queue counters in use (one per grouped launch)
     std::vector<BatchLaunch> launches;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    std::vector<const float*> hist;
-    std::vector<float*> I;
     ~nursd_batch() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
         if (cap) (void)hipStreamDestroy(cap);
-        if (ws) (void)hipFree(ws);
+        if (upload_done) (void)hipEventDestroy(upload_done);
         if (d_tab) (void)hipFree(d_tab);
         if (pinned) (void)hipHostFree(pinned);
         if (d_counters) (void)hipFree(d_counters);
@@ -816,36 +850,35 @@ size_t tab_push(std::vector<char>& tab, const std::vector<T>& v) {
 // about 1/R of every scene's planes.
 int batch_zc(const nursd_plan* p, int rounds) { return std::max(1, (p->nz + rounds - 1) / rounds); }
 
-constexpr size_t kBatchScratchCap = 96ull << 30;      // propagation scratch limit for candidates
-constexpr size_t kBatchScratchDefault = 24ull << 30;  // default without autotuning
+constexpr size_t kBatchScratchCap = 32ull << 30;      // propagation scratch limit of a tuner candidate
+constexpr size_t kBatchScratchDefault = 24ull << 30;  // default configuration without tuning
 
-size_t batch_scratch_bytes(const nursd_batch* bt, int rounds) {
+// Propagation scratch of the scenes propagated by grouped launches.
+size_t batch_scratch_bytes(const nursd_batch* bt, int rounds, int serial_min_m) {
     size_t t = 0;
     for (const auto& sc : bt->sc) {
         const nursd_plan* p = sc.p;
+        if (p->M >= serial_min_m) continue;
         const size_t zc = (size_t)batch_zc(p, rounds);
         t += (size_t)p->F * zc * ((size_t)(p->M / 2 + 1) * p->BS + (size_t)p->ny * p->M) * sizeof(float2);
     }
     return t;
 }
 
-// Workspace layout, item tables and launch list for `budget`, with the
-// current input / output pointers baked into the items.
-int batch_build(nursd_batch* bt, int budget) {
+// Workspace layout of configuration c (sets the scene offsets); returns its bytes.
+size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
     size_t o = 0;
     const size_t c8 = sizeof(float2);
-    int max_rounds = 0;
     size_t serial_bt = 0, serial_yt = 0;
     for (auto& sc : bt->sc) {
         nursd_plan* p = sc.p;
-        sc.serial = p->M >= bt->serial_min_m;
+        sc.serial = p->M >= c.serial_min_m;
         if (sc.serial) {
             serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
             serial_yt = std::max(serial_yt, (size_t)p->FC * p->ZC * p->ny * p->M * c8);
         }
-        sc.ZC = batch_zc(p, budget);
+        sc.ZC = batch_zc(p, c.rounds);
         sc.rounds = sc.serial ? 0 : (p->nz + sc.ZC - 1) / sc.ZC;
-        max_rounds = std::max(max_rounds, sc.rounds);
         sc.off_P = o;
         o = align_up(o + (size_t)p->F * p->L * c8);
         sc.off_T1 = o;
@@ -865,19 +898,20 @@ int batch_build(nursd_batch* bt, int budget) {
     o = align_up(o + serial_bt);
     bt->off_serial_Yt = o;
     o = align_up(o + serial_yt);
-    if (o > bt->ws_bytes) {
-        if (bt->ws) HIP_TRY(hipFree(bt->ws));
-        bt->ws = nullptr;
-        void* d = nullptr;
-        HIP_TRY(hipMalloc(&d, o));
-        bt->ws = static_cast<char*>(d);
-        bt->ws_bytes = o;
-    }
-    char* ws = bt->ws;
+    return o;
+}
+
+// Host side only: item tables and launch list of configuration c with the
+// workspace at ws_base and the bound histogram / output pointers baked into
+// the items.  Allocates nothing on the device.
+void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
+    batch_layout(bt, c);
+    char* ws = reinterpret_cast<char*>(ws_base);
     bt->tab.clear();
     bt->launches.clear();
+    int max_rounds = 0;
+    for (const auto& sc : bt->sc) max_rounds = std::max(max_rounds, sc.rounds);
     int counter = 0;
-    // one grouped launch per (kind, size class) over the given items
     // one grouped launch per (kind, size class); items are ordered by
     // descending work so the largest are dequeued first
     auto add = [&](int kind, int size, int fmax, auto& items_in, std::vector<int>& gx_in, std::vector<int>& gy_in,
@@ -929,7 +963,7 @@ int batch_build(nursd_batch* bt, int budget) {
             nursd_plan* p = bt->sc[i].p;
             if (p->T != T) continue;
             PhasorArgs a{};
-            a.hist = bt->hist[i];
+            a.hist = bt->hist.empty() ? nullptr : bt->hist[i];
             a.P = reinterpret_cast<float2*>(ws + bt->sc[i].off_P);
             a.L = p->L;
             a.T = p->T;
@@ -957,6 +991,7 @@ int batch_build(nursd_batch* bt, int budget) {
             if (p->Mf != Mf) continue;
             SpreadArgs a{};
             a.P = reinterpret_cast<float2*>(ws + sc.off_P);
+            a.wts = p->d_w;
             a.ent = p->d_ent;
             a.band_ptr = p->d_band_ptr;
             a.wave_rng = p->d_wave_rng;
@@ -1002,7 +1037,7 @@ int batch_build(nursd_batch* bt, int budget) {
             std::vector<double> w12, w3;
             bool half = true;       // one row-pass variant per launch: every window within M/2
             for (const BatchScene& sc : bt->sc)
-                if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx <= M;
+                if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx * sc.p->q <= M;
             for (size_t i = 0; i < bt->sc.size(); ++i) {
                 BatchScene& sc = bt->sc[i];
                 nursd_plan* p = sc.p;
@@ -1012,13 +1047,13 @@ int batch_build(nursd_batch* bt, int budget) {
                 float2* Bt = reinterpret_cast<float2*>(ws + sc.off_Bt);
                 float2* Yt = reinterpret_cast<float2*>(ws + sc.off_Yt);
                 const float2* U = reinterpret_cast<const float2*>(ws + sc.off_U);
-                i1.push_back(P1Args{g, Bt, p->M, p->BS, p->tw(p->M)});
+                i1.push_back(kernel_args(p, g, Bt));
                 g1x.push_back(grid_x_kernel_rows(M));
                 g1y.push_back(p->F * nzc);
-                i2.push_back(P2Args{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)});
+                i2.push_back(cols_args(p, g, Bt, U, Yt));
                 g2x.push_back(grid_x_propagate_cols(M));
                 g2y.push_back(p->F * nzc);
-                P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I[i], 0, p->F);
+                P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I.empty() ? nullptr : bt->I[i], 0, p->F);
                 i3.push_back(a3);
                 const int rb = rows_per_block_propagate(M, half);
                 g3x.push_back((p->ny + rb - 1) / rb);
@@ -1048,36 +1083,14 @@ int batch_build(nursd_batch* bt, int budget) {
             bt->launches.push_back(L);
         }
     }
-    // upload the tables through pinned staging (same device buffer if it fits)
-    const size_t nb = bt->tab.size();
-    if (nb > bt->tab_cap) {
-        if (bt->d_tab) HIP_TRY(hipFree(bt->d_tab));
-        void* d = nullptr;
-        HIP_TRY(hipMalloc(&d, nb));
-        bt->d_tab = static_cast<char*>(d);
-        bt->tab_cap = nb;
-    }
-    if (nb > bt->pinned_cap) {
-        if (bt->pinned) HIP_TRY(hipHostFree(bt->pinned));
-        HIP_TRY(hipHostMalloc(&bt->pinned, nb, hipHostMallocDefault));
-        bt->pinned_cap = nb;
-    }
-    if (counter > bt->counters_cap) {
-        if (bt->d_counters) HIP_TRY(hipFree(bt->d_counters));
-        void* d = nullptr;
-        HIP_TRY(hipMalloc(&d, (size_t)counter * sizeof(int)));
-        bt->d_counters = static_cast<int*>(d);
-        bt->counters_cap = counter;
-    }
-    return NURSD_OK;
+    bt->n_counters = counter;
 }
 
-int batch_upload(nursd_batch* bt, hipStream_t s) {
-    std::memcpy(bt->pinned, bt->tab.data(), bt->tab.size());
-    HIP_TRY(hipMemcpyAsync(bt->d_tab, bt->pinned, bt->tab.size(), hipMemcpyHostToDevice, s));
-    // the staging buffer is reused by the next upload only after this copy
-    HIP_TRY(hipStreamSynchronize(s));
-    return NURSD_OK;
+// Table bytes and counters configuration c needs.
+void batch_table_size(nursd_batch* bt, const BatchConfig& c, size_t* tab_bytes, int* counters) {
+    batch_tables(bt, c, kAlign);
+    *tab_bytes = bt->tab.size();
+    *counters = bt->n_counters;
 }
 
 template <typename A>
@@ -1090,17 +1103,22 @@ Group<A> group_of(nursd_batch* bt, const BatchLaunch& L) {
     g.n = L.n;
     g.total = L.total;
     g.counter = bt->d_counters + L.counter;
-    g.mode = bt->sched;
+    g.mode = bt->cfg.sched;
     return g;
 }
 
 int batch_enqueue(nursd_batch* bt, hipStream_t s) {
-    HIP_TRY(launch_zero_counters(bt->d_counters, (int)bt->launches.size(), s));
+    // One work-queue counter per grouped launch; scenes propagated with
+    // ordinary launches have none.
+    for (const BatchLaunch& L : bt->launches)
+        if (L.kind != BK_SERIAL && (L.counter < 0 || L.counter >= bt->n_counters || bt->n_counters > bt->counters_cap))
+            return fail(NURSD_ERR_ARG, "batch launch table refers to a counter outside the counter buffer");
+    if (bt->n_counters > 0) HIP_TRY(launch_zero_counters(bt->d_counters, bt->n_counters, s));
+    char* ws = const_cast<char*>(bt->ws);
     for (const BatchLaunch& L : bt->launches) {
         if (L.kind == BK_SERIAL) {
             const BatchScene& sc = bt->sc[L.scene];
             nursd_plan* p = sc.p;
-            char* ws = bt->ws;
             float2* Bt = reinterpret_cast<float2*>(ws + bt->off_serial_Bt);
             float2* Yt = reinterpret_cast<float2*>(ws + bt->off_serial_Yt);
             const float2* U = reinterpret_cast<const float2*>(ws + sc.off_U);
@@ -1110,8 +1128,8 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s) {
                 for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
                     const int nzc = std::min(p->ZC, p->nz - z0);
                     const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-                    HIP_TRY(launch_kernel_rows(P1Args{g, Bt, p->M, p->BS, p->tw(p->M)}, s));
-                    HIP_TRY(launch_propagate_cols(P2Args{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)}, s));
+                    HIP_TRY(launch_kernel_rows(kernel_args(p, g, Bt), s));
+                    HIP_TRY(launch_propagate_cols(cols_args(p, g, Bt, U, Yt), s));
                     HIP_TRY(launch_propagate_rows(rows_args(p, g, Yt, V, bt->I[L.scene], b0, nb), s));
                 }
             }
@@ -1148,15 +1166,50 @@ int batch_capture(nursd_batch* bt) {
     return NURSD_OK;
 }
 
-// Build, warm up (uncaptured run: sets kernel attributes), capture.
-int batch_prepare(nursd_batch* bt, int budget, int sched, hipStream_t s) {
-    bt->sched = sched;
-    int rc = batch_build(bt, budget);
+// Tables of the current configuration for the given workspace and the bound
+// histogram / output pointers: built on the host, copied to the batch's
+// device table buffer on `s` through the pinned staging buffer (the host
+// waits only for this batch's previous table copy to leave the staging
+// buffer), then the launch sequence is captured as a graph.
+int batch_bind(nursd_batch* bt, const char* ws, hipStream_t s) {
+    batch_tables(bt, bt->cfg, reinterpret_cast<uintptr_t>(ws));
+    if (bt->tab.size() > bt->tab_cap || bt->n_counters > bt->counters_cap)
+        return fail(NURSD_ERR_ARG, "batch tables exceed the buffers sized at creation");
+    if (bt->upload_pending) HIP_TRY(hipEventSynchronize(bt->upload_done));
+    if (!bt->tab.empty()) {
+        std::memcpy(bt->pinned, bt->tab.data(), bt->tab.size());
+        HIP_TRY(hipMemcpyAsync(bt->d_tab, bt->pinned, bt->tab.size(), hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(bt->upload_done, s));
+        bt->upload_pending = true;
+    }
+    bt->ws = ws;
+    bt->ready = false;
+    int rc = batch_capture(bt);
     if (rc) return rc;
-    if ((rc = batch_upload(bt, s))) return rc;
-    if ((rc = batch_enqueue(bt, s))) return rc;
-    HIP_TRY(hipStreamSynchronize(s));
-    return batch_capture(bt);
+    bt->ready = true;
+    return NURSD_OK;
+}
+
+int batch_check_io(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+                   bool* changed) {
+    if (!hist || !I) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (!ws) return fail(NURSD_ERR_WORKSPACE, "workspace pointer is NULL");
+    if (((uintptr_t)ws) % kAlign) return fail(NURSD_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < bt->ws_need)
+        return fail(NURSD_ERR_WORKSPACE, "batch workspace too small: need " + std::to_string(bt->ws_need) + " bytes");
+    const int n = (int)bt->sc.size();
+    for (int i = 0; i < n; ++i) {
+        if (!hist[i] || !I[i]) return fail(NURSD_ERR_ARG, "NULL histogram or output pointer");
+        if (reinterpret_cast<uintptr_t>(hist[i]) & 7) return fail(NURSD_ERR_ARG, "histograms must be 8-byte aligned");
+    }
+    bool ch = !bt->ready || bt->ws != ws;
+    for (int i = 0; i < n; ++i) {
+        if (hist[i] != bt->hist[i] || I[i] != bt->I[i]) ch = true;
+        bt->hist[i] = hist[i];
+        bt->I[i] = I[i];
+    }
+    *changed = ch;
+    return NURSD_OK;
 }
 
 }  // namespace
@@ -1168,6 +1221,7 @@ void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options
         std::memset(wl, 0, sizeof(*wl));
         wl->sigma_rel = 0.2;
         wl->coherent = 1;
+        wl->kernel_inv_r = 1;
     }
     if (geo) std::memset(geo, 0, sizeof(*geo));
     if (opt) {
@@ -1175,6 +1229,7 @@ void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options
         opt->pad = 2.0;
         opt->sigma_os = 2.0;
         opt->tol = 1e-6;
+        opt->upsample_q = 1;
     }
 }
 
@@ -1199,6 +1254,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     p->dt = wl->dt;
     p->t0 = wl->t0;
     p->coherent = wl->coherent ? 1 : 0;
+    p->kernel_inv_r = wl->kernel_inv_r ? 1 : 0;
     const double df = 1.0 / (p->T * p->dt);
     const double fc = kC / p->lambda_c;
     if (wl->bins) {
@@ -1237,6 +1293,10 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     const double tol = opt->tol > 0 ? opt->tol : 1e-6;
     p->w = std::min(8, std::max(2, (int)std::ceil(std::log10(1.0 / tol)) + 1));
     p->beta = 2.30 * p->w;
+    p->q = opt->upsample_q > 0 ? opt->upsample_q : 1;
+    if (p->q > 16) return bail(fail(NURSD_ERR_ARG, "upsample_q must be in [1, 16]"));
+    if (p->q > 1 && (p->mode == NURSD_MODE_SRSD || p->mode == NURSD_MODE_SRSD_POINTS))
+        return bail(fail(NURSD_ERR_UNSUPPORTED_SIZE, "the scaled RSD needs upsample_q = 1"));
 
     std::vector<float> rxy;
     int rc = read_points(relay_xy_dev, (size_t)p->L * 2, rxy, s);
@@ -1248,15 +1308,16 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     std::vector<float> vxy;
     if (p->mode == NURSD_MODE_GRID || p->mode == NURSD_MODE_GRID3D || p->scaled()) {
         if (p->nx < 1 || p->ny < 1) return bail(fail(NURSD_ERR_ARG, "nx, ny must be >= 1"));
-        p->dx = p->vdx;
-        p->dy = p->vdy;
-        p->cx = p->x0 + (p->nx / 2) * p->dx;
-        p->cy = p->y0 + (p->ny / 2) * p->dy;
+        // grid pitch vdx / q; voxel ix is grid point ix q - (nx q)/2 around c
+        p->dx = p->vdx / p->q;
+        p->dy = p->vdy / p->q;
+        p->cx = p->x0 + ((p->nx * p->q) / 2) * p->dx;
+        p->cy = p->y0 + ((p->ny * p->q) / 2) * p->dy;
         vlo[0] = p->x0;
         vlo[1] = p->y0;
-        vhi[0] = p->x0 + (p->nx - 1) * p->dx;
-        vhi[1] = p->y0 + (p->ny - 1) * p->dy;
-        mmin = p->pad * std::max(p->nx, p->ny);
+        vhi[0] = p->x0 + (p->nx - 1) * p->vdx;
+        vhi[1] = p->y0 + (p->ny - 1) * p->vdy;
+        mmin = p->pad * std::max(p->nx, p->ny) * p->q;
         if (p->scaled()) {
             p->zref = geo->zref;
             for (int i = 0; i < p->nz; ++i) {
@@ -1272,8 +1333,8 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         }
     } else {
         if (!geo->plane_ptr || !geo->voxel_xy_dev) return bail(fail(NURSD_ERR_ARG, "POINTS mode needs plane_ptr and voxel_xy_dev"));
-        p->dx = p->vdx;
-        p->dy = p->vdy;
+        p->dx = p->vdx / p->q;
+        p->dy = p->vdy / p->q;
         if ((rc = read_voxel_lists(p, geo, vxy, s))) return bail(rc);
         const int V = p->plane_ptr.back();
         double lo[2] = {1e300, 1e300}, hi[2] = {-1e300, -1e300};
@@ -1305,6 +1366,10 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         }
     }
     if (!p->M) return bail(fail(NURSD_ERR_GEOMETRY, "no supported transform size fits the geometry"));
+    for (int a = 0; a < 2; ++a) {
+        p->vlo[a] = vlo[a];
+        p->vhi[a] = vhi[a];
+    }
     p->Mf = 2 * p->M;
     p->BS = (p->M / 2 + 1 + 7) / 8 * 8;
     if (p->scaled()) {
@@ -1384,7 +1449,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if (!std::isfinite(p->z_mid)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite z_mid"));
         for (double zz : p->z)
             if (!(zz > p->z_mid)) return bail(fail(NURSD_ERR_GEOMETRY, "voxel planes must lie beyond z_mid"));
-        p->dz3 = geo->dz3 > 0 ? geo->dz3 : p->dx;
+        p->dz3 = geo->dz3 > 0 ? geo->dz3 : p->vdx;
         double ext = 0;
         for (float v : rz) {
             if (!std::isfinite(v)) return bail(fail(NURSD_ERR_GEOMETRY, "non-finite relay depth"));
@@ -1535,6 +1600,13 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
         if ((rc = upload(p, decx, &p->d_decx))) return bail(rc);
         if ((rc = upload(p, decy, &p->d_decy))) return bail(rc);
     }
+    if (opt->weights_dev) {
+        std::vector<float> wv;
+        if ((rc = read_points(opt->weights_dev, (size_t)p->L, wv, s))) return bail(rc);
+        for (float v : wv)
+            if (!std::isfinite(v)) return bail(fail(NURSD_ERR_ARG, "non-finite sample weight"));
+        if ((rc = upload(p, wv, &p->d_w))) return bail(rc);
+    }
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);
     *out = p;
@@ -1546,6 +1618,13 @@ int nursd_plan_set_points(nursd_plan* p, const float* relay_xy_dev, void* stream
     std::vector<float> rxy;
     int rc = read_points(relay_xy_dev, (size_t)p->L * 2, rxy, static_cast<hipStream_t>(stream));
     if (rc) return rc;
+    for (float v : rxy)
+        if (!std::isfinite(v)) return fail(NURSD_ERR_GEOMETRY, "non-finite relay position");
+    // the frame rule of plan creation: relays inside the period and every
+    // relay-voxel offset inside half a period (else the circular convolution
+    // would wrap)
+    if (!frame_fits(p->M, p->dx, p->dy, p->cx, p->cy, rxy, p->vlo, p->vhi))
+        return fail(NURSD_ERR_GEOMETRY, "relay positions leave the plan's frame (period or half-period offset rule)");
     return build_spread_lists(p, rxy);
 }
 
@@ -1566,6 +1645,7 @@ int nursd_plan_info(const nursd_plan* p, nursd_plan_info_t* info) {
     info->freq_chunk = p->FC;
     info->plane_chunk = p->ZC;
     info->depth3d = p->Mz3;
+    info->upsample_q = p->q;
     return NURSD_OK;
 }
 
@@ -1685,7 +1765,7 @@ int nursd_forward_video(nursd_plan* p, const void* P, int32_t n_frames, double t
         for (int b0 = 0; b0 < p->F; b0 += p->FC) {
             const int nb = std::min(p->FC, p->F - b0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             if (scaled) {
                 ChirpArgs ca{};
@@ -1706,7 +1786,7 @@ int nursd_forward_video(nursd_plan* p, const void* P, int32_t n_frames, double t
                 LAUNCH(p, NURSD_STAGE_CHIRP_ROWS, ChirpArgs, launch_chirp_rows, ca, s);
                 LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, ChirpArgs, launch_chirp_cols, ca, s);
             } else {
-                P2Args a2{g, Bt, U, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+                P2Args a2 = cols_args(p, g, Bt, U, Yt);
                 LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
             }
             P3Args a3 = rows_args(p, g, Yt, nullptr, nullptr, b0, nb);
@@ -1781,10 +1861,10 @@ int nursd_forward_multi(nursd_plan* p, const void* P, int32_t K, const double* x
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             for (int k = 0; k < K; ++k) {       // the kernel spectrum serves every position
-                P2Args a2{g, Bt, Us + k * uk, Yt, p->M, p->BS, p->ny, p->tw(p->M)};
+                P2Args a2 = cols_args(p, g, Bt, Us + k * uk, Yt);
                 LAUNCH(p, NURSD_STAGE_PROPAGATE_COLS, P2Args, launch_propagate_cols, a2, s);
                 P3Args a3 = rows_args(p, g, Yt, V, I, b0, nb);
                 a3.xp0 = xp[3 * k];
@@ -1851,13 +1931,15 @@ int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad
     a.xp2 = p->xp[2];
     a.relay_row_lo = p->relay_row_lo;
     a.relay_row_hi = p->relay_row_hi;
+    a.q = p->q;
+    a.wts = p->d_w;
     float2* Bt = const_cast<float2*>(a.Bt);
     for (int b0 = 0; b0 < p->F; b0 += p->FC) {
         const int nb = std::min(p->FC, p->F - b0);
         for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
             const int nzc = std::min(p->ZC, p->nz - z0);
             const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-            P1Args a1{g, Bt, p->M, p->BS, p->tw(p->M)};
+            P1Args a1 = kernel_args(p, g, Bt);
             LAUNCH(p, NURSD_STAGE_KERNEL_ROWS, P1Args, launch_kernel_rows, a1, s);
             a.g = g;
             a.first = z0 == 0;
@@ -1888,6 +1970,10 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
             return fail(NURSD_ERR_UNSUPPORTED_SIZE, "batched mode needs evenly spaced frequency bins");
     }
     auto bt = new nursd_batch();
+    auto bail = [&](int rc) {
+        delete bt;
+        return rc;
+    };
     for (int i = 0; i < n; ++i) {
         BatchScene sc;
         sc.p = plans[i];
@@ -1896,89 +1982,131 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
     bt->autotune = autotune ? 1 : 0;
     bt->hist.assign(n, nullptr);
     bt->I.assign(n, nullptr);
-    hipError_t e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        delete bt;
-        return fail(NURSD_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e));
+    // Default configuration: work queue, scenes with M >= 512 chunk by chunk,
+    // the fewest rounds whose propagation scratch fits the default budget.
+    std::vector<int> rounds;
+    for (int r : {4, 8, 16, 32, 64})
+        if (batch_scratch_bytes(bt, r, 512) <= kBatchScratchCap) rounds.push_back(r);
+    if (rounds.empty()) rounds.push_back(128);
+    bt->cfg = BatchConfig{rounds.front(), kQueue, 512};
+    for (int r : rounds)
+        if (batch_scratch_bytes(bt, r, 512) <= kBatchScratchDefault) {
+            bt->cfg.rounds = r;
+            break;
+        }
+    // Tuner candidates: serial threshold x schedule x the two fewest rounds
+    // whose grouped scratch fits the candidate limit.
+    bt->cands.push_back(bt->cfg);
+    if (bt->autotune) {
+        bt->cands.clear();
+        for (int mth : {256, 512, 1 << 20}) {
+            std::vector<int> rs;
+            for (int r : {4, 8, 16, 32, 64, 128})
+                if (rs.size() < 2 && batch_scratch_bytes(bt, r, mth) <= kBatchScratchCap) rs.push_back(r);
+            for (int sched : {kFlat, kQueue})
+                for (int r : rs) bt->cands.push_back(BatchConfig{r, sched, mth});
+        }
+        if (bt->cands.empty()) bt->cands.push_back(bt->cfg);
     }
+    // Size the workspace and the device tables for every candidate.
+    size_t tab_max = 0;
+    int cnt_max = 0;
+    for (const BatchConfig& c : bt->cands) {
+        bt->ws_need = std::max(bt->ws_need, batch_layout(bt, c));
+        size_t tb = 0;
+        int cn = 0;
+        batch_table_size(bt, c, &tb, &cn);
+        tab_max = std::max(tab_max, tb);
+        cnt_max = std::max(cnt_max, cn);
+    }
+    bt->ws_need = std::max(bt->ws_need, batch_layout(bt, bt->cfg));
+    bt->tab.clear();
+    bt->launches.clear();
+    hipError_t e;
+    if (tab_max > 0) {
+        void* d = nullptr;
+        if ((e = hipMalloc(&d, tab_max)) != hipSuccess)
+            return bail(fail(NURSD_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e)));
+        bt->d_tab = static_cast<char*>(d);
+        if ((e = hipHostMalloc(&bt->pinned, tab_max, hipHostMallocDefault)) != hipSuccess)
+            return bail(fail(NURSD_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e)));
+        bt->tab_cap = tab_max;
+    }
+    if (cnt_max > 0) {
+        void* d = nullptr;
+        if ((e = hipMalloc(&d, (size_t)cnt_max * sizeof(int))) != hipSuccess)
+            return bail(fail(NURSD_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e)));
+        bt->d_counters = static_cast<int*>(d);
+        bt->counters_cap = cnt_max;
+    }
+    if ((e = hipEventCreateWithFlags(&bt->upload_done, hipEventDisableTiming)) != hipSuccess)
+        return bail(fail(NURSD_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e)));
+    if ((e = hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking)) != hipSuccess)
+        return bail(fail(NURSD_ERR_HIP, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
     *out = bt;
     return NURSD_OK;
 }
 
-int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const* I, void* stream) {
-    if (!bt || !hist || !I) return fail(NURSD_ERR_ARG, "NULL argument");
+int nursd_batch_workspace_size(const nursd_batch* bt, size_t* bytes) {
+    if (!bt || !bytes) return fail(NURSD_ERR_ARG, "NULL argument");
+    *bytes = bt->ws_need;
+    return NURSD_OK;
+}
+
+int nursd_batch_autotune(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+                         void* stream) {
+    if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
+    if (!bt->autotune) return fail(NURSD_ERR_ARG, "the batch was created without autotuning");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const int n = (int)bt->sc.size();
     bool changed = false;
-    for (int i = 0; i < n; ++i) {
-        if (!hist[i] || !I[i]) return fail(NURSD_ERR_ARG, "NULL histogram or output pointer");
-        if (reinterpret_cast<uintptr_t>(hist[i]) & 7) return fail(NURSD_ERR_ARG, "histograms must be 8-byte aligned");
-        if (hist[i] != bt->hist[i] || I[i] != bt->I[i]) changed = true;
-        bt->hist[i] = hist[i];
-        bt->I[i] = I[i];
-    }
-    int rc;
-    if (!bt->budget) {
-        // choose the number of propagation rounds: measured (autotune) or
-        // the smallest whose scratch fits the default budget
-        std::vector<int> cands_tune;
-        for (int r : {4, 8, 16, 32, 64})
-            if (batch_scratch_bytes(bt, r) <= kBatchScratchCap) cands_tune.push_back(r);
-        if (cands_tune.empty()) cands_tune.push_back(128);
-        if (bt->autotune) {
-            hipEvent_t e0, e1;
-            HIP_TRY(hipEventCreate(&e0));
-            HIP_TRY(hipEventCreate(&e1));
-            float best = 1e30f;
-            int best_b = cands_tune.back(), best_s = kFlat;
-            if (cands_tune.size() > 2) cands_tune.resize(2);
-            int best_m = 512;
-            for (int mth : {256, 512, 1 << 20})
-            for (int sc : {kFlat, kQueue})
-            for (int c : cands_tune) {
-                bt->serial_min_m = mth;
-                if ((rc = batch_prepare(bt, c, sc, s))) return rc;
-                HIP_TRY(hipGraphLaunch(bt->exec, s));
-                HIP_TRY(hipEventRecord(e0, s));
-                for (int k = 0; k < 2; ++k) HIP_TRY(hipGraphLaunch(bt->exec, s));
-                HIP_TRY(hipEventRecord(e1, s));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                bt->tried.push_back(c + 1000 * sc + 10000 * (mth == 256 ? 1 : mth == 512 ? 2 : 0));
-                bt->tried_ms.push_back(ms / 2);
-                if (ms < best) {
-                    best = ms;
-                    best_b = c;
-                    best_s = sc;
-                    best_m = mth;
-                }
-            }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            bt->budget = best_b;
-            bt->sched = best_s;
-            bt->serial_min_m = best_m;
-        } else {
-            bt->sched = kQueue;
-            bt->serial_min_m = 512;
-            bt->budget = cands_tune.front();
-            for (int r : cands_tune)
-                if (batch_scratch_bytes(bt, r) <= kBatchScratchDefault) {
-                    bt->budget = r;
-                    break;
-                }
+    int rc = batch_check_io(bt, hist, I, ws, ws_bytes, &changed);
+    if (rc) return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    BatchConfig best_c = bt->cfg;
+    bt->tried.clear();
+    bt->tried_ms.clear();
+    for (const BatchConfig& c : bt->cands) {
+        bt->cfg = c;
+        if ((rc = batch_bind(bt, static_cast<const char*>(ws), s))) break;
+        hipError_t e = hipGraphLaunch(bt->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipGraphLaunch(bt->exec, s);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            rc = fail(NURSD_ERR_HIP, std::string("batch autotune: ") + hipGetErrorString(e));
+            break;
         }
-        if ((rc = batch_prepare(bt, bt->budget, bt->sched, s))) return rc;
-        changed = false;
+        bt->tried.push_back(config_code(c));
+        bt->tried_ms.push_back(ms / 2);
+        if (ms < best) {
+            best = ms;
+            best_c = c;
+        }
     }
-    if (changed) {
-        // same layout, new pointers: rebuild the item tables and re-capture
-        // (ordinary launches carry the output pointers as kernel arguments)
-        if ((rc = batch_build(bt, bt->budget))) return rc;
-        if ((rc = batch_upload(bt, s))) return rc;
-        if ((rc = batch_capture(bt))) return rc;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    bt->cfg = best_c;
+    if (rc) {
+        bt->ready = false;
+        return rc;
     }
+    return batch_bind(bt, static_cast<const char*>(ws), s);
+}
+
+int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+                        void* stream) {
+    if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    bool changed = false;
+    int rc = batch_check_io(bt, hist, I, ws, ws_bytes, &changed);
+    if (rc) return rc;
+    if (changed && (rc = batch_bind(bt, static_cast<const char*>(ws), s))) return rc;
     HIP_TRY(hipGraphLaunch(bt->exec, s));
     return NURSD_OK;
 }
@@ -1986,16 +2114,14 @@ int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const*
 int nursd_batch_info(const nursd_batch* bt, int32_t* budget, int32_t* launches, int32_t* n_tried, int32_t* tried,
                      float* tried_ms, size_t* workspace_bytes) {
     if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
-    if (budget)
-        *budget = bt->budget + 1000 * bt->sched +
-                  10000 * (bt->serial_min_m == 256 ? 1 : bt->serial_min_m == 512 ? 2 : 0);
+    if (budget) *budget = config_code(bt->cfg);
     if (launches) *launches = (int32_t)bt->launches.size();
     if (n_tried) *n_tried = (int32_t)bt->tried.size();
-    for (size_t i = 0; i < bt->tried.size(); ++i) {
+    for (size_t i = 0; i < bt->tried.size() && i < 16; ++i) {
         if (tried) tried[i] = bt->tried[i];
         if (tried_ms) tried_ms[i] = bt->tried_ms[i];
     }
-    if (workspace_bytes) *workspace_bytes = bt->ws_bytes;
+    if (workspace_bytes) *workspace_bytes = bt->ws_need;
     return NURSD_OK;
 }
 

@@ -69,14 +69,17 @@ __global__ __launch_bounds__(adj_row_waves<M>() * 64) void k_adj_rows(AdjArgs a)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int n = lane + 64 * e;
-            const int ix = (n < H ? n : n - M) + nx / 2;
+            // grid column m is window column (m + (nx q)/2) / q when that divides
+            const int m = n < H ? n : n - M;
+            const int t = m + (nx * a.q) / 2;
+            const int ix = (t >= 0 && t % a.q == 0) ? t / a.q : -1;
             const int sl = q * E + e;
             gv[sl] = make_float2(0.f, 0.f);
             dist[sl] = 0.0;
             if (iy < ny && ix >= 0 && ix < nx) {
                 gv[sl] = a.gV[((size_t)iz * ny + iy) * nx + ix];
-                const double x = a.xc + (ix - nx / 2) * a.g.dx;
-                const double y = a.yc + (iy - ny / 2) * a.g.dy;
+                const double x = a.xc + m * a.g.dx;
+                const double y = a.yc + (iy * a.q - (ny * a.q) / 2) * a.g.dy;
                 dist[sl] = adj_dist(x - a.xp0, y - a.xp1, z - a.xp2);
             }
         }
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(kAdjColWaves * 64) void k_adj_cols(AdjArgs a) {
     // waves take the chunk's planes in turn and their sums meet in LDS
     const int kx0 = blockIdx.x * LPW;
     float2* scr = sm + wave * F::SCR;
-    const int ny = a.ny, half = ny / 2;
+    const int ny = a.ny, hq = (ny * a.q) / 2;
     float2 acc[2][F::NV];
 #pragma unroll
     for (int sd = 0; sd < 2; ++sd)
@@ -156,7 +159,9 @@ __global__ __launch_bounds__(kAdjColWaves * 64) void k_adj_cols(AdjArgs a) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int n = lane + 64 * e;
-                    const int iy = (n < H ? n : n - M) + half;
+                    // grid row m is window row (m + (ny q)/2) / q when that divides
+                    const int t = (n < H ? n : n - M) + hq;
+                    const int iy = (t >= 0 && t % a.q == 0) ? t / a.q : -1;
                     v[q * E + e] = (kx <= H && iy >= 0 && iy < ny) ? Rt[(size_t)s * ny + iy] : make_float2(0.f, 0.f);
                 }
             }
@@ -320,6 +325,7 @@ __global__ __launch_bounds__(kAdjInterpWaves * 64) void k_adj_interp(AdjArgs a) 
             rowoff[i] = ((iy0 + i) & (MF - 1)) * MF;
         }
         const int nq = a.grad_xy ? 3 : 1;
+        const float wl = a.wts ? a.wts[l] : 1.0f;
         for (int fb = wave; fb < a.g.nb; fb += kAdjInterpWaves) {
             const int b = a.g.b0 + fb;
             float2 val[3];
@@ -343,11 +349,12 @@ __global__ __launch_bounds__(kAdjInterpWaves * 64) void k_adj_interp(AdjArgs a) 
                 }
                 val[qk] = sum;
             }
-            a.grad_P[(size_t)b * a.L + l] = val[0];
+            // the forward used w_l P_l: both gradients carry the weight
+            a.grad_P[(size_t)b * a.L + l] = cscale(val[0], wl);
             if (a.grad_xy) {
                 const float2 pv = a.P[(size_t)b * a.L + l];
-                gx += pv.x * val[1].x + pv.y * val[1].y;     // Re(conj(P) D)
-                gy += pv.x * val[2].x + pv.y * val[2].y;
+                gx += wl * (pv.x * val[1].x + pv.y * val[1].y);     // Re(conj(w P) D)
+                gy += wl * (pv.x * val[2].x + pv.y * val[2].y);
             }
         }
     }

@@ -87,9 +87,10 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
             packed = ((int)en.ix0 & 0xffff) | ((int)en.iy0 << 16);
             efx = en.fx;
             efy = en.fy;
+            const float wl = a.wts ? a.wts[en.idx] : 1.0f;     // per-sample weight
 #pragma unroll
             for (int f = 0; f < NF; ++f)
-                if (f < nf) ep[f] = Pb[(size_t)f * a.L + en.idx];
+                if (f < nf) ep[f] = cscale(Pb[(size_t)f * a.L + en.idx], wl);
         }
         const int cnt = min(64, s1 - base);
         for (int j = 0; j < cnt; ++j) {

@@ -219,16 +219,28 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
             const int kx = kx0 + q;
             const int s = side ? ((M - kx) & (M - 1)) : kx;
             if (kx > H || (side && s == kx)) continue;
-            // One row base per line; slot e sits at offset 64 e, or 64 e - M
-            // past the centre, which is a constant when M/2 is a multiple of
-            // 64, so the stores take immediate offsets.
-            float2* row = Yp + (size_t)s * a.ny + half + lane;
+            if (a.q == 1) {
+                // One row base per line; slot e sits at offset 64 e, or 64 e - M
+                // past the centre, which is a constant when M/2 is a multiple of
+                // 64, so the stores take immediate offsets.
+                float2* row = Yp + (size_t)s * a.ny + half + lane;
 #pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const bool lower = H % 64 == 0 ? 64 * e < H : lane + 64 * e < H;
-                const int off = lower ? 64 * e : 64 * e - M;
-                const int iy = lane + off + half;
-                if (iy >= 0 && iy < a.ny) row[off] = v[q * E + e];
+                for (int e = 0; e < E; ++e) {
+                    const bool lower = H % 64 == 0 ? 64 * e < H : lane + 64 * e < H;
+                    const int off = lower ? 64 * e : 64 * e - M;
+                    const int iy = lane + off + half;
+                    if (iy >= 0 && iy < a.ny) row[off] = v[q * E + e];
+                }
+            } else {
+                // upsampled frame: window row iy is grid row iy q - (ny q)/2
+                const int hq = (a.ny * a.q) / 2;
+                float2* row = Yp + (size_t)s * a.ny;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int n = lane + 64 * e;
+                    const int t = (n < H ? n : n - M) + hq;
+                    if (t >= 0 && t % a.q == 0 && t / a.q < a.ny) row[t / a.q] = v[q * E + e];
+                }
             }
         }
     }
@@ -291,14 +303,18 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
             int q;
             const int k = F::perm_k(lane, h, d, q);
             const int iy = iy0 + wave * LPW + q;
-            const int ix = (k < H ? k : k - M) + nx / 2;
+            // grid column m of the frame is window column (m + (nx q)/2) / q
+            // when that divides (q = 1: every column)
+            const int m = k < H ? k : k - M;
+            const int t = m + (nx * a.q) / 2;
+            const int ix = (t >= 0 && t % a.q == 0) ? t / a.q : -1;
             off[sl] = (iy < ny && ix >= 0 && ix < nx) ? iy * nx + ix : -1;
             acc[sl] = make_float2(0.f, 0.f);
             ph[sl] = make_float2(1.f, 0.f);
             st[sl] = make_float2(1.f, 0.f);
             if (off[sl] >= 0) {
-                const double x = a.xc + (ix - nx / 2) * px;
-                const double y = a.yc + (iy - ny / 2) * py;
+                const double x = a.xc + m * px;
+                const double y = a.yc + (iy * a.q - (ny * a.q) / 2) * py;
                 const double dd = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
                 ph[sl] = phase_of(dd, a.g.f[a.g.b0] / kC);
                 st[sl] = phase_of(dd, a.g.df / kC);
@@ -488,7 +504,8 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
 
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
     if (!a.g.uni) return hipErrorInvalidValue;     // phases advance by a fixed step
-    const bool half = 2 * a.nx <= a.M;
+    if (a.q < 1) return hipErrorInvalidValue;
+    const bool half = 2 * a.nx * a.q <= a.M;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
         constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;

@@ -51,6 +51,7 @@ hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s);
 // ---------------------------------------------------------------- steps 2-3
 struct SpreadArgs {
     const float2* P;              // [F][L] (frequency-major)
+    const float* wts;             // [L] per-sample weights multiplying P, or NULL
     const SpreadEntry* ent;       // entries sorted by band, then u
     const int* band_ptr;          // [nbands + 1]
     const int* wave_rng;          // [nbands][kSpreadWaves][4]: entry range, then column range, of each wave
@@ -103,6 +104,7 @@ struct P2Args {
     float2* Yt;         // [planes][M][ny]: kx line s, then window row iy
     int M, BS, ny;
     const float2* tw;
+    int q = 1;          // window row iy is grid row iy q - (ny q)/2 (upsampled frame)
 };
 hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s);
 
@@ -112,7 +114,7 @@ struct P3Args {
     float2* V;          // [Z][ny][nx] (may be NULL for incoherent)
     float* I;           // [Z][ny][nx] or NULL
     int M, nx, ny;
-    double xc, yc;      // voxel (ix, iy) at (xc + (ix - nx/2) px, yc + (iy - ny/2) py)
+    double xc, yc;      // voxel (ix, iy) at (xc + (ix q - (nx q)/2) px, yc + (iy q - (ny q)/2) py)
     double xp0, xp1, xp2;
     int first, last, coherent;
     const float2* tw;
@@ -121,6 +123,7 @@ struct P3Args {
     // (frequency stride field_nz * ny * nx) instead of being summed.
     float2* field;
     int field_z0, field_nz;
+    int q = 1;          // grid points per voxel pitch (upsampled frame)
 };
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s);
 
@@ -281,6 +284,8 @@ struct AdjArgs {
     int relay_row_lo, relay_row_hi;
     int first;               // first plane chunk: St is written, else accumulated
     int first_b;             // first frequency chunk: grad_xy is written, else accumulated
+    int q = 1;               // window index i is grid index i q - (n q)/2
+    const float* wts = nullptr;  // [L] per-sample weights of the forward, or NULL
 };
 hipError_t launch_adjoint_planes(const AdjArgs& a, hipStream_t s);
 hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s);

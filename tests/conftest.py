@@ -27,3 +27,11 @@ def device():
         pytest.skip("no GPU")
     import torch
     return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="session")
+def spad_hist():
+    """The rendered SPAD-scale histograms ([65,536][4,096] float32), shared by
+    the full-size parity tests (rendering takes about 20 s)."""
+    from workloads import scenes
+    return scenes.config_spad().hist

@@ -69,19 +69,8 @@ def test_batch_matches_plain_loop(device, autotune):
 def test_batch_matches_oracle(device):
     ws = small_scenes()
     plans, hists, plain, batch, outs = run_both(ws, device, False)
-    for w, I in zip(ws[:2] + ws[5:], outs[:2] + outs[5:]):
+    for w, I in zip(ws, outs):
         P, f = o.phasors_from_workload(w)
         ref = o.nursd_grid(P, w.relay_xy.astype(np.float64), f, o.frame_for_workload(w), w.grid, w.xp,
                            intensity=True)
         assert rel(I.cpu().numpy(), ref) < 1e-4
-
-
-@pytest.mark.slow
-def test_batch_64_uneven_scenes(device):
-    """The 64-scene serving workload (relays 2k-64k, grids 64^2x32 to
-    256^2x128, 16-128 frequencies, 4-8 cm wavelengths): batched == plain."""
-    print("case: batch 64 scenes", flush=True)
-    ws = scenes.config_batch()
-    plans, hists, plain, batch, outs = run_both(ws, device, True)
-    for a, b in zip(outs, plain):
-        assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5

@@ -231,33 +231,3 @@ def test_diff_config_forward_full(device):
     Vref = o.nursd_grid(Pref, w.relay_xy.astype(np.float64), f, fr, w.grid, w.xp)
     assert rel(V.cpu().numpy(), Vref) < TOL
     assert rel(I.cpu().numpy(), np.abs(Vref)) < TOL
-
-
-@pytest.mark.slow
-def test_spad_config_full_launch_sampled(device):
-    """Full SPAD-scale launch (65,536 relays, 96 frequencies, 256x256x128
-    voxels, the benchmark configuration) with phasors nonzero in two bins;
-    the oracle evaluates three whole planes.  Also checks the phasor stage
-    at sampled relays for all bins."""
-    print("case: spad full launch", flush=True)
-    w = scenes.config_spad()
-    plan = plan_for(w, device)
-    hist = torch.from_numpy(w.hist).to(device)
-    P = plan.phasor(hist).cpu().numpy()
-    wl = w.wavelet
-    bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
-    wts = o.phasor_weights(f, wl.lambda_c, wl.sigma_rel, wl.t0)
-    rows = np.random.default_rng(0).choice(w.relay_xy.shape[0], 256, replace=False)
-    Pref_rows = o.temporal_phasor(w.hist[rows], bins, wts)
-    assert rel(P[:, rows], Pref_rows) < 5e-6
-    sel = [10, 60]
-    Pin = np.zeros((wl.n_freq, w.relay_xy.shape[0]), np.complex64)
-    Pin[sel] = o.temporal_phasor(w.hist, bins[sel], wts[sel])
-    V, _ = plan.forward_phasor(torch.from_numpy(Pin).to(device), intensity=False)
-    V = V.cpu().numpy()
-    fr = o.frame_for_workload(w)
-    zi = [0, 64, 127]
-    g = w.grid
-    sub = scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[zi])
-    Vref = o.nursd_grid(Pin[sel].astype(np.complex128), w.relay_xy.astype(np.float64), f[sel], fr, sub, w.xp)
-    assert rel(V[zi], Vref) < TOL

@@ -56,31 +56,3 @@ def test_points_rejects_small_transform(device):
     assert o.frame_for_workload(w).M == 256
     with pytest.raises(RuntimeError, match="UNSUPPORTED_SIZE"):
         plan_from_workload(w, device)
-
-
-@pytest.mark.slow
-def test_frustum_points_full_launch_sampled(device):
-    """The 1,048,576-voxel frustum (64 planes over [1,4] m) from 65,536 relays
-    with 96 frequencies at full size, phasors nonzero in two bins; the oracle
-    evaluates 1,500 sampled voxels on each of three planes."""
-    print("case: frustum points full launch", flush=True)
-    from paper_2501_05244_amd.api import plan_from_workload
-    w = scenes.config_frustum_points()
-    plan = plan_from_workload(w, device)
-    fr = o.frame_for_workload(w)
-    assert plan.info["M"] == fr.M == 512
-    wl = w.wavelet
-    bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
-    wts = o.phasor_weights(f, wl.lambda_c, wl.sigma_rel, wl.t0)
-    sel = [30, 75]
-    Pin = np.zeros((wl.n_freq, w.relay_xy.shape[0]), np.complex64)
-    Pin[sel] = o.temporal_phasor(w.hist, bins[sel], wts[sel])
-    V, _ = plan.forward_phasor(torch.from_numpy(Pin).to(device), intensity=False)
-    V = V.cpu().numpy()
-    rng = np.random.default_rng(0)
-    for iz in (0, 31, 63):
-        a, e = w.plane_ptr[iz], w.plane_ptr[iz + 1]
-        idx = np.sort(rng.choice(np.arange(a, e), 1500, replace=False))
-        ref = o.nursd_points(Pin[sel].astype(np.complex128), w.relay_xy.astype(np.float64), f[sel], fr,
-                             [w.grid.z[iz]], np.array([0, len(idx)]), w.voxel_xy[idx].astype(np.float64), w.xp)
-        assert rel(V[idx], ref) < TOL

@@ -56,28 +56,3 @@ def test_srsd_rejects_bad_geometry(device):
     w.zref = 2.0          # alpha = zref / z > 1 on every plane
     with pytest.raises(RuntimeError, match="GEOMETRY"):
         plan_from_workload(w, device)
-
-
-@pytest.mark.slow
-def test_srsd_spad_full_launch_sampled(device):
-    """The scaled-RSD workload at full size (65,536 relays, 96 frequencies,
-    256x256 samples on 128 planes over [1,4] m) with phasors nonzero in two
-    bins; the oracle evaluates three whole planes."""
-    print("case: srsd spad full launch", flush=True)
-    from paper_2501_05244_amd.api import plan_from_workload
-    w = scenes.config_srsd()
-    plan = plan_from_workload(w, device)
-    wl = w.wavelet
-    bins, f = o.wavelet_bins(wl.lambda_c, wl.n_time, wl.dt, wl.n_freq)
-    wts = o.phasor_weights(f, wl.lambda_c, wl.sigma_rel, wl.t0)
-    sel = [20, 70]
-    Pin = np.zeros((wl.n_freq, w.relay_xy.shape[0]), np.complex64)
-    Pin[sel] = o.temporal_phasor(w.hist, bins[sel], wts[sel])
-    V, _ = plan.forward_phasor(torch.from_numpy(Pin).to(device), intensity=False)
-    V = V.cpu().numpy()
-    zi = [0, 63, 127]
-    g = w.grid
-    sub = scenes.Workload("sub", w.relay_xy, w.xp, wl, scenes.Grid(g.x0, g.y0, g.dx, g.dy, g.nx, g.ny, g.z[zi]),
-                          mode="srsd", zref=w.zref)
-    ref = oracle_srsd(sub, Pin[sel], f[sel])
-    assert rel(V[zi], ref) < TOL
