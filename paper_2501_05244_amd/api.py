@@ -158,14 +158,20 @@ class Plan:
 
     def bind_points(self, relay_xy: torch.Tensor, stream=None):
         """Make the plan use the positions held in `relay_xy` (a [L][2]
-        float tensor, any device-resident layout), re-binning only when the
-        plan is not already bound to this very tensor at its current version
-        (autograd calls this for every forward and backward)."""
+        float tensor), re-binning only when the plan does not already hold
+        exactly that memory at its current version (autograd calls this for
+        every forward and backward).  The plan keeps a reference to the
+        bound memory, so its address cannot be freed and reused by another
+        tensor while it is bound; tensors that share it (detach(), views of
+        the same contiguous layout) share its version counter, so an
+        in-place change to them is seen too."""
         bound = getattr(self, "_bound_xy", None)
-        if bound is not None and bound[0] is relay_xy and bound[1] == relay_xy._version:
+        if (bound is not None and relay_xy.is_contiguous() and relay_xy.data_ptr() == bound[0].data_ptr()
+                and relay_xy._version == bound[1]):
             return
-        self.set_points(relay_xy.detach().contiguous(), stream)
-        self._bound_xy = (relay_xy, relay_xy._version)
+        src = relay_xy.detach().contiguous()
+        self.set_points(src, stream)
+        self._bound_xy = (src, relay_xy._version)
 
     def phasor(self, hist: torch.Tensor, stream=None) -> torch.Tensor:
         _need(hist, torch.float32, (self.L, self.n_time), "hist")

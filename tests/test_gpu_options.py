@@ -181,6 +181,22 @@ def test_autograd_binds_each_forwards_positions(device):
         ref = o.nursd_grid(P.astype(np.complex128), xt.cpu().numpy().astype(np.float64), f, fr, w.grid, w.xp)
         assert rel(Vt.cpu().numpy(), ref) < TOL
         del xt, Vt
+    # fresh leaves detached from one tensor (an optimisation loop) share its
+    # memory and version: the plan bins them once
+    calls = []
+    orig = plan.set_points
+    plan.set_points = lambda t, stream=None: (calls.append(1), orig(t, stream))
+    base = xy1.clone()
+    for _ in range(3):
+        with torch.no_grad():
+            nursd(Pg.detach(), base.detach().requires_grad_(True), plan)
+    assert len(calls) == 1
+    base[0, 0] += 1e-3                      # in place: the next call re-bins
+    with torch.no_grad():
+        Vb = nursd(Pg.detach(), base.detach(), plan)
+    assert len(calls) == 2
+    ref = o.nursd_grid(P.astype(np.complex128), base.cpu().numpy().astype(np.float64), f, fr, w.grid, w.xp)
+    assert rel(Vb.cpu().numpy(), ref) < TOL
 
 
 def batch_scenes():
