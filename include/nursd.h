@@ -226,6 +226,21 @@ int nursd_spectrum(nursd_plan* plan, const void* P_dev, void* U_dev, void* ws_de
 int nursd_forward_hist(nursd_plan* plan, const float* hist_dev, void* vol_dev, float* I_dev,
                        void* ws_dev, size_t ws_bytes, void* stream);
 
+/* nursd_forward_hist without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the workspace is a fixed device
+ * array of NURSD_STATIC_SCRATCH_BYTES (512 MiB) inside the library, one per
+ * GPU, held until the process ends; its address is looked up once per
+ * device at plan creation.  The call allocates nothing and does not
+ * synchronise.  Every call on one GPU shares that GPU's array and leaves its
+ * contents behind (nothing in it needs to start at zero): calls that
+ * overlap on one GPU (several streams or threads) race, so order them.
+ * Errors: WORKSPACE when the plan's workspace exceeds the array (use
+ * nursd_forward_hist), ARG while profiling is active (profiling creates
+ * events), and those of nursd_forward_hist. */
+#define NURSD_STATIC_SCRATCH_BYTES ((size_t)512 << 20)
+int nursd_forward_hist_static(nursd_plan* plan, const float* hist_dev, void* vol_dev, float* I_dev, void* stream);
+
 /* Reconstruction from phasors P_dev ([F][L] complex64): steps 2-7. */
 int nursd_forward_phasor(nursd_plan* plan, const void* P_dev, void* vol_dev, float* I_dev,
                          void* ws_dev, size_t ws_bytes, void* stream);

@@ -75,6 +75,7 @@ SIGNATURES = {
     "nursd_phasor": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p]),
     "nursd_spectrum": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "nursd_forward_hist": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
+    "nursd_forward_hist_static": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "nursd_forward_phasor": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]),
     "nursd_adjoint": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_size_t,
                                 c_void_p]),

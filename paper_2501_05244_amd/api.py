@@ -205,6 +205,16 @@ class Plan:
               "nursd_forward_hist")
         return V, I
 
+    def forward_hist_static(self, hist: torch.Tensor, out_vol=None, out_I=None, stream=None):
+        """nursd_forward_hist on the library's fixed device scratch: the call
+        itself allocates nothing (pass out_vol / out_I to keep it so)."""
+        _need(hist, torch.float32, (self.L, self.n_time), "hist")
+        V, I = self._outs(out_vol is not None or out_I is None, True, out_vol, out_I) \
+            if out_vol is None and out_I is None else (out_vol, out_I)
+        check(self._lib.nursd_forward_hist_static(self.handle, _ptr(hist), _ptr(V), _ptr(I), _stream(stream)),
+              "nursd_forward_hist_static")
+        return V, I
+
     def forward_phasor(self, P: torch.Tensor, vol=True, intensity=True, out_vol=None, out_I=None,
                        stream=None):
         _need(P, torch.complex64, (self.F, self.L), "P")

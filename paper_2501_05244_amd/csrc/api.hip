@@ -9,6 +9,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1214,6 +1215,37 @@ int batch_check_io(nursd_batch* bt, const float* const* hist, float* const* I, v
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Fixed device scratch of the allocation-free forward.  The array's name is a
+// host-side stand-in in host code: its device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is ever passed to kernels.
+constexpr size_t kStaticScratchBytes = NURSD_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int static_scratch(void** out) {
+    *out = nullptr;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NURSD_ERR_HIP, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(NURSD_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return NURSD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options* opt) {
@@ -1609,6 +1641,10 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     }
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);
+    // device address of the fixed scratch of nursd_forward_hist_static on
+    // this device (looked up once per device)
+    void* scr = nullptr;
+    if ((rc = static_scratch(&scr))) return bail(rc);
     *out = p;
     return NURSD_OK;
 }
@@ -1706,6 +1742,20 @@ int nursd_forward_hist(nursd_plan* p, const float* hist, void* vol, float* I, vo
     float2* P = reinterpret_cast<float2*>(w + p->off_P);
     if ((rc = nursd_phasor(p, hist, P, stream))) return rc;
     return forward_from_P(p, P, vol, I, w, static_cast<hipStream_t>(stream));
+}
+
+int nursd_forward_hist_static(nursd_plan* p, const float* hist, void* vol, float* I, void* stream) {
+    if (!p || !hist) return fail(NURSD_ERR_ARG, "NULL argument");
+    if (p->ws_bytes > kStaticScratchBytes)
+        return fail(NURSD_ERR_WORKSPACE, "plan needs " + std::to_string(p->ws_bytes) +
+                                             " bytes of workspace; the fixed scratch holds " +
+                                             std::to_string(kStaticScratchBytes) +
+                                             " (use nursd_forward_hist with a caller workspace)");
+    if (p->prof_mask) return fail(NURSD_ERR_ARG, "profiling creates events; end it before this call");
+    void* scr = nullptr;
+    int rc = static_scratch(&scr);
+    if (rc) return rc;
+    return nursd_forward_hist(p, hist, vol, I, scr, kStaticScratchBytes, stream);
 }
 
 namespace {
