@@ -10,7 +10,8 @@ import ctypes
 import os
 from ctypes import POINTER, c_char_p, c_double, c_float, c_int32, c_size_t, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnursd.so")
+# NURSD_LIB names another build of the same library (e.g. a compile-time variant)
+LIB_PATH = os.environ.get("NURSD_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libnursd.so")
 
 NURSD_OK = 0
 ERRORS = {
