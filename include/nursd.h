@@ -304,7 +304,12 @@ int nursd_subsample_nearest(const void* in_dev, void* out_dev, int32_t F, int32_
  * chunk with ordinary launches inside the graph.  Grouped launches run in
  * one of three schedules: persistent workgroups fed by a device work queue,
  * persistent workgroups with a static stride, or one workgroup per work
- * block.
+ * block.  Plans whose kernels agree (transform size, grid pitch, 1/r form)
+ * form a kernel class: the kernel spectrum quadrant of each distinct
+ * (frequency, depth) pair of a class is generated once per batched forward
+ * into a table in the workspace and read by the column passes of every
+ * member plan (when the members use each pair at least 1.5 times on average
+ * and the tables fit 24 GiB), instead of once per plan.
  *
  * nursd_batch_create validates the plans, picks the default configuration
  * (work queue, threshold 512, the fewest rounds whose propagation scratch
@@ -336,9 +341,10 @@ int nursd_batch_autotune(nursd_batch* batch, const float* const* hist_dev, float
                          size_t ws_bytes, void* stream);
 int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float* const* I_dev, void* ws_dev,
                         size_t ws_bytes, void* stream);
-/* Configuration in use (R + 1000 * schedule + 10000 * threshold code;
- * schedule 0 = work queue, 1 = static stride, 2 = one workgroup per block;
- * threshold code 0 = none chunk by chunk, 1 = M >= 256, 2 = M >= 512),
+/* Configuration in use (R + 1000 * schedule + 10000 * threshold code +
+ * 100000 * shared kernel tables; schedule 0 = work queue, 1 = static
+ * stride, 2 = one workgroup per block; threshold code 0 = none chunk by
+ * chunk, 1 = M >= 256, 2 = M >= 512),
  * number of launch records in the graph, the autotuner's candidates (same
  * encoding) and their times (ms per batch), workspace bytes.  Arrays may be
  * NULL; tried / tried_ms need room for 16 entries. */

@@ -343,9 +343,11 @@ class Batch:
         serial = {0: "none", 1: "M>=256", 2: "M>=512"}
 
         def label(t):
-            return f"{names[(t // 1000) % 10]}/R{t % 1000}/serial:{serial[t // 10000]}"
+            return (f"{names[(t // 1000) % 10]}/R{t % 1000}/serial:{serial[(t // 10000) % 10]}"
+                    f"/shared:{t // 100000}")
         return {"rounds": b.value % 1000, "schedule": names[(b.value // 1000) % 10],
-                "serial": serial[b.value // 10000], "launches": nl.value, "workspace_bytes": wsb.value,
+                "serial": serial[(b.value // 10000) % 10], "shared_kernels": b.value // 100000,
+                "launches": nl.value, "workspace_bytes": wsb.value,
                 "tried": {label(t): tms[i] for i, t in enumerate(tried[:nt.value])}}
 
 

@@ -770,24 +770,47 @@ hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
 }
 }  // namespace nursd
 
-enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL };
+enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL, BK_KTAB };
 
 // One configuration of the batched launch sequence.
 struct BatchConfig {
     int rounds = 4;            // propagation rounds R of the grouped scenes
     int sched = kQueue;        // grouped-launch schedule (kQueue, kStatic, kFlat)
     int serial_min_m = 512;    // scenes with M >= this are propagated chunk by chunk
+    int share = 1;             // kernel spectra shared by the scenes of a kernel class
 };
 
 int config_code(const BatchConfig& c) {
-    return c.rounds + 1000 * c.sched + 10000 * (c.serial_min_m == 256 ? 1 : c.serial_min_m == 512 ? 2 : 0);
+    return c.rounds + 1000 * c.sched + 10000 * (c.serial_min_m == 256 ? 1 : c.serial_min_m == 512 ? 2 : 0) +
+           100000 * c.share;
 }
+
+// Scenes whose kernels G(m dx, n dy, z) = e^{+j 2 pi f r / c} / r agree in
+// transform size, pitch and amplitude form form a kernel class: the kernel
+// quadrant of each distinct (frequency, depth) pair of the class is
+// generated once per batched forward, into a table in the workspace that
+// the column passes of every member scene read.
+struct KernelClass {
+    int M = 0, BS = 0, inv_r = 1;
+    double dx = 0, dy = 0;
+    const float2* tw = nullptr;          // twiddles of size M (a member plan's table)
+    std::vector<double> f, z;            // distinct frequencies and depths
+    double* d_f = nullptr;               // device copies (owned by the batch)
+    double* d_z = nullptr;
+    size_t off = 0;                      // workspace offset of the table [f][z][M/2+1][BS]
+    bool on = false;                     // table within the limit and worth sharing
+    size_t bytes() const { return f.size() * z.size() * (size_t)(M / 2 + 1) * BS * sizeof(float2); }
+};
 
 struct BatchScene {
     nursd_plan* p = nullptr;
     size_t off_P = 0, off_T1 = 0, off_U = 0, off_Bt = 0, off_Yt = 0, off_V = 0;
     int ZC = 1, rounds = 1;
     bool serial = false;     // propagated chunk by chunk with ordinary launches
+    int kcls = -1;           // kernel class
+    std::vector<int> kidx;   // [F][nz] plane of (b, iz) in the class table
+    bool shared = false;     // reads the class table (set per configuration)
+    size_t kidx_off = 0;     // byte offset of kidx in the table buffer
 };
 
 struct BatchLaunch {
@@ -800,6 +823,7 @@ struct BatchLaunch {
 
 struct nursd_batch {
     std::vector<BatchScene> sc;
+    std::vector<KernelClass> kcls;
     int autotune = 0;
     BatchConfig cfg;                 // configuration in use
     std::vector<BatchConfig> cands;  // configurations the tuner times
@@ -834,6 +858,10 @@ struct nursd_batch {
         if (d_tab) (void)hipFree(d_tab);
         if (pinned) (void)hipHostFree(pinned);
         if (d_counters) (void)hipFree(d_counters);
+        for (auto& k : kcls) {
+            if (k.d_f) (void)hipFree(k.d_f);
+            if (k.d_z) (void)hipFree(k.d_z);
+        }
     }
 };
 
@@ -852,6 +880,8 @@ size_t tab_push(std::vector<char>& tab, const std::vector<T>& v) {
 int batch_zc(const nursd_plan* p, int rounds) { return std::max(1, (p->nz + rounds - 1) / rounds); }
 
 constexpr size_t kBatchScratchCap = 32ull << 30;      // propagation scratch limit of a tuner candidate
+constexpr size_t kBatchKernelTableCap = 24ull << 30;  // kernel tables of all shared classes together
+constexpr int kMaxGridY = 32768;                      // planes per kernel-table launch
 constexpr size_t kBatchScratchDefault = 24ull << 30;  // default configuration without tuning
 
 // Propagation scratch of the scenes propagated by grouped launches.
@@ -871,11 +901,17 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
     size_t o = 0;
     const size_t c8 = sizeof(float2);
     size_t serial_bt = 0, serial_yt = 0;
+    for (auto& k : bt->kcls)
+        if (c.share && k.on) {
+            k.off = o;
+            o = align_up(o + k.bytes());
+        }
     for (auto& sc : bt->sc) {
         nursd_plan* p = sc.p;
         sc.serial = p->M >= c.serial_min_m;
+        sc.shared = c.share && bt->kcls[sc.kcls].on;
         if (sc.serial) {
-            serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
+            if (!sc.shared) serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
             serial_yt = std::max(serial_yt, (size_t)p->FC * p->ZC * p->ny * p->M * c8);
         }
         sc.ZC = batch_zc(p, c.rounds);
@@ -888,7 +924,7 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
         o = align_up(o + (size_t)p->F * p->M * p->M * c8);
         if (!sc.serial) {
             sc.off_Bt = o;
-            o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
+            if (!sc.shared) o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
             sc.off_Yt = o;
             o = align_up(o + (size_t)p->F * sc.ZC * p->ny * p->M * c8);
         }
@@ -900,6 +936,109 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
     bt->off_serial_Yt = o;
     o = align_up(o + serial_yt);
     return o;
+}
+
+// Groups the scenes into kernel classes, lists each class's distinct
+// frequencies and depths, maps every (b, iz) of a scene to its table plane
+// and enables the table of a class when its scenes use each of its planes
+// at least 1.5 times on average, largest savings first, within the limit.
+int batch_kernel_classes(nursd_batch* bt) {
+    for (auto& sc : bt->sc) {
+        const nursd_plan* p = sc.p;
+        int k = -1;
+        for (size_t j = 0; j < bt->kcls.size() && k < 0; ++j) {
+            const KernelClass& c = bt->kcls[j];
+            if (c.M == p->M && c.BS == p->BS && c.inv_r == p->kernel_inv_r && c.dx == p->dx && c.dy == p->dy)
+                k = (int)j;
+        }
+        if (k < 0) {
+            KernelClass c;
+            c.M = p->M;
+            c.BS = p->BS;
+            c.inv_r = p->kernel_inv_r;
+            c.dx = p->dx;
+            c.dy = p->dy;
+            c.tw = p->tw(p->M);
+            bt->kcls.push_back(c);
+            k = (int)bt->kcls.size() - 1;
+        }
+        sc.kcls = k;
+        KernelClass& c = bt->kcls[k];
+        c.f.insert(c.f.end(), p->freqs.begin(), p->freqs.end());
+        c.z.insert(c.z.end(), p->z.begin(), p->z.end());
+    }
+    std::vector<double> uses(bt->kcls.size(), 0.0);
+    for (auto& c : bt->kcls) {
+        std::sort(c.f.begin(), c.f.end());
+        c.f.erase(std::unique(c.f.begin(), c.f.end()), c.f.end());
+        std::sort(c.z.begin(), c.z.end());
+        c.z.erase(std::unique(c.z.begin(), c.z.end()), c.z.end());
+    }
+    for (auto& sc : bt->sc) {
+        const nursd_plan* p = sc.p;
+        const KernelClass& c = bt->kcls[sc.kcls];
+        sc.kidx.assign((size_t)p->F * p->nz, 0);
+        for (int b = 0; b < p->F; ++b) {
+            const int fi = (int)(std::lower_bound(c.f.begin(), c.f.end(), p->freqs[b]) - c.f.begin());
+            for (int iz = 0; iz < p->nz; ++iz) {
+                const int zi = (int)(std::lower_bound(c.z.begin(), c.z.end(), p->z[iz]) - c.z.begin());
+                sc.kidx[(size_t)b * p->nz + iz] = fi * (int)c.z.size() + zi;
+            }
+        }
+        uses[sc.kcls] += (double)p->F * p->nz;
+    }
+    std::vector<int> order(bt->kcls.size());
+    for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
+    auto saved = [&](int j) {
+        const KernelClass& c = bt->kcls[j];
+        return (uses[j] - (double)c.f.size() * c.z.size()) * (c.M / 2 + 1) * c.BS;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return saved(a) > saved(b); });
+    size_t total = 0;
+    for (int j : order) {
+        KernelClass& c = bt->kcls[j];
+        const double pairs = (double)c.f.size() * c.z.size();
+        if (uses[j] < 1.5 * pairs || total + c.bytes() > kBatchKernelTableCap) continue;
+        total += c.bytes();
+        c.on = true;
+        void* d = nullptr;
+        HIP_TRY(hipMalloc(&d, c.f.size() * sizeof(double)));
+        c.d_f = static_cast<double*>(d);
+        HIP_TRY(hipMalloc(&d, c.z.size() * sizeof(double)));
+        c.d_z = static_cast<double*>(d);
+        HIP_TRY(hipMemcpy(c.d_f, c.f.data(), c.f.size() * sizeof(double), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(c.d_z, c.z.data(), c.z.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return NURSD_OK;
+}
+
+// Column-pass arguments of a chunk of a scene that reads its class table.
+P2Args shared_cols_args(const nursd_batch* bt, const BatchScene& sc, const ChunkGeom& g, const float2* U,
+                        float2* Yt, char* ws) {
+    const KernelClass& k = bt->kcls[sc.kcls];
+    P2Args a = cols_args(sc.p, g, reinterpret_cast<const float2*>(ws + k.off), U, Yt);
+    a.kidx = reinterpret_cast<const int*>(reinterpret_cast<uintptr_t>(bt->d_tab) + sc.kidx_off);
+    a.kz = sc.p->nz;
+    return a;
+}
+
+// Kernel rows of class k for frequencies [f0, f1) at every class depth.
+P1Args class_kernel_args(const nursd_batch* bt, int k, int f0, int f1, char* ws) {
+    const KernelClass& kc = bt->kcls[k];
+    ChunkGeom g{};
+    g.b0 = f0;
+    g.nb = f1 - f0;
+    g.z0 = 0;
+    g.nzc = (int)kc.z.size();
+    g.f = kc.d_f;
+    g.z = kc.d_z;
+    g.dx = kc.dx;
+    g.dy = kc.dy;
+    g.uni = 0;
+    const size_t plane = (size_t)(kc.M / 2 + 1) * kc.BS;
+    P1Args a{g, reinterpret_cast<float2*>(ws + kc.off) + (size_t)f0 * kc.z.size() * plane, kc.M, kc.BS, kc.tw};
+    a.plain = kc.inv_r ? 0 : 1;
+    return a;
 }
 
 // Host side only: item tables and launch list of configuration c with the
@@ -1027,6 +1166,17 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
         add(BK_SPREAD, Mf, 0, it, gx, gy, wk);
         add(BK_FINEY, Mf, 0, it2, gx2, gy2, wk);
     }
+    // kernel tables: the quadrant of every distinct (frequency, depth) pair
+    // of each shared kernel class, before any column pass reads them
+    for (size_t k = 0; k < bt->kcls.size(); ++k) {
+        if (!(c.share && bt->kcls[k].on)) continue;
+        BatchLaunch L;
+        L.kind = BK_KTAB;
+        L.scene = (int)k;
+        bt->launches.push_back(L);
+    }
+    for (auto& sc : bt->sc)
+        if (sc.shared) sc.kidx_off = tab_push(bt->tab, sc.kidx);
     // steps 4-7, round by round
     const std::vector<int> Ms = classes([](nursd_plan* p) { return p->M; });
     for (int r = 0; r < max_rounds; ++r) {
@@ -1035,7 +1185,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             std::vector<P2Args> i2;
             std::vector<P3Args> i3;
             std::vector<int> g1x, g1y, g2x, g2y, g3x, g3y;
-            std::vector<double> w12, w3;
+            std::vector<double> w1, w12, w3;
             bool half = true;       // one row-pass variant per launch: every window within M/2
             for (const BatchScene& sc : bt->sc)
                 if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx * sc.p->q <= M;
@@ -1048,10 +1198,15 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                 float2* Bt = reinterpret_cast<float2*>(ws + sc.off_Bt);
                 float2* Yt = reinterpret_cast<float2*>(ws + sc.off_Yt);
                 const float2* U = reinterpret_cast<const float2*>(ws + sc.off_U);
-                i1.push_back(kernel_args(p, g, Bt));
-                g1x.push_back(grid_x_kernel_rows(M));
-                g1y.push_back(p->F * nzc);
-                i2.push_back(cols_args(p, g, Bt, U, Yt));
+                if (sc.shared) {
+                    i2.push_back(shared_cols_args(bt, sc, g, U, Yt, ws));
+                } else {
+                    i1.push_back(kernel_args(p, g, Bt));
+                    g1x.push_back(grid_x_kernel_rows(M));
+                    g1y.push_back(p->F * nzc);
+                    w1.push_back((double)p->F * nzc);
+                    i2.push_back(cols_args(p, g, Bt, U, Yt));
+                }
                 g2x.push_back(grid_x_propagate_cols(M));
                 g2y.push_back(p->F * nzc);
                 P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I.empty() ? nullptr : bt->I[i], 0, p->F);
@@ -1062,7 +1217,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                 w12.push_back((double)p->F * nzc);
                 w3.push_back((double)p->F);      // per block: one pass per frequency
             }
-            add(BK_P1, M, 0, i1, g1x, g1y, w12);
+            add(BK_P1, M, 0, i1, g1x, g1y, w1);
             add(BK_P2, M, 0, i2, g2x, g2y, w12);
             add(BK_P3, M, 0, i3, g3x, g3y, w3);
             if (!i3.empty()) bt->launches.back().half = half ? 1 : 0;
@@ -1112,11 +1267,19 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s) {
     // One work-queue counter per grouped launch; scenes propagated with
     // ordinary launches have none.
     for (const BatchLaunch& L : bt->launches)
-        if (L.kind != BK_SERIAL && (L.counter < 0 || L.counter >= bt->n_counters || bt->n_counters > bt->counters_cap))
+        if (L.kind != BK_SERIAL && L.kind != BK_KTAB &&
+            (L.counter < 0 || L.counter >= bt->n_counters || bt->n_counters > bt->counters_cap))
             return fail(NURSD_ERR_ARG, "batch launch table refers to a counter outside the counter buffer");
     if (bt->n_counters > 0) HIP_TRY(launch_zero_counters(bt->d_counters, bt->n_counters, s));
     char* ws = const_cast<char*>(bt->ws);
     for (const BatchLaunch& L : bt->launches) {
+        if (L.kind == BK_KTAB) {
+            const int nf = (int)bt->kcls[L.scene].f.size(), nzk = (int)bt->kcls[L.scene].z.size();
+            const int fstep = std::max(1, kMaxGridY / std::max(1, nzk));
+            for (int f0 = 0; f0 < nf; f0 += fstep)
+                HIP_TRY(launch_kernel_rows(class_kernel_args(bt, L.scene, f0, std::min(nf, f0 + fstep), ws), s));
+            continue;
+        }
         if (L.kind == BK_SERIAL) {
             const BatchScene& sc = bt->sc[L.scene];
             nursd_plan* p = sc.p;
@@ -1129,8 +1292,12 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s) {
                 for (int z0 = 0; z0 < p->nz; z0 += p->ZC) {
                     const int nzc = std::min(p->ZC, p->nz - z0);
                     const ChunkGeom g = chunk_geom(p, b0, nb, z0, nzc);
-                    HIP_TRY(launch_kernel_rows(kernel_args(p, g, Bt), s));
-                    HIP_TRY(launch_propagate_cols(cols_args(p, g, Bt, U, Yt), s));
+                    if (sc.shared) {
+                        HIP_TRY(launch_propagate_cols(shared_cols_args(bt, sc, g, U, Yt, ws), s));
+                    } else {
+                        HIP_TRY(launch_kernel_rows(kernel_args(p, g, Bt), s));
+                        HIP_TRY(launch_propagate_cols(cols_args(p, g, Bt, U, Yt), s));
+                    }
                     HIP_TRY(launch_propagate_rows(rows_args(p, g, Yt, V, bt->I[L.scene], b0, nb), s));
                 }
             }
@@ -2032,6 +2199,7 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
     bt->autotune = autotune ? 1 : 0;
     bt->hist.assign(n, nullptr);
     bt->I.assign(n, nullptr);
+    if (int rc = batch_kernel_classes(bt)) return bail(rc);
     // Default configuration: work queue, scenes with M >= 512 chunk by chunk,
     // the fewest rounds whose propagation scratch fits the default budget.
     std::vector<int> rounds;

@@ -178,7 +178,8 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int kx0 = (bx * kP2Waves + wave) * LPW;
     float2* scr = sm + wave * F::SCR;
-    const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
+    const int kp = a.kidx ? a.kidx[b * a.kz + iz] : p;
+    const float2* Bt = a.Bt + (size_t)kp * (H + 1) * a.BS;
     float2 v[F::NV], g[F::NV];
     // The kernel lines are requested before the twiddle table is staged, so
     // that both global reads are in flight across the block barrier.

@@ -105,6 +105,11 @@ struct P2Args {
     int M, BS, ny;
     const float2* tw;
     int q = 1;          // window row iy is grid row iy q - (ny q)/2 (upsampled frame)
+    // Batched mode: the kernel quadrant of frequency b and plane iz is plane
+    // kidx[b * kz + iz] of Bt, a table shared by the scenes of one transform
+    // size and pitch; NULL: plane p of the chunk.
+    const int* kidx = nullptr;
+    int kz = 0;
 };
 hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s);
 
