@@ -266,7 +266,7 @@ def secondary(w_spad, dev) -> dict:
                       "plain_ms": round(t_plain, 3), "batched_ms": round(t_batch, 3),
                       "speedup": round(t_plain / t_batch, 4), "max_rel_l2_batched_vs_plain": err,
                       "voxel*freq/s": units / (t_batch * 1e-3),
-                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial", "shared_kernels")},
+                      "autotuned": {k: info[k] for k in ("rounds", "schedule", "serial", "shared_kernels", "kernel_choices")},
                       "workspace_bytes": info["workspace_bytes"]}
     return out
 

@@ -309,7 +309,8 @@ int nursd_subsample_nearest(const void* in_dev, void* out_dev, int32_t F, int32_
  * (frequency, depth) pair of a class is generated once per batched forward
  * into a table in the workspace and read by the column passes of every
  * member plan (when the members use each pair at least 1.5 times on average
- * and the tables fit 24 GiB), instead of once per plan.
+ * and the tables fit 24 GiB), instead of once per plan.  The plans must
+ * outlive the batch and keep their relay positions while it exists.
  *
  * nursd_batch_create validates the plans, picks the default configuration
  * (work queue, threshold 512, the fewest rounds whose propagation scratch
@@ -350,6 +351,18 @@ int nursd_batch_forward(nursd_batch* batch, const float* const* hist_dev, float*
  * NULL; tried / tried_ms need room for 16 entries. */
 int nursd_batch_info(const nursd_batch* batch, int32_t* budget, int32_t* launches, int32_t* n_tried,
                      int32_t* tried, float* tried_ms, size_t* workspace_bytes);
+/* What the autotuner's second stage picked: after choosing the
+ * configuration, nursd_batch_autotune tries the schedule variants of every
+ * grouped launch class (kernel type and size) in turn -- the spreading tile
+ * (fine rows per band 4 / 8 / 16 and frequencies per workgroup 1 / 2 / 4,
+ * within LDS), lines per workgroup of the fine-grid y transform (2 / 4 / 8)
+ * and waves per block of the kernel-row, column and last passes (4 / 8,
+ * 2 / 4 / 8, 4 / 8) -- timing that class's launches with events in an
+ * eager run, and keeps the fastest; picks are cached per process by (kind,
+ * size, log2 of the launch's work).  Writes one line per class
+ * ("kind/size: choice (best ms, default ms)", "; "-separated, truncated to
+ * len) into buf. */
+int nursd_batch_tuning(const nursd_batch* batch, char* buf, size_t len);
 void nursd_batch_destroy(nursd_batch* batch);
 
 /* Per-kernel timing with HIP events, for profiling and roofline reports.

@@ -93,6 +93,7 @@ SIGNATURES = {
                                        c_void_p]),
     "nursd_batch_forward": (c_int32, [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p, c_size_t,
                                       c_void_p]),
+    "nursd_batch_tuning": (c_int32, [c_void_p, c_char_p, c_size_t]),
     "nursd_batch_destroy": (None, [c_void_p]),
     "nursd_batch_info": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_int32), POINTER(c_int32), POINTER(c_int32),
                                    POINTER(c_float), POINTER(c_size_t)]),

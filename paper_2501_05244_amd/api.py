@@ -345,10 +345,14 @@ class Batch:
         def label(t):
             return (f"{names[(t // 1000) % 10]}/R{t % 1000}/serial:{serial[(t // 10000) % 10]}"
                     f"/shared:{t // 100000}")
+        buf = ctypes.create_string_buffer(4096)
+        check(self._lib.nursd_batch_tuning(self.handle, buf, len(buf)), "nursd_batch_tuning")
+        kernels = [x for x in buf.value.decode().split("; ") if x]
         return {"rounds": b.value % 1000, "schedule": names[(b.value // 1000) % 10],
                 "serial": serial[(b.value // 10000) % 10], "shared_kernels": b.value // 100000,
                 "launches": nl.value, "workspace_bytes": wsb.value,
-                "tried": {label(t): tms[i] for i, t in enumerate(tried[:nt.value])}}
+                "tried": {label(t): tms[i] for i, t in enumerate(tried[:nt.value])},
+                "kernel_choices": kernels}
 
 
 def plan_from_workload(w, device, relay_xy: torch.Tensor | None = None, **kw) -> Plan:

@@ -8,8 +8,11 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -153,6 +156,7 @@ struct nursd_plan {
     int* d_band_ptr = nullptr;
     int* d_wave_rng = nullptr;
     int nbands = 0, n_ent = 0;
+    std::vector<float> h_relay;   // host copy of the binned relay positions [L][2]
     // per-kernel event timing
     uint32_t prof_mask = 0;
     std::vector<hipEvent_t> ev_pool;
@@ -248,11 +252,19 @@ bool frame_fits(int M, double dx, double dy, double cx, double cy, const std::ve
     return true;
 }
 
-int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
+// Relay entries of the spreading kernel for bands of BR fine rows: one entry
+// per (sample or periodic image, band) it touches, sorted by band then by
+// ix0, with each band's columns split between the spreading waves.
+struct SpreadLists {
+    int nbands = 0;
+    std::vector<SpreadEntry> ent;
+    std::vector<int> band_ptr, wave_rng;
+};
+
+int bin_relays(const nursd_plan* p, const std::vector<float>& rxy, int BR, SpreadLists& sl) {
     const int Mf = p->Mf, w = p->w;
     const double hw = 0.5 * w;
-    const int BR = spread_band_rows(Mf);
-    p->nbands = Mf / BR;
+    sl.nbands = Mf / BR;
     struct E {
         int band, ix0, iy0, l;
         float fx, fy;
@@ -283,27 +295,26 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
     std::stable_sort(ents.begin(), ents.end(), [](const E& a, const E& b) {
         return a.band != b.band ? a.band < b.band : a.ix0 < b.ix0;
     });
-    std::vector<SpreadEntry> out(ents.size());
-    std::vector<int> ptr(p->nbands + 1, 0);
+    sl.ent.resize(ents.size());
+    sl.band_ptr.assign(sl.nbands + 1, 0);
     for (size_t i = 0; i < ents.size(); ++i) {
-        out[i].ix0 = (short)ents[i].ix0;
-        out[i].iy0 = (short)ents[i].iy0;
-        out[i].fx = ents[i].fx;
-        out[i].fy = ents[i].fy;
-        out[i].idx = ents[i].l;
-        ptr[ents[i].band + 1]++;
+        sl.ent[i].ix0 = (short)ents[i].ix0;
+        sl.ent[i].iy0 = (short)ents[i].iy0;
+        sl.ent[i].fx = ents[i].fx;
+        sl.ent[i].fy = ents[i].fy;
+        sl.ent[i].idx = ents[i].l;
+        sl.band_ptr[ents[i].band + 1]++;
     }
-    for (int b = 0; b < p->nbands; ++b) ptr[b + 1] += ptr[b];
-    p->n_ent = (int)out.size();
+    for (int b = 0; b < sl.nbands; ++b) sl.band_ptr[b + 1] += sl.band_ptr[b];
     // Column range and entry range of each spreading wave.  The columns of a
     // band are split where the band's entries (sorted by ix0) reach equal
     // counts, so that all waves of a workgroup walk about as many samples
     // (relays usually cover only part of the period).  Taps of entry e reach
     // columns ix0 .. ix0 + w - 1, so wave columns [c_lo, c_hi) need ix0 in
     // [c_lo - w + 1, c_hi).
-    std::vector<int> rng((size_t)p->nbands * kSpreadWaves * 4);
-    for (int b = 0; b < p->nbands; ++b) {
-        auto first = ents.begin() + ptr[b], last = ents.begin() + ptr[b + 1];
+    sl.wave_rng.assign((size_t)sl.nbands * kSpreadWaves * 4, 0);
+    for (int b = 0; b < sl.nbands; ++b) {
+        auto first = ents.begin() + sl.band_ptr[b], last = ents.begin() + sl.band_ptr[b + 1];
         const long n = last - first;
         int bound[kSpreadWaves + 1];
         bound[0] = 0;
@@ -317,13 +328,27 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
             const int lo = bound[wv] - w + 1, hi = bound[wv + 1];
             auto a = std::lower_bound(first, last, lo, [](const E& e, int v) { return e.ix0 < v; });
             auto c = std::lower_bound(first, last, hi, [](const E& e, int v) { return e.ix0 < v; });
-            int* r = &rng[((size_t)b * kSpreadWaves + wv) * 4];
+            int* r = &sl.wave_rng[((size_t)b * kSpreadWaves + wv) * 4];
             r[0] = (int)(a - ents.begin());
             r[1] = (int)(c - ents.begin());
             r[2] = bound[wv];
             r[3] = bound[wv + 1];
         }
     }
+    return NURSD_OK;
+}
+
+int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
+    const int Mf = p->Mf, w = p->w;
+    const double hw = 0.5 * w;
+    SpreadLists sl;
+    if (int rc = bin_relays(p, rxy, spread_band_rows(Mf), sl)) return rc;
+    p->nbands = sl.nbands;
+    p->n_ent = (int)sl.ent.size();
+    p->h_relay = rxy;
+    const std::vector<SpreadEntry>& out = sl.ent;
+    const std::vector<int>& ptr = sl.band_ptr;
+    const std::vector<int>& rng = sl.wave_rng;
     if (p->d_ent) {
         // replace previous lists
         for (auto it = p->owned.begin(); it != p->owned.end();) {
@@ -815,15 +840,29 @@ struct BatchScene {
 
 struct BatchLaunch {
     int kind = 0, size = 0, fmax = 0;
+    int var = 0;                                     // schedule variant of the grouped kernel
     int half = 0;                                    // row pass: every window within M/2
     int scene = -1;                                  // BK_SERIAL: scene propagated with ordinary launches
     size_t items = 0, prefix = 0, gridx = 0, item_of = 0;   // byte offsets in the table buffer
     int n = 0, total = 0, counter = -1;
 };
 
+// Relay lists of a scene binned for another spreading band height.
+struct BatchLists {
+    int nbands = 0;
+    SpreadEntry* ent = nullptr;
+    int* band_ptr = nullptr;
+    int* wave_rng = nullptr;
+};
+
 struct nursd_batch {
     std::vector<BatchScene> sc;
     std::vector<KernelClass> kcls;
+    // schedule variant of each grouped launch, keyed by (kind, size class)
+    std::map<std::pair<int, int>, int> choice;
+    std::vector<std::map<int, BatchLists>> lists;   // per scene: band rows -> lists
+    std::vector<void*> owned;                       // device buffers of those lists
+    std::vector<std::string> tuned;                 // what the kernel tuner picked, with times
     int autotune = 0;
     BatchConfig cfg;                 // configuration in use
     std::vector<BatchConfig> cands;  // configurations the tuner times
@@ -862,6 +901,7 @@ struct nursd_batch {
             if (k.d_f) (void)hipFree(k.d_f);
             if (k.d_z) (void)hipFree(k.d_z);
         }
+        for (void* d : owned) (void)hipFree(d);
     }
 };
 
@@ -936,6 +976,67 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
     bt->off_serial_Yt = o;
     o = align_up(o + serial_yt);
     return o;
+}
+
+// Schedule variants of the grouped launches: the plain launches' values by
+// default (spreading tile of the plan, 4 lines per fine-y workgroup, 8 / 4 /
+// 8 waves per block in the three propagation passes), else the tuner's pick.
+int default_choice(int kind) {
+    switch (kind) {
+        case BK_FINEY: return 4;
+        case BK_P1: return 8;
+        case BK_P2: return 4;
+        case BK_P3: return 8;
+        default: return 0;
+    }
+}
+int batch_choice(const nursd_batch* bt, int kind, int size) {
+    auto it = bt->choice.find({kind, size});
+    return it == bt->choice.end() ? default_choice(kind) : it->second;
+}
+// Candidate variants of a (kind, size class) the tuner times.
+std::vector<int> choice_candidates(const nursd_batch* bt, int kind, int size) {
+    std::vector<int> v;
+    switch (kind) {
+        case BK_SPREAD:
+            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1)}) {
+                if (!spread_var_ok(size, c)) continue;
+                const int br = spread_var_rows(c, size);
+                bool have = br == spread_band_rows(size);
+                if (!have) {
+                    have = true;
+                    for (size_t i = 0; i < bt->sc.size(); ++i)
+                        if (bt->sc[i].p->Mf == size && !bt->lists[i].count(br)) have = false;
+                }
+                if (have && (c == 0 || c != spread_var(spread_band_rows(size), spread_freqs(size)))) v.push_back(c);
+            }
+            break;
+        case BK_FINEY: v = {2, 4, 8}; break;
+        case BK_P1: v = {4, 8}; break;
+        case BK_P2: v = {2, 4, 8}; break;
+        case BK_P3: v = {4, 8}; break;
+        default: v = {0}; break;
+    }
+    return v;
+}
+// The finest variant of every grouped launch (the most virtual blocks), for
+// sizing the table buffer.
+void finest_choices(nursd_batch* bt) {
+    bt->choice.clear();
+    for (const auto& sc : bt->sc) {
+        const int Mf = sc.p->Mf, M = sc.p->M;
+        int sv = 0;
+        for (int c : choice_candidates(bt, BK_SPREAD, Mf))
+            if (c && (spread_var_rows(c, Mf) < spread_var_rows(sv, Mf) ||
+                      (spread_var_rows(c, Mf) == spread_var_rows(sv, Mf) &&
+                       spread_var_freqs(c, Mf) < spread_var_freqs(sv, Mf))))
+                sv = c;
+        bt->choice[{BK_SPREAD, Mf}] = sv;
+        bt->choice[{BK_FINEY, Mf}] = 2;
+        bt->choice[{BK_P1, M}] = 4;
+        bt->choice[{BK_P2, M}] = 2;
+        bt->choice[{BK_P3, M}] = 4;
+    }
 }
 
 // Groups the scenes into kernel classes, lists each class's distinct
@@ -1054,8 +1155,8 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
     int counter = 0;
     // one grouped launch per (kind, size class); items are ordered by
     // descending work so the largest are dequeued first
-    auto add = [&](int kind, int size, int fmax, auto& items_in, std::vector<int>& gx_in, std::vector<int>& gy_in,
-                   const std::vector<double>& work) {
+    auto add = [&](int kind, int size, int fmax, int var, auto& items_in, std::vector<int>& gx_in,
+                   std::vector<int>& gy_in, const std::vector<double>& work) {
         if (items_in.empty()) return;
         std::vector<size_t> ord(items_in.size());
         for (size_t i = 0; i < ord.size(); ++i) ord[i] = i;
@@ -1071,6 +1172,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
         L.kind = kind;
         L.size = size;
         L.fmax = fmax;
+        L.var = var;
         L.n = (int)items.size();
         std::vector<int> prefix(items.size() + 1, 0);
         for (size_t i = 0; i < items.size(); ++i) prefix[i + 1] = prefix[i] + gx[i] * gy[i];
@@ -1118,7 +1220,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             wk.push_back((double)p->L);
             fmax = std::max(fmax, p->F);
         }
-        add(BK_PHASOR, T, fmax, it, gx, gy, wk);
+        add(BK_PHASOR, T, fmax, 0, it, gx, gy, wk);
     }
     // steps 2-3
     for (int Mf : classes([](nursd_plan* p) { return p->Mf; })) {
@@ -1126,7 +1228,10 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
         std::vector<FineYArgs> it2;
         std::vector<int> gx, gy, gx2, gy2;
         std::vector<double> wk;
-        for (auto& sc : bt->sc) {
+        const int sv = batch_choice(bt, BK_SPREAD, Mf), nl = batch_choice(bt, BK_FINEY, Mf);
+        const int BR = spread_var_rows(sv, Mf), NF = spread_var_freqs(sv, Mf);
+        for (size_t i = 0; i < bt->sc.size(); ++i) {
+            BatchScene& sc = bt->sc[i];
             nursd_plan* p = sc.p;
             if (p->Mf != Mf) continue;
             SpreadArgs a{};
@@ -1135,6 +1240,14 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             a.ent = p->d_ent;
             a.band_ptr = p->d_band_ptr;
             a.wave_rng = p->d_wave_rng;
+            int nbands = p->nbands;
+            if (BR != spread_band_rows(Mf)) {     // lists the batch binned for this band height
+                const BatchLists& bl = bt->lists[i].at(BR);
+                a.ent = bl.ent;
+                a.band_ptr = bl.band_ptr;
+                a.wave_rng = bl.wave_rng;
+                nbands = bl.nbands;
+            }
             a.T1 = reinterpret_cast<float2*>(ws + sc.off_T1);
             a.decx = p->d_decx;
             a.tw = p->tw(Mf);
@@ -1147,8 +1260,8 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             a.b0 = 0;
             a.nb = p->F;
             it.push_back(a);
-            gx.push_back(p->nbands);
-            gy.push_back((p->F + spread_freqs(Mf) - 1) / spread_freqs(Mf));
+            gx.push_back(nbands);
+            gy.push_back((p->F + NF - 1) / NF);
             FineYArgs f{};
             f.T1 = a.T1;
             f.U = reinterpret_cast<float2*>(ws + sc.off_U);
@@ -1159,12 +1272,12 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             f.b0 = 0;
             f.nb = p->F;
             it2.push_back(f);
-            gx2.push_back(p->M / fine_y_lines());
+            gx2.push_back(p->M / nl);
             gy2.push_back(p->F);
             wk.push_back((double)p->F * p->L);
         }
-        add(BK_SPREAD, Mf, 0, it, gx, gy, wk);
-        add(BK_FINEY, Mf, 0, it2, gx2, gy2, wk);
+        add(BK_SPREAD, Mf, 0, sv, it, gx, gy, wk);
+        add(BK_FINEY, Mf, 0, nl, it2, gx2, gy2, wk);
     }
     // kernel tables: the quadrant of every distinct (frequency, depth) pair
     // of each shared kernel class, before any column pass reads them
@@ -1186,6 +1299,8 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             std::vector<P3Args> i3;
             std::vector<int> g1x, g1y, g2x, g2y, g3x, g3y;
             std::vector<double> w1, w12, w3;
+            const int nw1 = batch_choice(bt, BK_P1, M), nw2 = batch_choice(bt, BK_P2, M);
+            const int nw3 = batch_choice(bt, BK_P3, M);
             bool half = true;       // one row-pass variant per launch: every window within M/2
             for (const BatchScene& sc : bt->sc)
                 if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx * sc.p->q <= M;
@@ -1202,24 +1317,24 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                     i2.push_back(shared_cols_args(bt, sc, g, U, Yt, ws));
                 } else {
                     i1.push_back(kernel_args(p, g, Bt));
-                    g1x.push_back(grid_x_kernel_rows(M));
+                    g1x.push_back(grid_x_kernel_rows(M, nw1));
                     g1y.push_back(p->F * nzc);
                     w1.push_back((double)p->F * nzc);
                     i2.push_back(cols_args(p, g, Bt, U, Yt));
                 }
-                g2x.push_back(grid_x_propagate_cols(M));
+                g2x.push_back(grid_x_propagate_cols(M, nw2));
                 g2y.push_back(p->F * nzc);
                 P3Args a3 = rows_args(p, g, Yt, reinterpret_cast<float2*>(ws + sc.off_V), bt->I.empty() ? nullptr : bt->I[i], 0, p->F);
                 i3.push_back(a3);
-                const int rb = rows_per_block_propagate(M, half);
+                const int rb = rows_per_block_propagate(M, nw3);
                 g3x.push_back((p->ny + rb - 1) / rb);
                 g3y.push_back(nzc);
                 w12.push_back((double)p->F * nzc);
                 w3.push_back((double)p->F);      // per block: one pass per frequency
             }
-            add(BK_P1, M, 0, i1, g1x, g1y, w1);
-            add(BK_P2, M, 0, i2, g2x, g2y, w12);
-            add(BK_P3, M, 0, i3, g3x, g3y, w3);
+            add(BK_P1, M, 0, nw1, i1, g1x, g1y, w1);
+            add(BK_P2, M, 0, nw2, i2, g2x, g2y, w12);
+            add(BK_P3, M, 0, nw3, i3, g3x, g3y, w3);
             if (!i3.empty()) bt->launches.back().half = half ? 1 : 0;
         }
     }
@@ -1263,7 +1378,38 @@ Group<A> group_of(nursd_batch* bt, const BatchLaunch& L) {
     return g;
 }
 
-int batch_enqueue(nursd_batch* bt, hipStream_t s) {
+// Timing hook of the kernel tuner: events around every grouped launch of
+// one (kind, size class) in an eager run of the launch sequence.
+struct LaunchTimer {
+    int kind = -1, size = 0;
+    std::vector<hipEvent_t> ev;    // pairs, created on demand
+    size_t used = 0;
+    ~LaunchTimer() {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t mark(hipStream_t s) {
+        if (used == ev.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev.push_back(e);
+        }
+        return hipEventRecord(ev[used++], s);
+    }
+    hipError_t total_ms(float* ms) {
+        *ms = 0.f;
+        for (size_t i = 0; i + 1 < used; i += 2) {
+            float t = 0.f;
+            hipError_t r = hipEventSynchronize(ev[i + 1]);
+            if (r == hipSuccess) r = hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            if (r != hipSuccess) return r;
+            *ms += t;
+        }
+        return hipSuccess;
+    }
+};
+
+int batch_enqueue(nursd_batch* bt, hipStream_t s, LaunchTimer* tm = nullptr) {
     // One work-queue counter per grouped launch; scenes propagated with
     // ordinary launches have none.
     for (const BatchLaunch& L : bt->launches)
@@ -1303,14 +1449,19 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s) {
             }
             continue;
         }
+        const bool timed_launch = tm && L.kind == tm->kind && L.size == tm->size;
+        if (timed_launch) HIP_TRY(tm->mark(s));
         switch (L.kind) {
             case BK_PHASOR: HIP_TRY(launch_phasor_grouped(L.size, L.fmax, group_of<PhasorArgs>(bt, L), s)); break;
-            case BK_SPREAD: HIP_TRY(launch_spread_xfft_grouped(L.size, group_of<SpreadArgs>(bt, L), s)); break;
-            case BK_FINEY: HIP_TRY(launch_fine_y_grouped(L.size, group_of<FineYArgs>(bt, L), s)); break;
-            case BK_P1: HIP_TRY(launch_kernel_rows_grouped(L.size, group_of<P1Args>(bt, L), s)); break;
-            case BK_P2: HIP_TRY(launch_propagate_cols_grouped(L.size, group_of<P2Args>(bt, L), s)); break;
-            default: HIP_TRY(launch_propagate_rows_grouped(L.size, L.half != 0, group_of<P3Args>(bt, L), s)); break;
+            case BK_SPREAD: HIP_TRY(launch_spread_xfft_grouped(L.size, L.var, group_of<SpreadArgs>(bt, L), s)); break;
+            case BK_FINEY: HIP_TRY(launch_fine_y_grouped(L.size, L.var, group_of<FineYArgs>(bt, L), s)); break;
+            case BK_P1: HIP_TRY(launch_kernel_rows_grouped(L.size, L.var, group_of<P1Args>(bt, L), s)); break;
+            case BK_P2: HIP_TRY(launch_propagate_cols_grouped(L.size, L.var, group_of<P2Args>(bt, L), s)); break;
+            default:
+                HIP_TRY(launch_propagate_rows_grouped(L.size, L.half != 0, L.var, group_of<P3Args>(bt, L), s));
+                break;
         }
+        if (timed_launch) HIP_TRY(tm->mark(s));
     }
     return NURSD_OK;
 }
@@ -1339,7 +1490,7 @@ int batch_capture(nursd_batch* bt) {
 // device table buffer on `s` through the pinned staging buffer (the host
 // waits only for this batch's previous table copy to leave the staging
 // buffer), then the launch sequence is captured as a graph.
-int batch_bind(nursd_batch* bt, const char* ws, hipStream_t s) {
+int batch_upload(nursd_batch* bt, const char* ws, hipStream_t s) {
     batch_tables(bt, bt->cfg, reinterpret_cast<uintptr_t>(ws));
     if (bt->tab.size() > bt->tab_cap || bt->n_counters > bt->counters_cap)
         return fail(NURSD_ERR_ARG, "batch tables exceed the buffers sized at creation");
@@ -1351,8 +1502,14 @@ int batch_bind(nursd_batch* bt, const char* ws, hipStream_t s) {
         bt->upload_pending = true;
     }
     bt->ws = ws;
+    return NURSD_OK;
+}
+
+int batch_bind(nursd_batch* bt, const char* ws, hipStream_t s) {
     bt->ready = false;
-    int rc = batch_capture(bt);
+    int rc = batch_upload(bt, ws, s);
+    if (rc) return rc;
+    rc = batch_capture(bt);
     if (rc) return rc;
     bt->ready = true;
     return NURSD_OK;
@@ -1377,6 +1534,108 @@ int batch_check_io(nursd_batch* bt, const float* const* hist, float* const* I, v
         bt->I[i] = I[i];
     }
     *changed = ch;
+    return NURSD_OK;
+}
+
+}  // namespace
+
+namespace {
+
+// Process-wide picks of the kernel tuner, keyed by (kind, size class, work
+// bucket = floor(log2) of the launch's total work items), so a later batch
+// of the same shape reuses them without timing.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, int> g_tune_cache;
+
+const char* kind_name(int kind) {
+    switch (kind) {
+        case BK_SPREAD: return "spread";
+        case BK_FINEY: return "fine_y";
+        case BK_P1: return "kernel_rows";
+        case BK_P2: return "propagate_cols";
+        case BK_P3: return "propagate_rows";
+        default: return "other";
+    }
+}
+
+std::string choice_name(int kind, int size, int var) {
+    if (kind == BK_SPREAD)
+        return "band_rows=" + std::to_string(spread_var_rows(var, size)) +
+               ",freqs_per_block=" + std::to_string(spread_var_freqs(var, size));
+    if (kind == BK_FINEY) return "lines_per_block=" + std::to_string(var);
+    return "waves_per_block=" + std::to_string(var);
+}
+
+// Second tuner stage: for the chosen configuration, each grouped launch
+// class (kind, size) in turn tries its schedule variants (spreading tile;
+// lines or waves per block of the transforms), timed with events around
+// that class's launches in an eager run of the whole sequence (best of
+// two runs), and keeps the fastest.  Picks are cached per process.
+int batch_tune_kernels(nursd_batch* bt, const char* ws, hipStream_t s) {
+    bt->tuned.clear();
+    int rc = batch_upload(bt, ws, s);
+    if (rc) return rc;
+    std::vector<std::tuple<int, int, int>> keys;      // kind, size, work bucket
+    {
+        std::map<std::pair<int, int>, double> work;
+        for (size_t i = 0; i < bt->sc.size(); ++i) {
+            const nursd_plan* p = bt->sc[i].p;
+            work[{BK_SPREAD, p->Mf}] += (double)p->F * p->L;
+            work[{BK_FINEY, p->Mf}] += (double)p->F * p->M;
+            if (!bt->sc[i].serial) {
+                if (!bt->sc[i].shared) work[{BK_P1, p->M}] += (double)p->F * p->nz;
+                work[{BK_P2, p->M}] += (double)p->F * p->nz;
+                work[{BK_P3, p->M}] += (double)p->F * p->nz;
+            }
+        }
+        for (const auto& kv : work)
+            keys.emplace_back(kv.first.first, kv.first.second, (int)std::floor(std::log2(std::max(1.0, kv.second))));
+    }
+    for (const auto& key : keys) {
+        const int kind = std::get<0>(key), size = std::get<1>(key);
+        const std::vector<int> cand = choice_candidates(bt, kind, size);
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end() && std::find(cand.begin(), cand.end(), it->second) != cand.end()) {
+                bt->choice[{kind, size}] = it->second;
+                bt->tuned.push_back(std::string(kind_name(kind)) + "/" + std::to_string(size) + ": " +
+                                    choice_name(kind, size, it->second) + " (cached)");
+                continue;
+            }
+        }
+        int best_v = batch_choice(bt, kind, size);
+        float best = 1e30f, def_ms = -1.f;
+        for (int v : cand) {
+            bt->choice[{kind, size}] = v;
+            if ((rc = batch_upload(bt, ws, s))) return rc;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 2; ++rep) {
+                LaunchTimer tm;
+                tm.kind = kind;
+                tm.size = size;
+                if ((rc = batch_enqueue(bt, s, &tm))) return rc;
+                float t = 0.f;
+                const hipError_t e = tm.total_ms(&t);
+                if (e != hipSuccess) return fail(NURSD_ERR_HIP, std::string("kernel tuner: ") + hipGetErrorString(e));
+                ms = std::min(ms, t);
+            }
+            if (v == default_choice(kind)) def_ms = ms;
+            if (ms < best) {
+                best = ms;
+                best_v = v;
+            }
+        }
+        bt->choice[{kind, size}] = best_v;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tune_cache[key] = best_v;
+        }
+        char buf[96];
+        std::snprintf(buf, sizeof buf, " (%.3f ms, default %.3f ms)", best, def_ms);
+        bt->tuned.push_back(std::string(kind_name(kind)) + "/" + std::to_string(size) + ": " +
+                            choice_name(kind, size, best_v) + buf);
+    }
     return NURSD_OK;
 }
 
@@ -2200,6 +2459,35 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
     bt->hist.assign(n, nullptr);
     bt->I.assign(n, nullptr);
     if (int rc = batch_kernel_classes(bt)) return bail(rc);
+    // Relay lists for the other spreading band heights the tuner may try.
+    bt->lists.assign(n, {});
+    if (bt->autotune) {
+        for (int i = 0; i < n; ++i) {
+            const nursd_plan* p = plans[i];
+            for (int br : {4, 16}) {
+                if (br == spread_band_rows(p->Mf) || p->Mf / br < 2) continue;
+                SpreadLists sl;
+                if (int rc = bin_relays(p, p->h_relay, br, sl)) return bail(rc);
+                BatchLists bl;
+                bl.nbands = sl.nbands;
+                auto put = [&](const void* src, size_t bytes, void** dst) -> int {
+                    HIP_TRY(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+                    bt->owned.push_back(*dst);
+                    if (bytes) HIP_TRY(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+                    return NURSD_OK;
+                };
+                void *d0 = nullptr, *d1 = nullptr, *d2 = nullptr;
+                int rc = put(sl.ent.data(), sl.ent.size() * sizeof(SpreadEntry), &d0);
+                if (!rc) rc = put(sl.band_ptr.data(), sl.band_ptr.size() * sizeof(int), &d1);
+                if (!rc) rc = put(sl.wave_rng.data(), sl.wave_rng.size() * sizeof(int), &d2);
+                if (rc) return bail(rc);
+                bl.ent = static_cast<SpreadEntry*>(d0);
+                bl.band_ptr = static_cast<int*>(d1);
+                bl.wave_rng = static_cast<int*>(d2);
+                bt->lists[i][br] = bl;
+            }
+        }
+    }
     // Default configuration: work queue, scenes with M >= 512 chunk by chunk,
     // the fewest rounds whose propagation scratch fits the default budget.
     std::vector<int> rounds;
@@ -2226,17 +2514,22 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
         }
         if (bt->cands.empty()) bt->cands.push_back(bt->cfg);
     }
-    // Size the workspace and the device tables for every candidate.
+    // Size the workspace and the device tables for every candidate, with the
+    // default schedule variants and (for the tuner) the finest ones.
     size_t tab_max = 0;
     int cnt_max = 0;
-    for (const BatchConfig& c : bt->cands) {
-        bt->ws_need = std::max(bt->ws_need, batch_layout(bt, c));
-        size_t tb = 0;
-        int cn = 0;
-        batch_table_size(bt, c, &tb, &cn);
-        tab_max = std::max(tab_max, tb);
-        cnt_max = std::max(cnt_max, cn);
+    for (int pass = 0; pass < (bt->autotune ? 2 : 1); ++pass) {
+        if (pass == 1) finest_choices(bt);
+        for (const BatchConfig& c : bt->cands) {
+            bt->ws_need = std::max(bt->ws_need, batch_layout(bt, c));
+            size_t tb = 0;
+            int cn = 0;
+            batch_table_size(bt, c, &tb, &cn);
+            tab_max = std::max(tab_max, tb);
+            cnt_max = std::max(cnt_max, cn);
+        }
     }
+    bt->choice.clear();
     bt->ws_need = std::max(bt->ws_need, batch_layout(bt, bt->cfg));
     bt->tab.clear();
     bt->launches.clear();
@@ -2314,6 +2607,10 @@ int nursd_batch_autotune(nursd_batch* bt, const float* const* hist, float* const
         bt->ready = false;
         return rc;
     }
+    if ((rc = batch_tune_kernels(bt, static_cast<const char*>(ws), s))) {
+        bt->ready = false;
+        return rc;
+    }
     return batch_bind(bt, static_cast<const char*>(ws), s);
 }
 
@@ -2340,6 +2637,14 @@ int nursd_batch_info(const nursd_batch* bt, int32_t* budget, int32_t* launches, 
         if (tried_ms) tried_ms[i] = bt->tried_ms[i];
     }
     if (workspace_bytes) *workspace_bytes = bt->ws_need;
+    return NURSD_OK;
+}
+
+int nursd_batch_tuning(const nursd_batch* bt, char* buf, size_t len) {
+    if (!bt || !buf || len == 0) return fail(NURSD_ERR_ARG, "NULL argument");
+    std::string t;
+    for (size_t i = 0; i < bt->tuned.size(); ++i) t += (i ? "; " : "") + bt->tuned[i];
+    std::snprintf(buf, len, "%s", t.c_str());
     return NURSD_OK;
 }
 

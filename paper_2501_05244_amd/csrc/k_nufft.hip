@@ -37,10 +37,8 @@ __device__ __forceinline__ float lane_f(float v, int j) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
 }
 
-template <int MF>
+template <int MF, int kBandRows = spread_band_rows(MF), int NF = spread_freqs(MF)>
 __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, int by) {
-    constexpr int kBandRows = spread_band_rows(MF);
-    constexpr int NF = spread_freqs(MF);
     constexpr int LDT = spread_row_stride<MF>();
     extern __shared__ float2 tile[];   // [NF][kBandRows][LDT]
     const int band = bx;
@@ -128,22 +126,24 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
 constexpr int kFineYThreads = 256;
 constexpr int kFineYLines = 4;
 
-template <int MF>
+// NL lines of MF points per workgroup, NT / NL threads per line (the
+// batched variants keep 64 threads per line).
+template <int MF, int NL = kFineYLines, int NT = kFineYThreads>
 __device__ __forceinline__ void fine_y_body(const FineYArgs& a, int bx, int by) {
-    extern __shared__ float2 buf[];    // [kFineYLines][MF]
+    extern __shared__ float2 buf[];    // [NL][MF]
     const int M = a.M;
-    const int kx0 = bx * kFineYLines;
+    const int kx0 = bx * NL;
     const int fb = by;
     const float2* T1 = a.T1 + (size_t)fb * M * MF;
     float2* U = a.U + (size_t)(a.b0 + fb) * M * M;
     const int tid = threadIdx.x;
-    for (int i = tid; i < kFineYLines * MF; i += kFineYThreads) {
+    for (int i = tid; i < NL * MF; i += NT) {
         const int l = i / MF, c = i % MF;
         buf[i] = T1[(size_t)(kx0 + l) * MF + c];
     }
     __syncthreads();
-    fft_lines<MF, kFineYThreads / kFineYLines, false>(buf, MF, kFineYLines, a.tw);
-    for (int i = tid; i < kFineYLines * M; i += kFineYThreads) {
+    fft_lines<MF, NT / NL, false>(buf, MF, NL, a.tw);
+    for (int i = tid; i < NL * M; i += NT) {
         const int l = i / M, km = i % M;
         const int kf = km < M / 2 ? km : km + (MF - M);
         U[(size_t)(kx0 + l) * M + km] = cscale(buf[l * MF + kf], a.decy[km]);
@@ -154,17 +154,17 @@ template <int MF>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
     spread_xfft_body<MF>(a, blockIdx.x, blockIdx.y);
 }
-template <int MF>
+template <int MF, int BR, int NF>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_grouped(Group<SpreadArgs> g) {
-    persistent_loop(g, [](const SpreadArgs& a, int bx, int by) { spread_xfft_body<MF>(a, bx, by); });
+    persistent_loop(g, [](const SpreadArgs& a, int bx, int by) { spread_xfft_body<MF, BR, NF>(a, bx, by); });
 }
 template <int MF>
 __global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
     fine_y_body<MF>(a, blockIdx.x, blockIdx.y);
 }
-template <int MF>
-__global__ __launch_bounds__(kFineYThreads) void k_fine_y_grouped(Group<FineYArgs> g) {
-    persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_body<MF>(a, bx, by); });
+template <int MF, int NL>
+__global__ __launch_bounds__(NL * 64) void k_fine_y_grouped(Group<FineYArgs> g) {
+    persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_body<MF, NL, NL * 64>(a, bx, by); });
 }
 
 
@@ -236,23 +236,74 @@ hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s) {
     }
 }
 
-hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStream_t s) {
-    switch (Mf) {
-#define NURSD_SG(n) \
-    case n: return launch_grouped(k_spread_xfft_grouped<n>, g, kSpreadThreads, \
-                                  (size_t)spread_freqs(n) * spread_band_rows(n) * spread_row_stride<n>() * sizeof(float2), s);
-        NURSD_SG(128) NURSD_SG(256) NURSD_SG(512) NURSD_SG(1024) NURSD_SG(2048)
-#undef NURSD_SG
+// A spreading tile (BR rows of NF frequencies, row stride MF + 8) fits LDS
+// and the in-LDS transform keeps at least one wavefront per line.
+constexpr bool spread_fits(int MF, int BR, int NF) {
+    return BR * NF <= 16 && (size_t)BR * NF * (MF + 8) * sizeof(float2) <= 160 * 1024 && MF / BR >= 1;
+}
+
+template <int MF, int BR, int NF>
+static hipError_t spread_grouped(const Group<SpreadArgs>& g, hipStream_t s) {
+    if constexpr (spread_fits(MF, BR, NF)) {
+        return launch_grouped(k_spread_xfft_grouped<MF, BR, NF>, g, kSpreadThreads,
+                              (size_t)NF * BR * spread_row_stride<MF>() * sizeof(float2), s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int MF>
+static hipError_t spread_grouped_mf(int var, const Group<SpreadArgs>& g, hipStream_t s) {
+    switch (var) {
+        case 0: return spread_grouped<MF, spread_band_rows(MF), spread_freqs(MF)>(g, s);
+        case spread_var(4, 1): return spread_grouped<MF, 4, 1>(g, s);
+        case spread_var(4, 2): return spread_grouped<MF, 4, 2>(g, s);
+        case spread_var(4, 4): return spread_grouped<MF, 4, 4>(g, s);
+        case spread_var(8, 1): return spread_grouped<MF, 8, 1>(g, s);
+        case spread_var(8, 2): return spread_grouped<MF, 8, 2>(g, s);
+        case spread_var(16, 1): return spread_grouped<MF, 16, 1>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_fine_y_grouped(int Mf, const Group<FineYArgs>& g, hipStream_t s) {
+bool spread_var_ok(int Mf, int var) {
+    if (Mf < 128 || Mf > 2048 || (Mf & (Mf - 1))) return false;
+    if (var == 0) return true;
+    const int br = var / 10, nf = var % 10;
+    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1)))
+        return false;
+    return spread_fits(Mf, br, nf);
+}
+
+hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s) {
     switch (Mf) {
-#define NURSD_FG(n) \
-    case n: return launch_grouped(k_fine_y_grouped<n>, g, kFineYThreads, (size_t)kFineYLines * n * sizeof(float2), s);
-        NURSD_FG(128) NURSD_FG(256) NURSD_FG(512) NURSD_FG(1024) NURSD_FG(2048)
+        case 128: return spread_grouped_mf<128>(var, g, s);
+        case 256: return spread_grouped_mf<256>(var, g, s);
+        case 512: return spread_grouped_mf<512>(var, g, s);
+        case 1024: return spread_grouped_mf<1024>(var, g, s);
+        case 2048: return spread_grouped_mf<2048>(var, g, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int MF>
+static hipError_t fine_y_grouped_mf(int lines, const Group<FineYArgs>& g, hipStream_t s) {
+    switch (lines) {
+#define NURSD_FG(NL) \
+    case NL: return launch_grouped(k_fine_y_grouped<MF, NL>, g, NL * 64, (size_t)NL * MF * sizeof(float2), s);
+        NURSD_FG(2) NURSD_FG(4) NURSD_FG(8)
 #undef NURSD_FG
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_fine_y_grouped(int Mf, int lines, const Group<FineYArgs>& g, hipStream_t s) {
+    switch (Mf) {
+        case 128: return fine_y_grouped_mf<128>(lines, g, s);
+        case 256: return fine_y_grouped_mf<256>(lines, g, s);
+        case 512: return fine_y_grouped_mf<512>(lines, g, s);
+        case 1024: return fine_y_grouped_mf<1024>(lines, g, s);
+        case 2048: return fine_y_grouped_mf<2048>(lines, g, s);
         default: return hipErrorInvalidValue;
     }
 }

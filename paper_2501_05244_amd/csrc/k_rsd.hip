@@ -75,13 +75,13 @@ __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int&
 #endif
 constexpr int kP1Waves = NURSD_P1_WAVES;
 
-template <int M>
+template <int M, int NW = kP1Waves>
 __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = F::SCR + 1;
-    extern __shared__ float2 sm[];      // [kP1Waves][SCRP], twiddles [M], Nyquist samples [LB]
-    float2* tws = sm + kP1Waves * SCRP;
-    for (int i = threadIdx.x; i < M; i += kP1Waves * 64) tws[i] = a.tw[i];
+    extern __shared__ float2 sm[];      // [NW][SCRP], twiddles [M], Nyquist samples [LB]
+    float2* tws = sm + NW * SCRP;
+    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
     const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
@@ -90,7 +90,7 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
     const double px = a.g.pitch_x ? a.g.pitch_x[iz] : a.g.dx;
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    constexpr int LB = kP1Waves * LPW;
+    constexpr int LB = NW * LPW;
     const int my0 = bx * LB;
     // For M >= 128 the sample n = M/2 of a row sits alone in slot E/2 of lane
     // 0; the block computes those LB samples once, one per thread, instead of
@@ -150,7 +150,7 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
     }
     __syncthreads();
     float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
-    for (int i = tid; i < (H + 1) * LB; i += kP1Waves * 64) {
+    for (int i = tid; i < (H + 1) * LB; i += NW * 64) {
         const int kx = i / LB, j = i % LB;
         const int my = my0 + j;
         if (my <= H) Bt[(size_t)kx * a.BS + my] = sm[(j / LPW) * SCRP + (j % LPW) * (H + 1) + kx];
@@ -166,17 +166,17 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
 #endif
 constexpr int kP2Waves = NURSD_P2_WAVES;
 
-template <int M>
+template <int M, int NW = kP2Waves>
 __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
-    extern __shared__ float2 sm[];      // [kP2Waves][SCR], then twiddles [M]
-    float2* tws = sm + kP2Waves * F::SCR;
+    extern __shared__ float2 sm[];      // [NW][SCR], then twiddles [M]
+    float2* tws = sm + NW * F::SCR;
     const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int kx0 = (bx * kP2Waves + wave) * LPW;
+    const int kx0 = (bx * NW + wave) * LPW;
     float2* scr = sm + wave * F::SCR;
     const int kp = a.kidx ? a.kidx[b * a.kz + iz] : p;
     const float2* Bt = a.Bt + (size_t)kp * (H + 1) * a.BS;
@@ -193,7 +193,7 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
             v[q * E + e] = kx <= H ? Bt[(size_t)kx * a.BS + dd] : make_float2(0.f, 0.f);
         }
     }
-    for (int i = threadIdx.x; i < M; i += kP2Waves * 64) tws[i] = a.tw[i];
+    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
     __syncthreads();
     if (kx0 > H) return;                // wave-uniform; no block barriers below
     const float2* Ub = a.U + (size_t)b * M * M;
@@ -266,9 +266,8 @@ constexpr int p3_waves() { return (M >= 1024 || !HALF) ? 8 : NURSD_P3_WAVES; }
 // With nx <= M/2 (zero padding >= 2) only permuted slots d in {0, 1, 6, 7}
 // of each 8-point group can fall inside the window (|m'| < M/4); HALF keeps
 // per-voxel state for those four slots only.
-// The persistent (grouped) launches run 8 waves per block at every size: with
-// the work-queue loop around the body, 16 waves (128 VGPRs each) spill.
-constexpr int kP3GroupWaves = 8;
+// The persistent (grouped) launches run 4 or 8 waves per block: with the
+// work-queue loop around the body, 16 waves (128 VGPRs each) spill.
 
 template <int M, bool HALF, int NW = p3_waves<M, HALF>()>
 __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
@@ -410,9 +409,11 @@ template <int M>
 __global__ __launch_bounds__(kP1Waves * 64) void k_kernel_rows(P1Args a) {
     kernel_rows_body<M>(a, blockIdx.x, blockIdx.y);
 }
-template <int M>
-__global__ __launch_bounds__(kP1Waves * 64, (M >= 1024 ? 4 : 8)) void k_kernel_rows_grouped(Group<P1Args> g) {
-    persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M>(a, bx, by); });
+// Grouped (batched) variants take the waves per block as a template
+// parameter: the batch's tuner picks one per transform size.
+template <int M, int NW>
+__global__ __launch_bounds__(NW * 64, (M >= 1024 ? 4 : 8)) void k_kernel_rows_grouped(Group<P1Args> g) {
+    persistent_loop(g, [](const P1Args& a, int bx, int by) { kernel_rows_body<M, NW>(a, bx, by); });
 }
 // The column pass renumbers its workgroups (xcd_contiguous) so that each XCD
 // works through a contiguous run of (plane, kx block) work items: the planes
@@ -423,18 +424,18 @@ __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
     const int v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
     propagate_cols_body<M>(a, v % gridDim.x, v / gridDim.x);
 }
-template <int M>
-__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
-    persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M>(a, bx, by); });
+template <int M, int NW>
+__global__ __launch_bounds__(NW * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
+    persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M, NW>(a, bx, by); });
 }
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
     const int v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
     propagate_rows_body<M, HALF>(a, v % gridDim.x, v / gridDim.x);
 }
-template <int M, bool HALF>
-__global__ __launch_bounds__(kP3GroupWaves * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
-    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF, kP3GroupWaves>(a, bx, by); });
+template <int M, bool HALF, int NW>
+__global__ __launch_bounds__(NW * 64) void k_propagate_rows_grouped(Group<P3Args> g) {
+    persistent_loop(g, [](const P3Args& a, int bx, int by) { propagate_rows_body<M, HALF, NW>(a, bx, by); });
 }
 
 template <typename Args>
@@ -523,51 +524,76 @@ hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
     })
 }
 
-hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t s) {
-    NURSD_SWITCH_M(M, {
-        using F = WaveFFT<MM>;
-        return launch_grouped(k_kernel_rows_grouped<MM>, g, kP1Waves * 64,
-                              (size_t)(kP1Waves * (F::SCR + 1) + MM + kP1Waves * F::LPW) * sizeof(float2), s);
-    })
+template <int M, int W>
+static hipError_t p1_grouped(const Group<P1Args>& g, hipStream_t s) {
+    using F = WaveFFT<M>;
+    return launch_grouped(k_kernel_rows_grouped<M, W>, g, W * 64,
+                          (size_t)(W * (F::SCR + 1) + M + W * F::LPW) * sizeof(float2), s);
 }
-
-hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStream_t s) {
-    NURSD_SWITCH_M(M, {
-        using F = WaveFFT<MM>;
-        return launch_grouped(k_propagate_cols_grouped<MM>, g, kP2Waves * 64,
-                              (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s);
-    })
+template <int M, int W>
+static hipError_t p2_grouped(const Group<P2Args>& g, hipStream_t s) {
+    using F = WaveFFT<M>;
+    return launch_grouped(k_propagate_cols_grouped<M, W>, g, W * 64, (size_t)(W * F::SCR + M) * sizeof(float2), s);
 }
-
-hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s) {
-    NURSD_SWITCH_M(M, {
-        using F = WaveFFT<MM>;
-        constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
-        constexpr int NW = kP3GroupWaves;
-        if (half)
-            return launch_grouped(k_propagate_rows_grouped<MM, true>, g, NW * 64,
-                                  (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
-        return launch_grouped(k_propagate_rows_grouped<MM, false>, g, NW * 64,
-                              (size_t)(2 * NW * SCRP + MM) * sizeof(float2), s);
-    })
+template <int M, int W>
+static hipError_t p3_grouped(bool half, const Group<P3Args>& g, hipStream_t s) {
+    using F = WaveFFT<M>;
+    constexpr int SCRP = (F::SCR > F::LPW * M ? F::SCR : F::LPW * M) + 1;
+    constexpr size_t sh = (size_t)(2 * W * SCRP + M) * sizeof(float2);
+    if (half) return launch_grouped(k_propagate_rows_grouped<M, true, W>, g, W * 64, sh, s);
+    return launch_grouped(k_propagate_rows_grouped<M, false, W>, g, W * 64, sh, s);
 }
-
-int grid_x_kernel_rows(int M) {
-    switch (M) {
-        case 64: return (33 + kP1Waves * 8 - 1) / (kP1Waves * 8);
-        case 128: return (65 + kP1Waves * 4 - 1) / (kP1Waves * 4);
-        case 256: return (129 + kP1Waves * 2 - 1) / (kP1Waves * 2);
-        case 512: return (257 + kP1Waves - 1) / kP1Waves;
-        default: return (513 + kP1Waves - 1) / kP1Waves;
+template <int M>
+static hipError_t p1_grouped_m(int nw, const Group<P1Args>& g, hipStream_t s) {
+    switch (nw) {
+        case 4: return p1_grouped<M, 4>(g, s);
+        case 8: return p1_grouped<M, 8>(g, s);
+        default: return hipErrorInvalidValue;
     }
 }
-int grid_x_propagate_cols(int M) {
-    const int lpw = M >= 512 ? 1 : 512 / M;
-    return (M / 2 + 1 + kP2Waves * lpw - 1) / (kP2Waves * lpw);
+template <int M>
+static hipError_t p2_grouped_m(int nw, const Group<P2Args>& g, hipStream_t s) {
+    switch (nw) {
+        case 2: return p2_grouped<M, 2>(g, s);
+        case 4: return p2_grouped<M, 4>(g, s);
+        case 8: return p2_grouped<M, 8>(g, s);
+        default: return hipErrorInvalidValue;
+    }
 }
-int rows_per_block_propagate(int M, bool) {
+template <int M>
+static hipError_t p3_grouped_m(bool half, int nw, const Group<P3Args>& g, hipStream_t s) {
+    switch (nw) {
+        case 4: return p3_grouped<M, 4>(half, g, s);
+        case 8: return p3_grouped<M, 8>(half, g, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, return p1_grouped_m<MM>(nw, g, s));
+}
+
+hipError_t launch_propagate_cols_grouped(int M, int nw, const Group<P2Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, return p2_grouped_m<MM>(nw, g, s));
+}
+
+hipError_t launch_propagate_rows_grouped(int M, bool half, int nw, const Group<P3Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, return p3_grouped_m<MM>(half, nw, g, s));
+}
+
+// Blocks along x of one (plane or depth) of the three passes at M with nw
+// waves per block.
+int grid_x_kernel_rows(int M, int nw) {
     const int lpw = M >= 512 ? 1 : 512 / M;
-    return kP3GroupWaves * lpw;
+    return (M / 2 + 1 + nw * lpw - 1) / (nw * lpw);
+}
+int grid_x_propagate_cols(int M, int nw) {
+    const int lpw = M >= 512 ? 1 : 512 / M;
+    return (M / 2 + 1 + nw * lpw - 1) / (nw * lpw);
+}
+int rows_per_block_propagate(int M, int nw) {
+    const int lpw = M >= 512 ? 1 : 512 / M;
+    return nw * lpw;
 }
 
 }  // namespace nursd

@@ -297,14 +297,25 @@ hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- grouped launches
 hipError_t launch_phasor_grouped(int T, int F_max, const Group<PhasorArgs>& g, hipStream_t s);
-hipError_t launch_spread_xfft_grouped(int Mf, const Group<SpreadArgs>& g, hipStream_t s);
-hipError_t launch_fine_y_grouped(int Mf, const Group<FineYArgs>& g, hipStream_t s);
-hipError_t launch_kernel_rows_grouped(int M, const Group<P1Args>& g, hipStream_t s);
-hipError_t launch_propagate_cols_grouped(int M, const Group<P2Args>& g, hipStream_t s);
-hipError_t launch_propagate_rows_grouped(int M, bool half, const Group<P3Args>& g, hipStream_t s);
-int grid_x_kernel_rows(int M);
-int grid_x_propagate_cols(int M);
-int rows_per_block_propagate(int M, bool half);
+// Grouped launches of the batched mode.  Each takes a schedule variant of its
+// kernel, which the batch's tuner picks per size class:
+//   spreading: spread_var(BR, NF) = BR * 10 + NF (band rows, frequencies
+//     per workgroup; 0 = the plan default), valid where spread_var_ok;
+//   fine y: lines per workgroup (2, 4, 8; 64 threads per line);
+//   kernel rows: waves per block (4, 8); column pass: waves per block
+//   (2, 4, 8); last pass: waves per block (4, 8).
+constexpr int spread_var(int br, int nf) { return br * 10 + nf; }
+constexpr int spread_var_rows(int var, int Mf) { return var ? var / 10 : spread_band_rows(Mf); }
+constexpr int spread_var_freqs(int var, int Mf) { return var ? var % 10 : spread_freqs(Mf); }
+bool spread_var_ok(int Mf, int var);
+hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s);
+hipError_t launch_fine_y_grouped(int Mf, int lines, const Group<FineYArgs>& g, hipStream_t s);
+hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hipStream_t s);
+hipError_t launch_propagate_cols_grouped(int M, int nw, const Group<P2Args>& g, hipStream_t s);
+hipError_t launch_propagate_rows_grouped(int M, bool half, int nw, const Group<P3Args>& g, hipStream_t s);
+int grid_x_kernel_rows(int M, int nw);
+int grid_x_propagate_cols(int M, int nw);
+int rows_per_block_propagate(int M, int nw);
 int fine_y_lines();
 int phasor_group();
 hipError_t launch_zero_counters(int* c, int n, hipStream_t s);

@@ -60,6 +60,11 @@ def test_batch_matches_plain_loop(device, autotune):
     assert info["serial"] in ("none", "M>=256", "M>=512")
     if autotune:
         assert len(info["tried"]) >= 3
+        # second tuner stage: one pick per grouped launch class (spreading
+        # tile, lines or waves per block), each with its measured time
+        print("  kernel choices:", info["kernel_choices"], flush=True)
+        kinds = {c.split("/")[0] for c in info["kernel_choices"]}
+        assert {"spread", "fine_y"} <= kinds
     # new output buffers: tables are re-uploaded, results unchanged
     outs2 = batch.forward(hists, [torch.zeros_like(x) for x in outs])
     for a, b in zip(outs2, plain):
