@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <stdexcept>
 #include <tuple>
 #include <string>
 #include <vector>
@@ -34,7 +35,31 @@ int fail(int code, const std::string& msg) {
             return fail(NURSD_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+#define NURSD_GUARD(call)                                                   \
+    do {                                                                    \
+        try {                                                               \
+            return call;                                                    \
+        } catch (const std::exception& ex_) {                               \
+            return fail(NURSD_ERR_HIP, std::string("host exception: ") + ex_.what()); \
+        } catch (...) {                                                     \
+            return fail(NURSD_ERR_HIP, "host exception");                   \
+        }                                                                   \
+    } while (0)
+
 constexpr int kSupportedM[] = {64, 128, 256, 512, 1024};
+
+// Spreading tile of the plans' own launches (spread_var(band rows,
+// frequencies per workgroup)), for 3D (depth-mode) plans and others: 4 x 4
+// measured 6 % faster than 8 x 2 at the SPAD workload and 5 % faster in the
+// 3D stage 1 (2 x 8 and 1 x 16 slower: the walk is bound by the per-entry
+// read-modify-write steps, not by the kernel weights they share).  Sizes
+// whose tile does not fit LDS keep 8 x 2 (or 8 x 1).
+#ifndef NURSD_PLAN_SPREAD_VAR
+#define NURSD_PLAN_SPREAD_VAR 404
+#endif
+#ifndef NURSD_PLAN3D_SPREAD_VAR
+#define NURSD_PLAN3D_SPREAD_VAR 404
+#endif
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -156,6 +181,7 @@ struct nursd_plan {
     int* d_band_ptr = nullptr;
     int* d_wave_rng = nullptr;
     int nbands = 0, n_ent = 0;
+    int spread_var = 0;           // spreading tile of the plan's own launches (spread_var)
     std::vector<float> h_relay;   // host copy of the binned relay positions [L][2]
     // per-kernel event timing
     uint32_t prof_mask = 0;
@@ -342,7 +368,7 @@ int build_spread_lists(nursd_plan* p, const std::vector<float>& rxy) {
     const int Mf = p->Mf, w = p->w;
     const double hw = 0.5 * w;
     SpreadLists sl;
-    if (int rc = bin_relays(p, rxy, spread_band_rows(Mf), sl)) return rc;
+    if (int rc = bin_relays(p, rxy, spread_var_rows(p->spread_var, Mf), sl)) return rc;
     p->nbands = sl.nbands;
     p->n_ent = (int)sl.ent.size();
     p->h_relay = rxy;
@@ -514,6 +540,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
     for (int b0 = 0; b0 < n; b0 += p->FCn) {
         const int nb = std::min(p->FCn, n - b0);
         SpreadArgs sa{};
+        sa.var = p->spread_var;
         sa.P = P;
         sa.wts = p->d_w;
         sa.ent = p->d_ent;
@@ -863,6 +890,7 @@ struct nursd_batch {
     std::vector<std::map<int, BatchLists>> lists;   // per scene: band rows -> lists
     std::vector<void*> owned;                       // device buffers of those lists
     std::vector<std::string> tuned;                 // what the kernel tuner picked, with times
+    bool lists_missing = false;                     // a spreading tile without relay lists was asked for
     int autotune = 0;
     BatchConfig cfg;                 // configuration in use
     std::vector<BatchConfig> cands;  // configurations the tuner times
@@ -992,21 +1020,27 @@ int default_choice(int kind) {
 }
 int batch_choice(const nursd_batch* bt, int kind, int size) {
     auto it = bt->choice.find({kind, size});
-    return it == bt->choice.end() ? default_choice(kind) : it->second;
+    if (it != bt->choice.end()) return it->second;
+    if (kind == BK_SPREAD) {             // the plans' own tile (the first plan of the size class)
+        for (const auto& sc : bt->sc)
+            if (sc.p->Mf == size) return sc.p->spread_var;
+    }
+    return default_choice(kind);
 }
 // Candidate variants of a (kind, size class) the tuner times.
 std::vector<int> choice_candidates(const nursd_batch* bt, int kind, int size) {
     std::vector<int> v;
     switch (kind) {
         case BK_SPREAD:
-            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1)}) {
+            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1),
+                          spread_var(2, 8), spread_var(1, 16)}) {
                 if (!spread_var_ok(size, c)) continue;
                 const int br = spread_var_rows(c, size);
-                bool have = br == spread_band_rows(size);
-                if (!have) {
-                    have = true;
-                    for (size_t i = 0; i < bt->sc.size(); ++i)
-                        if (bt->sc[i].p->Mf == size && !bt->lists[i].count(br)) have = false;
+                bool have = true;
+                for (size_t i = 0; i < bt->sc.size(); ++i) {
+                    const nursd_plan* p = bt->sc[i].p;
+                    if (p->Mf == size && br != spread_var_rows(p->spread_var, size) && !bt->lists[i].count(br))
+                        have = false;
                 }
                 if (have && (c == 0 || c != spread_var(spread_band_rows(size), spread_freqs(size)))) v.push_back(c);
             }
@@ -1241,12 +1275,16 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             a.band_ptr = p->d_band_ptr;
             a.wave_rng = p->d_wave_rng;
             int nbands = p->nbands;
-            if (BR != spread_band_rows(Mf)) {     // lists the batch binned for this band height
-                const BatchLists& bl = bt->lists[i].at(BR);
-                a.ent = bl.ent;
-                a.band_ptr = bl.band_ptr;
-                a.wave_rng = bl.wave_rng;
-                nbands = bl.nbands;
+            if (BR != spread_var_rows(p->spread_var, Mf)) {     // lists the batch binned for this band height
+                auto li = bt->lists[i].find(BR);
+                if (li == bt->lists[i].end()) {
+                    bt->lists_missing = true;        // reported by batch_upload / creation
+                } else {
+                    a.ent = li->second.ent;
+                    a.band_ptr = li->second.band_ptr;
+                    a.wave_rng = li->second.wave_rng;
+                    nbands = li->second.nbands;
+                }
             }
             a.T1 = reinterpret_cast<float2*>(ws + sc.off_T1);
             a.decx = p->d_decx;
@@ -1491,7 +1529,9 @@ int batch_capture(nursd_batch* bt) {
 // waits only for this batch's previous table copy to leave the staging
 // buffer), then the launch sequence is captured as a graph.
 int batch_upload(nursd_batch* bt, const char* ws, hipStream_t s) {
+    bt->lists_missing = false;
     batch_tables(bt, bt->cfg, reinterpret_cast<uintptr_t>(ws));
+    if (bt->lists_missing) return fail(NURSD_ERR_ARG, "batch spreading tile without binned relay lists");
     if (bt->tab.size() > bt->tab_cap || bt->n_counters > bt->counters_cap)
         return fail(NURSD_ERR_ARG, "batch tables exceed the buffers sized at creation");
     if (bt->upload_pending) HIP_TRY(hipEventSynchronize(bt->upload_done));
@@ -1691,7 +1731,7 @@ void nursd_default_options(nursd_wavelet* wl, nursd_geometry* geo, nursd_options
     }
 }
 
-int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const nursd_options* opt,
+static int nursd_plan_create_body(const nursd_wavelet* wl, const nursd_geometry* geo, const nursd_options* opt,
                       const float* relay_xy_dev, void* stream, nursd_plan** out) {
     if (!out) return fail(NURSD_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -2065,6 +2105,8 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
             if (!std::isfinite(v)) return bail(fail(NURSD_ERR_ARG, "non-finite sample weight"));
         if ((rc = upload(p, wv, &p->d_w))) return bail(rc);
     }
+    p->spread_var = p->mode == NURSD_MODE_GRID3D ? NURSD_PLAN3D_SPREAD_VAR : NURSD_PLAN_SPREAD_VAR;
+    if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = 0;
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);
     // device address of the fixed scratch of nursd_forward_hist_static on
@@ -2075,7 +2117,7 @@ int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const 
     return NURSD_OK;
 }
 
-int nursd_plan_set_points(nursd_plan* p, const float* relay_xy_dev, void* stream) {
+static int nursd_plan_set_points_body(nursd_plan* p, const float* relay_xy_dev, void* stream) {
     if (!p || !relay_xy_dev) return fail(NURSD_ERR_ARG, "NULL argument");
     std::vector<float> rxy;
     int rc = read_points(relay_xy_dev, (size_t)p->L * 2, rxy, static_cast<hipStream_t>(stream));
@@ -2431,7 +2473,7 @@ int nursd_adjoint(nursd_plan* p, const void* grad_vol, const void* P, void* grad
     return NURSD_OK;
 }
 
-int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream, nursd_batch** out) {
+static int nursd_batch_create_body(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream, nursd_batch** out) {
     (void)stream;
     if (!out) return fail(NURSD_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -2459,13 +2501,17 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
     bt->hist.assign(n, nullptr);
     bt->I.assign(n, nullptr);
     if (int rc = batch_kernel_classes(bt)) return bail(rc);
-    // Relay lists for the other spreading band heights the tuner may try.
+    // Relay lists for the other spreading band heights the tuner may try, or
+    // (without tuning) for the tile of the first plan of the size class when
+    // a plan's own tile differs.
     bt->lists.assign(n, {});
-    if (bt->autotune) {
+    {
         for (int i = 0; i < n; ++i) {
             const nursd_plan* p = plans[i];
-            for (int br : {4, 16}) {
-                if (br == spread_band_rows(p->Mf) || p->Mf / br < 2) continue;
+            const int class_br = spread_var_rows(batch_choice(bt, BK_SPREAD, p->Mf), p->Mf);
+            for (int br : {1, 2, 4, 8, 16}) {
+                if (br == spread_var_rows(p->spread_var, p->Mf) || p->Mf / br < 2) continue;
+                if (!bt->autotune && br != class_br) continue;
                 SpreadLists sl;
                 if (int rc = bin_relays(p, p->h_relay, br, sl)) return bail(rc);
                 BatchLists bl;
@@ -2531,6 +2577,7 @@ int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, vo
     }
     bt->choice.clear();
     bt->ws_need = std::max(bt->ws_need, batch_layout(bt, bt->cfg));
+    if (bt->lists_missing) return bail(fail(NURSD_ERR_ARG, "batch spreading tile without binned relay lists"));
     bt->tab.clear();
     bt->launches.clear();
     hipError_t e;
@@ -2564,7 +2611,7 @@ int nursd_batch_workspace_size(const nursd_batch* bt, size_t* bytes) {
     return NURSD_OK;
 }
 
-int nursd_batch_autotune(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+static int nursd_batch_autotune_body(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
                          void* stream) {
     if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
     if (!bt->autotune) return fail(NURSD_ERR_ARG, "the batch was created without autotuning");
@@ -2614,7 +2661,7 @@ int nursd_batch_autotune(nursd_batch* bt, const float* const* hist, float* const
     return batch_bind(bt, static_cast<const char*>(ws), s);
 }
 
-int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+static int nursd_batch_forward_body(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
                         void* stream) {
     if (!bt) return fail(NURSD_ERR_ARG, "NULL batch");
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -2640,7 +2687,7 @@ int nursd_batch_info(const nursd_batch* bt, int32_t* budget, int32_t* launches, 
     return NURSD_OK;
 }
 
-int nursd_batch_tuning(const nursd_batch* bt, char* buf, size_t len) {
+static int nursd_batch_tuning_body(const nursd_batch* bt, char* buf, size_t len) {
     if (!bt || !buf || len == 0) return fail(NURSD_ERR_ARG, "NULL argument");
     std::string t;
     for (size_t i = 0; i < bt->tuned.size(); ++i) t += (i ? "; " : "") + bt->tuned[i];
@@ -2678,5 +2725,35 @@ int nursd_profile_end(nursd_plan* p, double* ms, int32_t* calls) {
 }
 
 const char* nursd_last_error(void) { return g_err.c_str(); }
+
+
+// Entry points whose bodies use host containers: no C++ exception crosses
+// the C ABI.
+int nursd_plan_create(const nursd_wavelet* wl, const nursd_geometry* geo, const nursd_options* opt,
+                      const float* relay_xy_dev, void* stream, nursd_plan** out) {
+    NURSD_GUARD(nursd_plan_create_body(wl, geo, opt, relay_xy_dev, stream, out));
+}
+
+int nursd_plan_set_points(nursd_plan* p, const float* relay_xy_dev, void* stream) {
+    NURSD_GUARD(nursd_plan_set_points_body(p, relay_xy_dev, stream));
+}
+
+int nursd_batch_create(nursd_plan* const* plans, int32_t n, int32_t autotune, void* stream, nursd_batch** out) {
+    NURSD_GUARD(nursd_batch_create_body(plans, n, autotune, stream, out));
+}
+
+int nursd_batch_autotune(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+                         void* stream) {
+    NURSD_GUARD(nursd_batch_autotune_body(bt, hist, I, ws, ws_bytes, stream));
+}
+
+int nursd_batch_forward(nursd_batch* bt, const float* const* hist, float* const* I, void* ws, size_t ws_bytes,
+                        void* stream) {
+    NURSD_GUARD(nursd_batch_forward_body(bt, hist, I, ws, ws_bytes, stream));
+}
+
+int nursd_batch_tuning(const nursd_batch* bt, char* buf, size_t len) {
+    NURSD_GUARD(nursd_batch_tuning_body(bt, buf, len));
+}
 
 }  // extern "C"

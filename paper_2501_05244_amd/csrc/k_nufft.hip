@@ -190,17 +190,42 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
     return hipGetLastError();
 }
 
+template <int MF, int BR, int NF>
+__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_var(SpreadArgs a) {
+    spread_xfft_body<MF, BR, NF>(a, blockIdx.x, blockIdx.y);
+}
+
+// A spreading tile (BR rows of NF frequencies, row stride MF + 8) fits LDS
+// and the in-LDS transform keeps at least one wavefront per line.
+constexpr bool spread_fits(int MF, int BR, int NF) {
+    return BR * NF <= 16 && (size_t)BR * NF * (MF + 8) * sizeof(float2) <= 160 * 1024 && MF / BR >= 2;
+}
+
+template <int MF, int BR, int NF>
+static hipError_t spread_plain(const SpreadArgs& a, hipStream_t s) {
+    if constexpr (spread_fits(MF, BR, NF)) {
+        const size_t sh = (size_t)NF * BR * spread_row_stride<MF>() * sizeof(float2);
+        void (*k)(SpreadArgs) = nullptr;
+        if constexpr (BR == spread_band_rows(MF) && NF == spread_freqs(MF)) k = k_spread_xfft<MF>;
+        else k = k_spread_xfft_var<MF, BR, NF>;
+        hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(MF / BR, (a.nb + NF - 1) / NF), dim3(kSpreadThreads), sh, s, a);
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
 template <int MF>
 static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
-    constexpr int kBandRows = spread_band_rows(MF);
-    constexpr int NF = spread_freqs(MF);
-    size_t sh = (size_t)NF * kBandRows * spread_row_stride<MF>() * sizeof(float2);
-    hipError_t e = hipFuncSetAttribute((const void*)k_spread_xfft<MF>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_spread_xfft<MF>, dim3(MF / kBandRows, (a.nb + NF - 1) / NF), dim3(kSpreadThreads), sh, s,
-                       a);
-    return hipGetLastError();
+    switch (a.var) {
+        case 0: return spread_plain<MF, spread_band_rows(MF), spread_freqs(MF)>(a, s);
+        case spread_var(2, 8): return spread_plain<MF, 2, 8>(a, s);
+        case spread_var(4, 4): return spread_plain<MF, 4, 4>(a, s);
+        case spread_var(1, 16): return spread_plain<MF, 1, 16>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s) {
@@ -236,12 +261,6 @@ hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s) {
     }
 }
 
-// A spreading tile (BR rows of NF frequencies, row stride MF + 8) fits LDS
-// and the in-LDS transform keeps at least one wavefront per line.
-constexpr bool spread_fits(int MF, int BR, int NF) {
-    return BR * NF <= 16 && (size_t)BR * NF * (MF + 8) * sizeof(float2) <= 160 * 1024 && MF / BR >= 1;
-}
-
 template <int MF, int BR, int NF>
 static hipError_t spread_grouped(const Group<SpreadArgs>& g, hipStream_t s) {
     if constexpr (spread_fits(MF, BR, NF)) {
@@ -262,6 +281,8 @@ static hipError_t spread_grouped_mf(int var, const Group<SpreadArgs>& g, hipStre
         case spread_var(8, 1): return spread_grouped<MF, 8, 1>(g, s);
         case spread_var(8, 2): return spread_grouped<MF, 8, 2>(g, s);
         case spread_var(16, 1): return spread_grouped<MF, 16, 1>(g, s);
+        case spread_var(2, 8): return spread_grouped<MF, 2, 8>(g, s);
+        case spread_var(1, 16): return spread_grouped<MF, 1, 16>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -269,10 +290,16 @@ static hipError_t spread_grouped_mf(int var, const Group<SpreadArgs>& g, hipStre
 bool spread_var_ok(int Mf, int var) {
     if (Mf < 128 || Mf > 2048 || (Mf & (Mf - 1))) return false;
     if (var == 0) return true;
-    const int br = var / 10, nf = var % 10;
-    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1)))
+    const int br = var / 100, nf = var % 100;
+    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1) ||
+          (br == 2 && nf == 8) || (br == 1 && nf == 16)))
         return false;
     return spread_fits(Mf, br, nf);
+}
+
+bool spread_var_plain_ok(int Mf, int var) {
+    return var == 0 || ((var == spread_var(2, 8) || var == spread_var(4, 4) || var == spread_var(1, 16)) &&
+                        spread_var_ok(Mf, var) && Mf >= 32 && Mf <= 2048);
 }
 
 hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s) {

@@ -269,11 +269,22 @@ constexpr int p3_waves() { return (M >= 1024 || !HALF) ? 8 : NURSD_P3_WAVES; }
 // The persistent (grouped) launches run 4 or 8 waves per block: with the
 // work-queue loop around the body, 16 waves (128 VGPRs each) spill.
 
+// Row pitch of the last pass's tile (float2): a wave's FFT scratch or its
+// LPW output rows, plus NURSD_P3_PAD.
+#ifndef NURSD_P3_PAD
+#define NURSD_P3_PAD 1
+#endif
+template <int M>
+constexpr int p3_scrp() {
+    using F = WaveFFT<M>;
+    return (F::SCR > F::LPW * M ? F::SCR : F::LPW * M) + NURSD_P3_PAD;
+}
+
 template <int M, bool HALF, int NW = p3_waves<M, HALF>()>
 __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
-    constexpr int SCRP = (F::SCR > LPW * M ? F::SCR : LPW * M) + 1;
+    constexpr int SCRP = p3_scrp<M>();
     constexpr int RB = NW * LPW;
     constexpr int NPRE = M * RB / (NW * 64);     // tile values per thread
     static_assert(M * RB % (NW * 64) == 0, "tile must divide over the block");
@@ -510,7 +521,7 @@ hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
     const bool half = 2 * a.nx * a.q <= a.M;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
-        constexpr int SCRP = (F::SCR > F::LPW * MM ? F::SCR : F::LPW * MM) + 1;
+        constexpr int SCRP = p3_scrp<MM>();
         if (half) {
             constexpr int NW = (p3_waves<MM, true>());
             constexpr int RB = NW * F::LPW;
@@ -537,8 +548,7 @@ static hipError_t p2_grouped(const Group<P2Args>& g, hipStream_t s) {
 }
 template <int M, int W>
 static hipError_t p3_grouped(bool half, const Group<P3Args>& g, hipStream_t s) {
-    using F = WaveFFT<M>;
-    constexpr int SCRP = (F::SCR > F::LPW * M ? F::SCR : F::LPW * M) + 1;
+    constexpr int SCRP = p3_scrp<M>();
     constexpr size_t sh = (size_t)(2 * W * SCRP + M) * sizeof(float2);
     if (half) return launch_grouped(k_propagate_rows_grouped<M, true, W>, g, W * 64, sh, s);
     return launch_grouped(k_propagate_rows_grouped<M, false, W>, g, W * 64, sh, s);

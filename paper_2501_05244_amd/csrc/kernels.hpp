@@ -50,6 +50,7 @@ hipError_t launch_phasor(const PhasorArgs& a, hipStream_t s);
 
 // ---------------------------------------------------------------- steps 2-3
 struct SpreadArgs {
+    int var = 0;                  // spreading tile (spread_var); the lists are binned for its rows
     const float2* P;              // [F][L] (frequency-major)
     const float* wts;             // [L] per-sample weights multiplying P, or NULL
     const SpreadEntry* ent;       // entries sorted by band, then u
@@ -299,15 +300,17 @@ hipError_t launch_adjoint_type2(const AdjArgs& a, hipStream_t s);
 hipError_t launch_phasor_grouped(int T, int F_max, const Group<PhasorArgs>& g, hipStream_t s);
 // Grouped launches of the batched mode.  Each takes a schedule variant of its
 // kernel, which the batch's tuner picks per size class:
-//   spreading: spread_var(BR, NF) = BR * 10 + NF (band rows, frequencies
-//     per workgroup; 0 = the plan default), valid where spread_var_ok;
+//   spreading: spread_var(BR, NF) = BR * 100 + NF (band rows, frequencies
+//     per workgroup; 0 = spread_band_rows / spread_freqs), valid where
+//     spread_var_ok (also the plans' own spreading tile);
 //   fine y: lines per workgroup (2, 4, 8; 64 threads per line);
 //   kernel rows: waves per block (4, 8); column pass: waves per block
 //   (2, 4, 8); last pass: waves per block (4, 8).
-constexpr int spread_var(int br, int nf) { return br * 10 + nf; }
-constexpr int spread_var_rows(int var, int Mf) { return var ? var / 10 : spread_band_rows(Mf); }
-constexpr int spread_var_freqs(int var, int Mf) { return var ? var % 10 : spread_freqs(Mf); }
+constexpr int spread_var(int br, int nf) { return br * 100 + nf; }
+constexpr int spread_var_rows(int var, int Mf) { return var ? var / 100 : spread_band_rows(Mf); }
+constexpr int spread_var_freqs(int var, int Mf) { return var ? var % 100 : spread_freqs(Mf); }
 bool spread_var_ok(int Mf, int var);
+bool spread_var_plain_ok(int Mf, int var);   // variants of the plain (per-plan) launch
 hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s);
 hipError_t launch_fine_y_grouped(int Mf, int lines, const Group<FineYArgs>& g, hipStream_t s);
 hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hipStream_t s);

@@ -18,6 +18,10 @@
 #pragma once
 #include "fft.hpp"
 
+#ifndef NURSD_WFFT_RP
+#define NURSD_WFFT_RP 9
+#endif
+
 namespace nursd {
 
 #define NURSD_WAVE_SYNC()                                   \
@@ -83,7 +87,10 @@ struct WaveFFT {
     static constexpr int LPW = N >= 512 ? 1 : 512 / N;   // lines per wave
     static constexpr int GPL = E >= 8 ? E / 8 : 1;       // 8-point groups per lane
     static constexpr int NV = E * LPW;                   // values per lane (== 8 * GPL)
-    static constexpr int SCR = LPW * E * 72;             // LDS scratch per wave (float2)
+    // Exchange tile of one (line, k1): 8 rows of RP float2 (RP > 8 keeps the
+    // lane strides off multiples of the bank count); BP per tile.
+    static constexpr int RP = NURSD_WFFT_RP, BP = 8 * RP;
+    static constexpr int SCR = LPW * E * BP;             // LDS scratch per wave (float2)
     static_assert(NV == 8 * GPL, "layout");
 
     __device__ static __forceinline__ void decode(int gi, int& q, int& k1, int& x) {
@@ -114,13 +121,13 @@ struct WaveFFT {
 #pragma unroll
         for (int q = 0; q < LPW; ++q)
 #pragma unroll
-            for (int k1 = 0; k1 < E; ++k1) scr[(q * E + k1) * 72 + a * 9 + b] = v[q * E + k1];
+            for (int k1 = 0; k1 < E; ++k1) scr[(q * E + k1) * BP + a * RP + b] = v[q * E + k1];
         NURSD_WAVE_SYNC();
 #pragma unroll
         for (int h = 0; h < GPL; ++h) {
             int q, k1, aa;
             decode(lane + 64 * h, q, k1, aa);
-            const int base = (q * E + k1) * 72 + aa * 9;
+            const int base = (q * E + k1) * BP + aa * RP;
             float2* t = v + h * 8;
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) t[bb] = scr[base + bb];
@@ -133,16 +140,16 @@ struct WaveFFT {
         for (int h = 0; h < GPL; ++h) {
             int q, k1, aa;
             decode(lane + 64 * h, q, k1, aa);
-            const int base = (q * E + k1) * 72 + aa;
+            const int base = (q * E + k1) * BP + aa;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) scr[base + c * 9] = v[h * 8 + c];
+            for (int c = 0; c < 8; ++c) scr[base + c * RP] = v[h * 8 + c];
         }
         NURSD_WAVE_SYNC();
 #pragma unroll
         for (int h = 0; h < GPL; ++h) {
             int q, k1, c;
             decode(lane + 64 * h, q, k1, c);
-            const int base = (q * E + k1) * 72 + c * 9;
+            const int base = (q * E + k1) * BP + c * RP;
             float2* w = v + h * 8;
 #pragma unroll
             for (int aa = 0; aa < 8; ++aa) w[aa] = scr[base + aa];
@@ -161,7 +168,7 @@ struct WaveFFT {
         for (int h = 0; h < GPL; ++h) {
             int q, k1, c;
             decode(lane + 64 * h, q, k1, c);
-            const int base = (q * E + k1) * 72 + c * 9;
+            const int base = (q * E + k1) * BP + c * RP;
 #pragma unroll
             for (int aa = 0; aa < 8; ++aa) scr[base + aa] = v[h * 8 + aa];
         }
@@ -170,10 +177,10 @@ struct WaveFFT {
         for (int h = 0; h < GPL; ++h) {
             int q, k1, aa;
             decode(lane + 64 * h, q, k1, aa);
-            const int base = (q * E + k1) * 72 + aa;
+            const int base = (q * E + k1) * BP + aa;
             float2* u = v + h * 8;
 #pragma unroll
-            for (int c = 0; c < 8; ++c) u[c] = scr[base + c * 9];
+            for (int c = 0; c < 8; ++c) u[c] = scr[base + c * RP];
 #pragma unroll
             for (int c = 1; c < 8; ++c) u[c] = twiddle<INV>(u[c], tw[(E * aa * c) & (N - 1)]);
             dft_reg<8, INV>(u);
@@ -183,7 +190,7 @@ struct WaveFFT {
         for (int h = 0; h < GPL; ++h) {
             int q, k1, aa;
             decode(lane + 64 * h, q, k1, aa);
-            const int base = (q * E + k1) * 72 + aa * 9;
+            const int base = (q * E + k1) * BP + aa * RP;
 #pragma unroll
             for (int bb = 0; bb < 8; ++bb) scr[base + bb] = v[h * 8 + bb];
         }
@@ -193,7 +200,7 @@ struct WaveFFT {
         for (int q = 0; q < LPW; ++q) {
             float2* y = v + q * E;
 #pragma unroll
-            for (int k1 = 0; k1 < E; ++k1) y[k1] = scr[(q * E + k1) * 72 + a * 9 + b];
+            for (int k1 = 0; k1 < E; ++k1) y[k1] = scr[(q * E + k1) * BP + a * RP + b];
 #pragma unroll
             for (int k1 = 1; k1 < E; ++k1) y[k1] = twiddle<INV>(y[k1], tw[(lane * k1) & (N - 1)]);
             dft_reg<E, INV>(y);
