@@ -6,6 +6,7 @@
 #include "kernels.hpp"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -822,7 +823,7 @@ hipError_t launch_zero_counters(int* c, int n, hipStream_t s) {
 }
 }  // namespace nursd
 
-enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL, BK_KTAB };
+enum { BK_PHASOR = 0, BK_SPREAD, BK_FINEY, BK_P1, BK_P2, BK_P3, BK_SERIAL, BK_KTAB, BK_MULTI };
 
 // One configuration of the batched launch sequence.
 struct BatchConfig {
@@ -863,6 +864,9 @@ struct BatchScene {
     std::vector<int> kidx;   // [F][nz] plane of (b, iz) in the class table
     bool shared = false;     // reads the class table (set per configuration)
     size_t kidx_off = 0;     // byte offset of kidx in the table buffer
+    bool multi = false;      // shared and chunk by chunk: column passes shared per kernel line
+    bool zmono = false;      // plane depths map strictly monotonically onto the class depths
+    size_t off_Ym = 0;       // [F][zr][M][ny] column-pass output of one depth round
 };
 
 struct BatchLaunch {
@@ -872,6 +876,8 @@ struct BatchLaunch {
     int scene = -1;                                  // BK_SERIAL: scene propagated with ordinary launches
     size_t items = 0, prefix = 0, gridx = 0, item_of = 0;   // byte offsets in the table buffer
     int n = 0, total = 0, counter = -1;
+    // BK_MULTI: last-pass chunks (scene, first plane, planes) of the round
+    std::vector<std::array<int, 3>> p3;
 };
 
 // Relay lists of a scene binned for another spreading band height.
@@ -891,6 +897,7 @@ struct nursd_batch {
     std::vector<void*> owned;                       // device buffers of those lists
     std::vector<std::string> tuned;                 // what the kernel tuner picked, with times
     bool lists_missing = false;                     // a spreading tile without relay lists was asked for
+    int multi_zr = 16;                              // class depths per round of the shared column passes
     int autotune = 0;
     BatchConfig cfg;                 // configuration in use
     std::vector<BatchConfig> cands;  // configurations the tuner times
@@ -978,9 +985,14 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
         nursd_plan* p = sc.p;
         sc.serial = p->M >= c.serial_min_m;
         sc.shared = c.share && bt->kcls[sc.kcls].on;
-        if (sc.serial) {
+        sc.multi = sc.serial && sc.shared && sc.zmono;
+        if (sc.serial && !sc.multi) {
             if (!sc.shared) serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
             serial_yt = std::max(serial_yt, (size_t)p->FC * p->ZC * p->ny * p->M * c8);
+        }
+        if (sc.multi) {
+            sc.off_Ym = o;
+            o = align_up(o + (size_t)p->F * bt->multi_zr * p->M * p->ny * c8);
         }
         sc.ZC = batch_zc(p, c.rounds);
         sc.rounds = sc.serial ? 0 : (p->nz + sc.ZC - 1) / sc.ZC;
@@ -1121,6 +1133,11 @@ int batch_kernel_classes(nursd_batch* bt) {
             }
         }
         uses[sc.kcls] += (double)p->F * p->nz;
+        sc.zmono = true;
+        for (int iz = 1; iz < p->nz; ++iz) {
+            const int d = sc.kidx[iz] - sc.kidx[iz - 1];
+            if (d == 0 || (iz > 1 && (d > 0) != (sc.kidx[1] > sc.kidx[0]))) sc.zmono = false;
+        }
     }
     std::vector<int> order(bt->kcls.size());
     for (size_t j = 0; j < order.size(); ++j) order[j] = (int)j;
@@ -1376,11 +1393,65 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             if (!i3.empty()) bt->launches.back().half = half ? 1 : 0;
         }
     }
+    // chunk-by-chunk scenes of shared classes: rounds of class depths, each
+    // one column pass per kernel line for all the class's scenes, then the
+    // scenes' last passes with ordinary launches
+    for (size_t k = 0; k < bt->kcls.size(); ++k) {
+        const KernelClass& kc = bt->kcls[k];
+        std::vector<int> mem;
+        for (size_t i = 0; i < bt->sc.size(); ++i)
+            if (bt->sc[i].multi && bt->sc[i].kcls == (int)k) mem.push_back((int)i);
+        if (mem.empty()) continue;
+        const int nzk = (int)kc.z.size(), zr = bt->multi_zr;
+        for (int zi0 = 0; zi0 < nzk; zi0 += zr) {
+            const int zi1 = std::min(nzk, zi0 + zr);
+            std::map<int, std::vector<P2MUser>> users;     // table plane -> users
+            BatchLaunch L;
+            L.kind = BK_MULTI;
+            L.scene = (int)k;
+            for (int i : mem) {
+                const BatchScene& sc = bt->sc[i];
+                const nursd_plan* p = sc.p;
+                int iz0 = -1, iz1 = -1;
+                for (int iz = 0; iz < p->nz; ++iz) {
+                    const int zi = sc.kidx[iz] % nzk;             // b = 0 row of the plane map
+                    if (zi >= zi0 && zi < zi1) {
+                        if (iz0 < 0) iz0 = iz;
+                        iz1 = iz + 1;
+                    }
+                }
+                if (iz0 < 0) continue;
+                const int nzr = iz1 - iz0;
+                for (int b = 0; b < p->F; ++b)
+                    for (int iz = iz0; iz < iz1; ++iz) {
+                        P2MUser u;
+                        u.U = reinterpret_cast<const float2*>(ws + sc.off_U) + (size_t)b * p->M * p->M;
+                        u.Yt = reinterpret_cast<float2*>(ws + sc.off_Ym) + ((size_t)b * nzr + (iz - iz0)) * p->M * p->ny;
+                        u.ny = p->ny;
+                        u.q = p->q;
+                        users[sc.kidx[(size_t)b * p->nz + iz]].push_back(u);
+                    }
+                L.p3.push_back({i, iz0, nzr});
+            }
+            std::vector<int> kp, ptr(1, 0);
+            std::vector<P2MUser> flat;
+            for (auto& kv : users) {
+                kp.push_back(kv.first);
+                flat.insert(flat.end(), kv.second.begin(), kv.second.end());
+                ptr.push_back((int)flat.size());
+            }
+            L.n = (int)kp.size();
+            L.items = tab_push(bt->tab, kp);
+            L.prefix = tab_push(bt->tab, ptr);
+            L.gridx = tab_push(bt->tab, flat);
+            bt->launches.push_back(L);
+        }
+    }
     // large-transform scenes: ordinary chunked launches, largest first
     {
         std::vector<int> order;
         for (size_t i = 0; i < bt->sc.size(); ++i)
-            if (bt->sc[i].serial) order.push_back((int)i);
+            if (bt->sc[i].serial && !bt->sc[i].multi) order.push_back((int)i);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
             const nursd_plan *pa = bt->sc[a].p, *pb = bt->sc[b].p;
             return (double)pa->F * pa->nz * pa->M * pa->M > (double)pb->F * pb->nz * pb->M * pb->M;
@@ -1451,12 +1522,42 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s, LaunchTimer* tm = nullptr) {
     // One work-queue counter per grouped launch; scenes propagated with
     // ordinary launches have none.
     for (const BatchLaunch& L : bt->launches)
-        if (L.kind != BK_SERIAL && L.kind != BK_KTAB &&
+        if (L.kind != BK_SERIAL && L.kind != BK_KTAB && L.kind != BK_MULTI &&
             (L.counter < 0 || L.counter >= bt->n_counters || bt->n_counters > bt->counters_cap))
             return fail(NURSD_ERR_ARG, "batch launch table refers to a counter outside the counter buffer");
     if (bt->n_counters > 0) HIP_TRY(launch_zero_counters(bt->d_counters, bt->n_counters, s));
     char* ws = const_cast<char*>(bt->ws);
     for (const BatchLaunch& L : bt->launches) {
+        if (L.kind == BK_MULTI) {
+            const KernelClass& kc = bt->kcls[L.scene];
+            P2MArgs ma{};
+            ma.Bt = reinterpret_cast<const float2*>(ws + kc.off);
+            ma.kp = reinterpret_cast<const int*>(bt->d_tab + L.items);
+            ma.user_ptr = reinterpret_cast<const int*>(bt->d_tab + L.prefix);
+            ma.users = reinterpret_cast<const P2MUser*>(bt->d_tab + L.gridx);
+            ma.M = kc.M;
+            ma.BS = kc.BS;
+            ma.tw = kc.tw;
+            for (int i0 = 0; i0 < L.n; i0 += 65535) {
+                P2MArgs part = ma;
+                part.kp += i0;
+                part.user_ptr += i0;
+                HIP_TRY(launch_propagate_cols_multi(part, std::min(65535, L.n - i0), s));
+            }
+            for (const auto& t : L.p3) {
+                const BatchScene& sc = bt->sc[t[0]];
+                nursd_plan* p = sc.p;
+                float2* Ym = reinterpret_cast<float2*>(ws + sc.off_Ym);
+                float2* V = reinterpret_cast<float2*>(ws + sc.off_V);
+                for (int b0 = 0; b0 < p->F; b0 += p->FC) {
+                    const int nb = std::min(p->FC, p->F - b0);
+                    const ChunkGeom g = chunk_geom(p, b0, nb, t[1], t[2]);
+                    HIP_TRY(launch_propagate_rows(
+                        rows_args(p, g, Ym + (size_t)b0 * t[2] * p->M * p->ny, V, bt->I[t[0]], b0, nb), s));
+                }
+            }
+            continue;
+        }
         if (L.kind == BK_KTAB) {
             const int nf = (int)bt->kcls[L.scene].f.size(), nzk = (int)bt->kcls[L.scene].z.size();
             const int fstep = std::max(1, kMaxGridY / std::max(1, nzk));

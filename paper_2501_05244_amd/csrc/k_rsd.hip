@@ -166,42 +166,17 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
 #endif
 constexpr int kP2Waves = NURSD_P2_WAVES;
 
-template <int M, int NW = kP2Waves>
-__device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
+// Spectrum product and inverse y transform of a wave's kx lines for one
+// target: for s = kx and s = M - kx, Yp[s][iy] = IDFT_y(U[s] * g)[window row
+// iy] with g the permuted kernel spectrum line(s).  ny, q: the target's
+// window rows and upsampling.
+template <int M>
+__device__ __forceinline__ void cols_apply(const float2* g, const float2* __restrict__ Ub, float2* Yp, int ny, int qf,
+                                           int kx0, float2* scr, const float2* tws, int lane) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
-    extern __shared__ float2 sm[];      // [NW][SCR], then twiddles [M]
-    float2* tws = sm + NW * F::SCR;
-    const int p = by;
-    int b, iz;
-    plane_of(a.g, p, b, iz);
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int kx0 = (bx * NW + wave) * LPW;
-    float2* scr = sm + wave * F::SCR;
-    const int kp = a.kidx ? a.kidx[b * a.kz + iz] : p;
-    const float2* Bt = a.Bt + (size_t)kp * (H + 1) * a.BS;
-    float2 v[F::NV], g[F::NV];
-    // The kernel lines are requested before the twiddle table is staged, so
-    // that both global reads are in flight across the block barrier.
-#pragma unroll
-    for (int q = 0; q < LPW; ++q) {
-        const int kx = kx0 + q;
-#pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int n = lane + 64 * e;
-            const int dd = n <= H ? n : M - n;
-            v[q * E + e] = kx <= H ? Bt[(size_t)kx * a.BS + dd] : make_float2(0.f, 0.f);
-        }
-    }
-    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
-    __syncthreads();
-    if (kx0 > H) return;                // wave-uniform; no block barriers below
-    const float2* Ub = a.U + (size_t)b * M * M;
-    F::template nat_to_perm<false>(v, scr, tws, lane);
-#pragma unroll
-    for (int i = 0; i < F::NV; ++i) g[i] = v[i];
-    float2* Yp = a.Yt + (size_t)p * M * a.ny;
-    const int half = a.ny / 2;
+    const int half = ny / 2;
+    float2 v[F::NV];
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
 #pragma unroll
@@ -220,30 +195,98 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
             const int kx = kx0 + q;
             const int s = side ? ((M - kx) & (M - 1)) : kx;
             if (kx > H || (side && s == kx)) continue;
-            if (a.q == 1) {
+            if (qf == 1) {
                 // One row base per line; slot e sits at offset 64 e, or 64 e - M
                 // past the centre, which is a constant when M/2 is a multiple of
                 // 64, so the stores take immediate offsets.
-                float2* row = Yp + (size_t)s * a.ny + half + lane;
+                float2* row = Yp + (size_t)s * ny + half + lane;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const bool lower = H % 64 == 0 ? 64 * e < H : lane + 64 * e < H;
                     const int off = lower ? 64 * e : 64 * e - M;
                     const int iy = lane + off + half;
-                    if (iy >= 0 && iy < a.ny) row[off] = v[q * E + e];
+                    if (iy >= 0 && iy < ny) row[off] = v[q * E + e];
                 }
             } else {
                 // upsampled frame: window row iy is grid row iy q - (ny q)/2
-                const int hq = (a.ny * a.q) / 2;
-                float2* row = Yp + (size_t)s * a.ny;
+                const int hq = (ny * qf) / 2;
+                float2* row = Yp + (size_t)s * ny;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const int n = lane + 64 * e;
                     const int t = (n < H ? n : n - M) + hq;
-                    if (t >= 0 && t % a.q == 0 && t / a.q < a.ny) row[t / a.q] = v[q * E + e];
+                    if (t >= 0 && t % qf == 0 && t / qf < ny) row[t / qf] = v[q * E + e];
                 }
             }
         }
+    }
+}
+
+// The kernel quadrant line(s) of the wave's kx lines (even extension along
+// y), requested before the block stages the twiddle table so that both
+// global reads are in flight across the block barrier.
+template <int M>
+__device__ __forceinline__ void load_kernel_lines(float2* v, const float2* __restrict__ Bt, int BS, int kx0,
+                                                  int lane) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW;
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int kx = kx0 + q;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int n = lane + 64 * e;
+            const int dd = n <= H ? n : M - n;
+            v[q * E + e] = kx <= H ? Bt[(size_t)kx * BS + dd] : make_float2(0.f, 0.f);
+        }
+    }
+}
+
+template <int M, int NW = kP2Waves>
+__device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2;
+    extern __shared__ float2 sm[];      // [NW][SCR], then twiddles [M]
+    float2* tws = sm + NW * F::SCR;
+    const int p = by;
+    int b, iz;
+    plane_of(a.g, p, b, iz);
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kx0 = (bx * NW + wave) * F::LPW;
+    float2* scr = sm + wave * F::SCR;
+    const int kp = a.kidx ? a.kidx[b * a.kz + iz] : p;
+    float2 g[F::NV];
+    load_kernel_lines<M>(g, a.Bt + (size_t)kp * (H + 1) * a.BS, a.BS, kx0, lane);
+    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
+    __syncthreads();
+    if (kx0 > H) return;                // wave-uniform; no block barriers below
+    F::template nat_to_perm<false>(g, scr, tws, lane);
+    cols_apply<M>(g, a.U + (size_t)b * M * M, a.Yt + (size_t)p * M * a.ny, a.ny, a.q, kx0, scr, tws, lane);
+}
+
+// Batched mode, one kernel spectrum line for many scenes: block (bx, item)
+// transforms the kernel lines of table plane kp[item] once and applies them
+// to every user of that plane (a scene's spectrum at the user's frequency
+// and its output plane).
+template <int M, int NW = kP2Waves>
+__device__ __forceinline__ void propagate_cols_multi_body(const P2MArgs& a, int bx, int item) {
+    using F = WaveFFT<M>;
+    constexpr int H = M / 2;
+    extern __shared__ float2 sm[];      // [NW][SCR], then twiddles [M]
+    float2* tws = sm + NW * F::SCR;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kx0 = (bx * NW + wave) * F::LPW;
+    float2* scr = sm + wave * F::SCR;
+    float2 g[F::NV];
+    load_kernel_lines<M>(g, a.Bt + (size_t)a.kp[item] * (H + 1) * a.BS, a.BS, kx0, lane);
+    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
+    __syncthreads();
+    if (kx0 > H) return;                // wave-uniform; no block barriers below
+    F::template nat_to_perm<false>(g, scr, tws, lane);
+    const int u1 = a.user_ptr[item + 1];
+    for (int u = a.user_ptr[item]; u < u1; ++u) {
+        const P2MUser us = a.users[u];
+        cols_apply<M>(g, us.U, us.Yt, us.ny, us.q, kx0, scr, tws, lane);
     }
 }
 
@@ -439,6 +482,10 @@ template <int M, int NW>
 __global__ __launch_bounds__(NW * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
     persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M, NW>(a, bx, by); });
 }
+template <int M>
+__global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_multi(P2MArgs a) {
+    propagate_cols_multi_body<M>(a, blockIdx.x, blockIdx.y);
+}
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
     const int v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
@@ -512,6 +559,18 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
         dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
         return launch_rsd(k_propagate_cols<MM>, grid, kP2Waves * 64, (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s,
                           a);
+    })
+}
+
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int items, hipStream_t s) {
+    if (items <= 0) return hipSuccess;
+    if (items > 65535) return hipErrorInvalidValue;
+    NURSD_SWITCH_M(a.M, {
+        using F = WaveFFT<MM>;
+        constexpr int LB = kP2Waves * F::LPW;
+        dim3 grid((MM / 2 + 1 + LB - 1) / LB, items);
+        return launch_rsd(k_propagate_cols_multi<MM>, grid, kP2Waves * 64, (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2),
+                          s, a);
     })
 }
 

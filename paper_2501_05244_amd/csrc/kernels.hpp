@@ -114,6 +114,26 @@ struct P2Args {
 };
 hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s);
 
+// Batched mode: the column pass of one kernel table plane for several
+// scenes.  Item i (grid y) transforms the kernel lines of table plane kp[i]
+// once and, for each user u in [user_ptr[i], user_ptr[i + 1]), multiplies
+// them by the user's spectrum rows U[+-kx] and writes the inverse transform
+// of the window rows to the user's output plane Yt ([M][ny], as P2Args).
+struct P2MUser {
+    const float2* U;    // [M][M] spectrum of the user's frequency
+    float2* Yt;         // [M][ny] output plane
+    int ny, q;
+};
+struct P2MArgs {
+    const float2* Bt;       // kernel table [planes][M/2+1][BS]
+    const int* kp;          // [items] table plane of each item
+    const int* user_ptr;    // [items + 1]
+    const P2MUser* users;
+    int M, BS;
+    const float2* tw;
+};
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int items, hipStream_t s);
+
 struct P3Args {
     ChunkGeom g;
     const float2* Yt;   // [planes][M][ny]: kx line s, then window row iy

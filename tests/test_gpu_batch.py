@@ -82,20 +82,23 @@ def test_batch_matches_oracle(device):
 
 
 def shared_scenes():
-    """Scenes that share kernel classes: four at transform size 128 and two at
-    512 (run chunk by chunk), each group on one pitch and one depth grid with
+    """Scenes that share kernel classes: four at transform size 128 and three
+    at 512 (run chunk by chunk), each group on one pitch and one depth grid with
     overlapping frequency bands (wavelengths 5-6 cm), so every (frequency,
     depth) kernel of a class serves several scenes."""
     out = []
     dx = 0.0078125
     for s, (n, L, F, Z, lam) in enumerate([(64, 900, 6, 4, 0.05), (64, 1500, 8, 4, 0.055), (64, 700, 5, 4, 0.06),
-                                           (64, 2000, 7, 4, 0.05), (160, 3000, 3, 3, 0.055), (160, 2500, 4, 3, 0.055)]):
+                                           (64, 2000, 7, 4, 0.05), (160, 3000, 3, 3, 0.055), (160, 2500, 4, 3, 0.055),
+                                           (160, 1800, 3, 3, 0.055)]):
         half = n * dx / 2
         relay = scenes.relay_uniform(L, half * 0.98, seed=300 + s)
         scat, alb = scenes.scatter_points(3, 0.8 * half, 0.3, 0.3 + n * dx, seed=400 + s)
         wl = scenes.Wavelet(lambda_c=lam, n_time=2048, dt=4e-12, t0=0.0, n_freq=F)
-        g = scenes.Grid(x0=-half + dx / 2, y0=-half + dx / 2, dx=dx, dy=dx, nx=n, ny=n,
-                        z=scenes.cell_centres(0.3, 0.3 + 32 * dx, Z))
+        z = scenes.cell_centres(0.3, 0.3 + 32 * dx, Z)
+        if s == 6:
+            z = z[::-1].copy()          # planes listed far to near
+        g = scenes.Grid(x0=-half + dx / 2, y0=-half + dx / 2, dx=dx, dy=dx, nx=n, ny=n, z=z)
         w = scenes.Workload(f"k{s}", relay, np.zeros(3), wl, g, scatterers=scat, albedo=alb)
         w.hist = scenes.render_transients(relay, scat, alb, w.xp, 2048, 4e-12, 0.0)
         out.append(w)
@@ -103,9 +106,11 @@ def shared_scenes():
 
 
 def test_batch_shared_kernel_tables(device):
-    """Kernel spectra generated once per class and read by every member scene:
-    batched equals the plain loop (<= 1e-5) and two scenes (one per class)
-    match the FP64 oracle (<= 1e-4)."""
+    """Kernel spectra generated once per class and read by every member scene
+    (the chunk-by-chunk class also shares each kernel line's column pass
+    among its scenes, one of them with its planes listed far to near):
+    batched equals the plain loop (<= 1e-5) and three scenes match the FP64
+    oracle (<= 1e-4)."""
     print("case: batch with shared kernel tables", flush=True)
     ws = shared_scenes()
     plans, hists, plain, batch, outs = run_both(ws, device, False)
@@ -115,7 +120,7 @@ def test_batch_shared_kernel_tables(device):
     assert sorted({p.M for p in plans}) == [128, 512]
     for a, b in zip(outs, plain):
         assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-5
-    for i in (1, 4):
+    for i in (1, 4, 6):
         w = ws[i]
         P, f = o.phasors_from_workload(w)
         ref = o.nursd_grid(P, w.relay_xy.astype(np.float64), f, o.frame_for_workload(w), w.grid, w.xp,
