@@ -1440,10 +1440,25 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                 flat.insert(flat.end(), kv.second.begin(), kv.second.end());
                 ptr.push_back((int)flat.size());
             }
+            // work blocks: for each frequency's run of items (table planes
+            // are frequency-major), eight kx blocks at a time, interleaved
+            // so that one kx block's depths fall on one XCD
+            const int kxb = grid_x_propagate_cols_multi(kc.M);
+            std::vector<int2> blk;
+            for (size_t i0 = 0; i0 < kp.size();) {
+                size_t i1 = i0;
+                while (i1 < kp.size() && kp[i1] / nzk == kp[i0] / nzk) ++i1;
+                for (int c0 = 0; c0 < kxb; c0 += kXcds)
+                    for (size_t i = i0; i < i1; ++i)
+                        for (int x = c0; x < std::min(kxb, c0 + kXcds); ++x) blk.push_back(make_int2((int)i, x));
+                i0 = i1;
+            }
             L.n = (int)kp.size();
+            L.total = (int)blk.size();
             L.items = tab_push(bt->tab, kp);
             L.prefix = tab_push(bt->tab, ptr);
             L.gridx = tab_push(bt->tab, flat);
+            L.item_of = tab_push(bt->tab, blk);
             bt->launches.push_back(L);
         }
     }
@@ -1535,15 +1550,11 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s, LaunchTimer* tm = nullptr) {
             ma.kp = reinterpret_cast<const int*>(bt->d_tab + L.items);
             ma.user_ptr = reinterpret_cast<const int*>(bt->d_tab + L.prefix);
             ma.users = reinterpret_cast<const P2MUser*>(bt->d_tab + L.gridx);
+            ma.blk = reinterpret_cast<const int2*>(bt->d_tab + L.item_of);
             ma.M = kc.M;
             ma.BS = kc.BS;
             ma.tw = kc.tw;
-            for (int i0 = 0; i0 < L.n; i0 += 65535) {
-                P2MArgs part = ma;
-                part.kp += i0;
-                part.user_ptr += i0;
-                HIP_TRY(launch_propagate_cols_multi(part, std::min(65535, L.n - i0), s));
-            }
+            HIP_TRY(launch_propagate_cols_multi(ma, L.total, s));
             for (const auto& t : L.p3) {
                 const BatchScene& sc = bt->sc[t[0]];
                 nursd_plan* p = sc.p;

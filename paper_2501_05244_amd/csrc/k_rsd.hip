@@ -484,7 +484,8 @@ __global__ __launch_bounds__(NW * 64) void k_propagate_cols_grouped(Group<P2Args
 }
 template <int M>
 __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_multi(P2MArgs a) {
-    propagate_cols_multi_body<M>(a, blockIdx.x, blockIdx.y);
+    const int2 w = a.blk[blockIdx.x];
+    propagate_cols_multi_body<M>(a, w.y, w.x);
 }
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
@@ -562,17 +563,15 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
     })
 }
 
-hipError_t launch_propagate_cols_multi(const P2MArgs& a, int items, hipStream_t s) {
-    if (items <= 0) return hipSuccess;
-    if (items > 65535) return hipErrorInvalidValue;
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, hipStream_t s) {
+    if (nblk <= 0) return hipSuccess;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
-        constexpr int LB = kP2Waves * F::LPW;
-        dim3 grid((MM / 2 + 1 + LB - 1) / LB, items);
-        return launch_rsd(k_propagate_cols_multi<MM>, grid, kP2Waves * 64, (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2),
-                          s, a);
+        return launch_rsd(k_propagate_cols_multi<MM>, dim3(nblk), kP2Waves * 64,
+                          (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s, a);
     })
 }
+int grid_x_propagate_cols_multi(int M) { return grid_x_propagate_cols(M, kP2Waves); }
 
 hipError_t launch_propagate_rows(const P3Args& a, hipStream_t s) {
     if (!a.g.uni) return hipErrorInvalidValue;     // phases advance by a fixed step

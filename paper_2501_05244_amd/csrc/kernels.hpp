@@ -129,10 +129,17 @@ struct P2MArgs {
     const int* kp;          // [items] table plane of each item
     const int* user_ptr;    // [items + 1]
     const P2MUser* users;
+    // Work blocks (item, kx block) by block index.  The dispatcher deals
+    // block indices to the 8 XCDs in turn, so the host interleaves eight kx
+    // blocks of one frequency at a time: each XCD then walks the depths of
+    // one (frequency, kx block) back to back and reads the users' spectrum
+    // rows from its L2, while the XCDs stay balanced block by block.
+    const int2* blk;
     int M, BS;
     const float2* tw;
 };
-hipError_t launch_propagate_cols_multi(const P2MArgs& a, int items, hipStream_t s);
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, hipStream_t s);
+int grid_x_propagate_cols_multi(int M);
 
 struct P3Args {
     ChunkGeom g;
