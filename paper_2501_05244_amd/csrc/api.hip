@@ -985,7 +985,7 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
         nursd_plan* p = sc.p;
         sc.serial = p->M >= c.serial_min_m;
         sc.shared = c.share && bt->kcls[sc.kcls].on;
-        sc.multi = sc.serial && sc.shared && sc.zmono;
+        sc.multi = sc.shared && sc.zmono;
         if (sc.serial && !sc.multi) {
             if (!sc.shared) serial_bt = std::max(serial_bt, (size_t)p->FC * p->ZC * (p->M / 2 + 1) * p->BS * c8);
             serial_yt = std::max(serial_yt, (size_t)p->FC * p->ZC * p->ny * p->M * c8);
@@ -995,14 +995,14 @@ size_t batch_layout(nursd_batch* bt, const BatchConfig& c) {
             o = align_up(o + (size_t)p->F * bt->multi_zr * p->M * p->ny * c8);
         }
         sc.ZC = batch_zc(p, c.rounds);
-        sc.rounds = sc.serial ? 0 : (p->nz + sc.ZC - 1) / sc.ZC;
+        sc.rounds = (sc.serial || sc.multi) ? 0 : (p->nz + sc.ZC - 1) / sc.ZC;
         sc.off_P = o;
         o = align_up(o + (size_t)p->F * p->L * c8);
         sc.off_T1 = o;
         o = align_up(o + (size_t)p->F * p->M * p->Mf * c8);
         sc.off_U = o;
         o = align_up(o + (size_t)p->F * p->M * p->M * c8);
-        if (!sc.serial) {
+        if (!sc.serial && !sc.multi) {
             sc.off_Bt = o;
             if (!sc.shared) o = align_up(o + (size_t)p->F * sc.ZC * (p->M / 2 + 1) * p->BS * c8);
             sc.off_Yt = o;
@@ -1433,6 +1433,40 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                     }
                 L.p3.push_back({i, iz0, nzr});
             }
+            // last passes of the round: chunk-by-chunk scenes as ordinary
+            // launches (listed in L.p3), the others in one grouped launch
+            std::vector<P3Args> g3;
+            std::vector<int> g3x, g3y;
+            std::vector<double> w3;
+            bool half = true;
+            std::vector<std::array<int, 3>> ord;
+            for (const auto& t : L.p3) {
+                const BatchScene& sc = bt->sc[t[0]];
+                const nursd_plan* p = sc.p;
+                if (sc.serial) {
+                    ord.push_back(t);
+                    continue;
+                }
+                half = half && 2 * p->nx * p->q <= p->M;
+            }
+            const int nw3 = batch_choice(bt, BK_P3, kc.M);
+            for (const auto& t : L.p3) {
+                const BatchScene& sc = bt->sc[t[0]];
+                nursd_plan* p = sc.p;
+                if (sc.serial) continue;
+                // one item per scene and round over all its frequencies: the
+                // items of a grouped launch run concurrently, so frequency
+                // chunks of the same planes must not be separate items
+                float2* Ym = reinterpret_cast<float2*>(ws + sc.off_Ym);
+                const ChunkGeom g = chunk_geom(p, 0, p->F, t[1], t[2]);
+                g3.push_back(rows_args(p, g, Ym, reinterpret_cast<float2*>(ws + sc.off_V),
+                                       bt->I.empty() ? nullptr : bt->I[t[0]], 0, p->F));
+                const int rb = rows_per_block_propagate(p->M, nw3);
+                g3x.push_back((p->ny + rb - 1) / rb);
+                g3y.push_back(t[2]);
+                w3.push_back((double)p->F);
+            }
+            L.p3 = ord;
             std::vector<int> kp, ptr(1, 0);
             std::vector<P2MUser> flat;
             for (auto& kv : users) {
@@ -1460,6 +1494,10 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             L.gridx = tab_push(bt->tab, flat);
             L.item_of = tab_push(bt->tab, blk);
             bt->launches.push_back(L);
+            if (!g3.empty()) {
+                add(BK_P3, kc.M, 0, nw3, g3, g3x, g3y, w3);
+                bt->launches.back().half = half ? 1 : 0;
+            }
         }
     }
     // large-transform scenes: ordinary chunked launches, largest first
@@ -1727,19 +1765,14 @@ int batch_tune_kernels(nursd_batch* bt, const char* ws, hipStream_t s) {
     bt->tuned.clear();
     int rc = batch_upload(bt, ws, s);
     if (rc) return rc;
+    // the grouped launch classes of the chosen configuration, with the
+    // log2 of their virtual blocks as the work bucket
     std::vector<std::tuple<int, int, int>> keys;      // kind, size, work bucket
     {
         std::map<std::pair<int, int>, double> work;
-        for (size_t i = 0; i < bt->sc.size(); ++i) {
-            const nursd_plan* p = bt->sc[i].p;
-            work[{BK_SPREAD, p->Mf}] += (double)p->F * p->L;
-            work[{BK_FINEY, p->Mf}] += (double)p->F * p->M;
-            if (!bt->sc[i].serial) {
-                if (!bt->sc[i].shared) work[{BK_P1, p->M}] += (double)p->F * p->nz;
-                work[{BK_P2, p->M}] += (double)p->F * p->nz;
-                work[{BK_P3, p->M}] += (double)p->F * p->nz;
-            }
-        }
+        for (const BatchLaunch& L : bt->launches)
+            if (L.kind == BK_SPREAD || L.kind == BK_FINEY || L.kind == BK_P1 || L.kind == BK_P2 || L.kind == BK_P3)
+                work[{L.kind, L.size}] += (double)L.total;
         for (const auto& kv : work)
             keys.emplace_back(kv.first.first, kv.first.second, (int)std::floor(std::log2(std::max(1.0, kv.second))));
     }

@@ -82,14 +82,16 @@ def test_batch_matches_oracle(device):
 
 
 def shared_scenes():
-    """Scenes that share kernel classes: four at transform size 128 and three
-    at 512 (run chunk by chunk), each group on one pitch and one depth grid with
-    overlapping frequency bands (wavelengths 5-6 cm), so every (frequency,
-    depth) kernel of a class serves several scenes."""
+    """Scenes that share kernel classes: four at transform size 128 (20
+    planes: two rounds of 16 depths; one scene has 12 frequencies, more than
+    one propagation chunk) and three at 512 (run chunk by chunk), each group
+    on one pitch and one depth grid with overlapping frequency bands
+    (wavelengths 5-6 cm), so every (frequency, depth) kernel of a class
+    serves several scenes."""
     out = []
     dx = 0.0078125
-    for s, (n, L, F, Z, lam) in enumerate([(64, 900, 6, 4, 0.05), (64, 1500, 8, 4, 0.055), (64, 700, 5, 4, 0.06),
-                                           (64, 2000, 7, 4, 0.05), (160, 3000, 3, 3, 0.055), (160, 2500, 4, 3, 0.055),
+    for s, (n, L, F, Z, lam) in enumerate([(64, 900, 6, 20, 0.05), (64, 1500, 12, 20, 0.055), (64, 700, 5, 20, 0.06),
+                                           (64, 2000, 7, 20, 0.05), (160, 3000, 3, 3, 0.055), (160, 2500, 4, 3, 0.055),
                                            (160, 1800, 3, 3, 0.055)]):
         half = n * dx / 2
         relay = scenes.relay_uniform(L, half * 0.98, seed=300 + s)
