@@ -52,8 +52,8 @@ constexpr int kSupportedM[] = {64, 128, 256, 512, 1024};
 // Spreading tile of the plans' own launches (spread_var(band rows,
 // frequencies per workgroup)), for 3D (depth-mode) plans and others: 4 x 4
 // measured 6 % faster than 8 x 2 at the SPAD workload and 5 % faster in the
-// 3D stage 1 (2 x 8 and 1 x 16 slower: the walk is bound by the per-entry
-// read-modify-write steps, not by the kernel weights they share).  Sizes
+// 3D stage 1 (2 x 8 and 1 x 16 were slower: the walk is not bound by the
+// kernel weights the frequencies share).  Sizes
 // whose tile does not fit LDS keep 8 x 2 (or 8 x 1).
 #ifndef NURSD_PLAN_SPREAD_VAR
 #define NURSD_PLAN_SPREAD_VAR 404
@@ -1044,8 +1044,7 @@ std::vector<int> choice_candidates(const nursd_batch* bt, int kind, int size) {
     std::vector<int> v;
     switch (kind) {
         case BK_SPREAD:
-            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1),
-                          spread_var(2, 8), spread_var(1, 16)}) {
+            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1)}) {
                 if (!spread_var_ok(size, c)) continue;
                 const int br = spread_var_rows(c, size);
                 bool have = true;
@@ -2654,7 +2653,7 @@ static int nursd_batch_create_body(nursd_plan* const* plans, int32_t n, int32_t 
         for (int i = 0; i < n; ++i) {
             const nursd_plan* p = plans[i];
             const int class_br = spread_var_rows(batch_choice(bt, BK_SPREAD, p->Mf), p->Mf);
-            for (int br : {1, 2, 4, 8, 16}) {
+            for (int br : {4, 8, 16}) {
                 if (br == spread_var_rows(p->spread_var, p->Mf) || p->Mf / br < 2) continue;
                 if (!bt->autotune && br != class_br) continue;
                 SpreadLists sl;

@@ -221,9 +221,7 @@ template <int MF>
 static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
     switch (a.var) {
         case 0: return spread_plain<MF, spread_band_rows(MF), spread_freqs(MF)>(a, s);
-        case spread_var(2, 8): return spread_plain<MF, 2, 8>(a, s);
         case spread_var(4, 4): return spread_plain<MF, 4, 4>(a, s);
-        case spread_var(1, 16): return spread_plain<MF, 1, 16>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -281,8 +279,6 @@ static hipError_t spread_grouped_mf(int var, const Group<SpreadArgs>& g, hipStre
         case spread_var(8, 1): return spread_grouped<MF, 8, 1>(g, s);
         case spread_var(8, 2): return spread_grouped<MF, 8, 2>(g, s);
         case spread_var(16, 1): return spread_grouped<MF, 16, 1>(g, s);
-        case spread_var(2, 8): return spread_grouped<MF, 2, 8>(g, s);
-        case spread_var(1, 16): return spread_grouped<MF, 1, 16>(g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -291,14 +287,13 @@ bool spread_var_ok(int Mf, int var) {
     if (Mf < 128 || Mf > 2048 || (Mf & (Mf - 1))) return false;
     if (var == 0) return true;
     const int br = var / 100, nf = var % 100;
-    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1) ||
-          (br == 2 && nf == 8) || (br == 1 && nf == 16)))
+    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1)))
         return false;
     return spread_fits(Mf, br, nf);
 }
 
 bool spread_var_plain_ok(int Mf, int var) {
-    return var == 0 || ((var == spread_var(2, 8) || var == spread_var(4, 4) || var == spread_var(1, 16)) &&
+    return var == 0 || (var == spread_var(4, 4) &&
                         spread_var_ok(Mf, var) && Mf >= 32 && Mf <= 2048);
 }
 
