@@ -1356,8 +1356,12 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             const int nw1 = batch_choice(bt, BK_P1, M), nw2 = batch_choice(bt, BK_P2, M);
             const int nw3 = batch_choice(bt, BK_P3, M);
             bool half = true;       // one row-pass variant per launch: every window within M/2
+            bool halfy = true;      // the same for the column pass, along y
             for (const BatchScene& sc : bt->sc)
-                if (sc.p->M == M && r < sc.rounds) half = half && 2 * sc.p->nx * sc.p->q <= M;
+                if (sc.p->M == M && r < sc.rounds) {
+                    half = half && 2 * sc.p->nx * sc.p->q <= M;
+                    halfy = halfy && 2 * sc.p->ny * sc.p->q <= M;
+                }
             for (size_t i = 0; i < bt->sc.size(); ++i) {
                 BatchScene& sc = bt->sc[i];
                 nursd_plan* p = sc.p;
@@ -1388,6 +1392,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             }
             add(BK_P1, M, 0, nw1, i1, g1x, g1y, w1);
             add(BK_P2, M, 0, nw2, i2, g2x, g2y, w12);
+            if (!i2.empty()) bt->launches.back().half = halfy ? 1 : 0;
             add(BK_P3, M, 0, nw3, i3, g3x, g3y, w3);
             if (!i3.empty()) bt->launches.back().half = half ? 1 : 0;
         }
@@ -1408,6 +1413,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             BatchLaunch L;
             L.kind = BK_MULTI;
             L.scene = (int)k;
+            L.half = 1;             // every user's window within M/2 rows
             for (int i : mem) {
                 const BatchScene& sc = bt->sc[i];
                 const nursd_plan* p = sc.p;
@@ -1429,6 +1435,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
                         u.ny = p->ny;
                         u.q = p->q;
                         users[sc.kidx[(size_t)b * p->nz + iz]].push_back(u);
+                        if (2 * p->ny * p->q > p->M) L.half = 0;
                     }
                 L.p3.push_back({i, iz0, nzr});
             }
@@ -1591,7 +1598,7 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s, LaunchTimer* tm = nullptr) {
             ma.M = kc.M;
             ma.BS = kc.BS;
             ma.tw = kc.tw;
-            HIP_TRY(launch_propagate_cols_multi(ma, L.total, s));
+            HIP_TRY(launch_propagate_cols_multi(ma, L.total, L.half != 0, s));
             for (const auto& t : L.p3) {
                 const BatchScene& sc = bt->sc[t[0]];
                 nursd_plan* p = sc.p;
@@ -1643,7 +1650,9 @@ int batch_enqueue(nursd_batch* bt, hipStream_t s, LaunchTimer* tm = nullptr) {
             case BK_SPREAD: HIP_TRY(launch_spread_xfft_grouped(L.size, L.var, group_of<SpreadArgs>(bt, L), s)); break;
             case BK_FINEY: HIP_TRY(launch_fine_y_grouped(L.size, L.var, group_of<FineYArgs>(bt, L), s)); break;
             case BK_P1: HIP_TRY(launch_kernel_rows_grouped(L.size, L.var, group_of<P1Args>(bt, L), s)); break;
-            case BK_P2: HIP_TRY(launch_propagate_cols_grouped(L.size, L.var, group_of<P2Args>(bt, L), s)); break;
+            case BK_P2:
+                HIP_TRY(launch_propagate_cols_grouped(L.size, L.half != 0, L.var, group_of<P2Args>(bt, L), s));
+                break;
             default:
                 HIP_TRY(launch_propagate_rows_grouped(L.size, L.half != 0, L.var, group_of<P3Args>(bt, L), s));
                 break;

@@ -170,11 +170,15 @@ constexpr int kP2Waves = NURSD_P2_WAVES;
 // target: for s = kx and s = M - kx, Yp[s][iy] = IDFT_y(U[s] * g)[window row
 // iy] with g the permuted kernel spectrum line(s).  ny, q: the target's
 // window rows and upsampling.
-template <int M>
+// HALFY (M >= 256, ny q <= M/2): window rows lie within |m| < M/4, so the
+// slots e with M/4 <= 64 e < 3M/4 are never stored and the last radix stage
+// of the inverse transform only forms the outputs that are.
+template <int M, bool HALFY = false>
 __device__ __forceinline__ void cols_apply(const float2* g, const float2* __restrict__ Ub, float2* Yp, int ny, int qf,
                                            int kx0, float2* scr, const float2* tws, int lane) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW;
+    static_assert(!HALFY || M >= 256, "row pruning needs quarter periods of whole 64-row slots");
     const int half = ny / 2;
     float2 v[F::NV];
 #pragma unroll
@@ -202,6 +206,7 @@ __device__ __forceinline__ void cols_apply(const float2* g, const float2* __rest
                 float2* row = Yp + (size_t)s * ny + half + lane;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
+                    if (HALFY && 64 * e >= M / 4 && 64 * e < 3 * M / 4) continue;
                     const bool lower = H % 64 == 0 ? 64 * e < H : lane + 64 * e < H;
                     const int off = lower ? 64 * e : 64 * e - M;
                     const int iy = lane + off + half;
@@ -213,6 +218,7 @@ __device__ __forceinline__ void cols_apply(const float2* g, const float2* __rest
                 float2* row = Yp + (size_t)s * ny;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
+                    if (HALFY && 64 * e >= M / 4 && 64 * e < 3 * M / 4) continue;
                     const int n = lane + 64 * e;
                     const int t = (n < H ? n : n - M) + hq;
                     if (t >= 0 && t % qf == 0 && t / qf < ny) row[t / qf] = v[q * E + e];
@@ -242,7 +248,7 @@ __device__ __forceinline__ void load_kernel_lines(float2* v, const float2* __res
     }
 }
 
-template <int M, int NW = kP2Waves>
+template <int M, int NW = kP2Waves, bool HALFY = false>
 __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2;
@@ -261,14 +267,14 @@ __device__ __forceinline__ void propagate_cols_body(const P2Args& a, int bx, int
     __syncthreads();
     if (kx0 > H) return;                // wave-uniform; no block barriers below
     F::template nat_to_perm<false>(g, scr, tws, lane);
-    cols_apply<M>(g, a.U + (size_t)b * M * M, a.Yt + (size_t)p * M * a.ny, a.ny, a.q, kx0, scr, tws, lane);
+    cols_apply<M, HALFY>(g, a.U + (size_t)b * M * M, a.Yt + (size_t)p * M * a.ny, a.ny, a.q, kx0, scr, tws, lane);
 }
 
 // Batched mode, one kernel spectrum line for many scenes: block (bx, item)
 // transforms the kernel lines of table plane kp[item] once and applies them
 // to every user of that plane (a scene's spectrum at the user's frequency
 // and its output plane).
-template <int M, int NW = kP2Waves>
+template <int M, int NW = kP2Waves, bool HALFY = false>
 __device__ __forceinline__ void propagate_cols_multi_body(const P2MArgs& a, int bx, int item) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2;
@@ -286,7 +292,7 @@ __device__ __forceinline__ void propagate_cols_multi_body(const P2MArgs& a, int 
     const int u1 = a.user_ptr[item + 1];
     for (int u = a.user_ptr[item]; u < u1; ++u) {
         const P2MUser us = a.users[u];
-        cols_apply<M>(g, us.U, us.Yt, us.ny, us.q, kx0, scr, tws, lane);
+        cols_apply<M, HALFY>(g, us.U, us.Yt, us.ny, us.q, kx0, scr, tws, lane);
     }
 }
 
@@ -473,19 +479,19 @@ __global__ __launch_bounds__(NW * 64, (M >= 1024 ? 4 : 8)) void k_kernel_rows_gr
 // works through a contiguous run of (plane, kx block) work items: the planes
 // of one frequency share its spectrum U, which then stays in that XCD's L2.
 
-template <int M>
+template <int M, bool HALFY>
 __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols(P2Args a) {
     const int v = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
-    propagate_cols_body<M>(a, v % gridDim.x, v / gridDim.x);
+    propagate_cols_body<M, kP2Waves, HALFY>(a, v % gridDim.x, v / gridDim.x);
 }
-template <int M, int NW>
+template <int M, int NW, bool HALFY>
 __global__ __launch_bounds__(NW * 64) void k_propagate_cols_grouped(Group<P2Args> g) {
-    persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M, NW>(a, bx, by); });
+    persistent_loop(g, [](const P2Args& a, int bx, int by) { propagate_cols_body<M, NW, HALFY>(a, bx, by); });
 }
-template <int M>
+template <int M, bool HALFY>
 __global__ __launch_bounds__(kP2Waves * 64) void k_propagate_cols_multi(P2MArgs a) {
     const int2 w = a.blk[blockIdx.x];
-    propagate_cols_multi_body<M>(a, w.y, w.x);
+    propagate_cols_multi_body<M, kP2Waves, HALFY>(a, w.y, w.x);
 }
 template <int M, bool HALF>
 __global__ __launch_bounds__((p3_waves<M, HALF>() * 64)) void k_propagate_rows(P3Args a) {
@@ -558,17 +564,21 @@ hipError_t launch_propagate_cols(const P2Args& a, hipStream_t s) {
         using F = WaveFFT<MM>;
         constexpr int LB = kP2Waves * F::LPW;
         dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
-        return launch_rsd(k_propagate_cols<MM>, grid, kP2Waves * 64, (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s,
-                          a);
+        const size_t sh = (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2);
+        if (MM >= 256 && 2 * a.ny * a.q <= MM)
+            return launch_rsd(k_propagate_cols<MM, (MM >= 256)>, grid, kP2Waves * 64, sh, s, a);
+        return launch_rsd(k_propagate_cols<MM, false>, grid, kP2Waves * 64, sh, s, a);
     })
 }
 
-hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, hipStream_t s) {
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, bool halfy, hipStream_t s) {
     if (nblk <= 0) return hipSuccess;
     NURSD_SWITCH_M(a.M, {
         using F = WaveFFT<MM>;
-        return launch_rsd(k_propagate_cols_multi<MM>, dim3(nblk), kP2Waves * 64,
-                          (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2), s, a);
+        const size_t sh = (size_t)(kP2Waves * F::SCR + MM) * sizeof(float2);
+        if (halfy && MM >= 256)
+            return launch_rsd(k_propagate_cols_multi<MM, (MM >= 256)>, dim3(nblk), kP2Waves * 64, sh, s, a);
+        return launch_rsd(k_propagate_cols_multi<MM, false>, dim3(nblk), kP2Waves * 64, sh, s, a);
     })
 }
 int grid_x_propagate_cols_multi(int M) { return grid_x_propagate_cols(M, kP2Waves); }
@@ -600,9 +610,11 @@ static hipError_t p1_grouped(const Group<P1Args>& g, hipStream_t s) {
                           (size_t)(W * (F::SCR + 1) + M + W * F::LPW) * sizeof(float2), s);
 }
 template <int M, int W>
-static hipError_t p2_grouped(const Group<P2Args>& g, hipStream_t s) {
+static hipError_t p2_grouped(bool halfy, const Group<P2Args>& g, hipStream_t s) {
     using F = WaveFFT<M>;
-    return launch_grouped(k_propagate_cols_grouped<M, W>, g, W * 64, (size_t)(W * F::SCR + M) * sizeof(float2), s);
+    constexpr size_t sh = (size_t)(W * F::SCR + M) * sizeof(float2);
+    if (halfy && M >= 256) return launch_grouped(k_propagate_cols_grouped<M, W, (M >= 256)>, g, W * 64, sh, s);
+    return launch_grouped(k_propagate_cols_grouped<M, W, false>, g, W * 64, sh, s);
 }
 template <int M, int W>
 static hipError_t p3_grouped(bool half, const Group<P3Args>& g, hipStream_t s) {
@@ -620,11 +632,11 @@ static hipError_t p1_grouped_m(int nw, const Group<P1Args>& g, hipStream_t s) {
     }
 }
 template <int M>
-static hipError_t p2_grouped_m(int nw, const Group<P2Args>& g, hipStream_t s) {
+static hipError_t p2_grouped_m(bool halfy, int nw, const Group<P2Args>& g, hipStream_t s) {
     switch (nw) {
-        case 2: return p2_grouped<M, 2>(g, s);
-        case 4: return p2_grouped<M, 4>(g, s);
-        case 8: return p2_grouped<M, 8>(g, s);
+        case 2: return p2_grouped<M, 2>(halfy, g, s);
+        case 4: return p2_grouped<M, 4>(halfy, g, s);
+        case 8: return p2_grouped<M, 8>(halfy, g, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -641,8 +653,8 @@ hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hip
     NURSD_SWITCH_M(M, return p1_grouped_m<MM>(nw, g, s));
 }
 
-hipError_t launch_propagate_cols_grouped(int M, int nw, const Group<P2Args>& g, hipStream_t s) {
-    NURSD_SWITCH_M(M, return p2_grouped_m<MM>(nw, g, s));
+hipError_t launch_propagate_cols_grouped(int M, bool halfy, int nw, const Group<P2Args>& g, hipStream_t s) {
+    NURSD_SWITCH_M(M, return p2_grouped_m<MM>(halfy, nw, g, s));
 }
 
 hipError_t launch_propagate_rows_grouped(int M, bool half, int nw, const Group<P3Args>& g, hipStream_t s) {

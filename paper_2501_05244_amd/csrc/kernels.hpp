@@ -138,7 +138,8 @@ struct P2MArgs {
     int M, BS;
     const float2* tw;
 };
-hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, hipStream_t s);
+// halfy: every user's window satisfies ny q <= M/2 (rows |m| >= M/4 unused).
+hipError_t launch_propagate_cols_multi(const P2MArgs& a, int nblk, bool halfy, hipStream_t s);
 int grid_x_propagate_cols_multi(int M);
 
 struct P3Args {
@@ -341,7 +342,7 @@ bool spread_var_plain_ok(int Mf, int var);   // variants of the plain (per-plan)
 hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s);
 hipError_t launch_fine_y_grouped(int Mf, int lines, const Group<FineYArgs>& g, hipStream_t s);
 hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hipStream_t s);
-hipError_t launch_propagate_cols_grouped(int M, int nw, const Group<P2Args>& g, hipStream_t s);
+hipError_t launch_propagate_cols_grouped(int M, bool halfy, int nw, const Group<P2Args>& g, hipStream_t s);
 hipError_t launch_propagate_rows_grouped(int M, bool half, int nw, const Group<P3Args>& g, hipStream_t s);
 int grid_x_kernel_rows(int M, int nw);
 int grid_x_propagate_cols(int M, int nw);
