@@ -67,13 +67,21 @@ __device__ __forceinline__ void dft4(float2* v) {
     v[3] = csub(a1, a3);
 }
 
+// dft4 of (v0, v1, 0, 0): the inputs above the first half are zero.
 template <bool INV>
-__device__ __forceinline__ void dft8(float2* v) {
+__device__ __forceinline__ void dft4_lo(float2* v) {
+    const float2 a = v[0], b = v[1], jb = mul_mj<INV>(b);
+    v[0] = cadd(a, b);
+    v[1] = cadd(a, jb);
+    v[2] = csub(a, b);
+    v[3] = csub(a, jb);
+}
+
+// Last step of the 8-point DFT from the 4-point DFTs of the even and odd
+// inputs.
+template <bool INV>
+__device__ __forceinline__ void dft8_join(float2* v, const float2* e, const float2* o) {
     constexpr float h = 0.70710678118654752440f;
-    float2 e[4] = {v[0], v[2], v[4], v[6]};
-    float2 o[4] = {v[1], v[3], v[5], v[7]};
-    dft4<INV>(e);
-    dft4<INV>(o);
     // w8^1 = (1 -/+ j)/sqrt2, w8^2 = -/+ j, w8^3 = (-1 -/+ j)/sqrt2
     float2 t1 = INV ? make_float2(h * (o[1].x - o[1].y), h * (o[1].x + o[1].y))
                     : make_float2(h * (o[1].x + o[1].y), h * (o[1].y - o[1].x));
@@ -88,6 +96,26 @@ __device__ __forceinline__ void dft8(float2* v) {
     v[6] = csub(e[2], t2);
     v[3] = cadd(e[3], t3);
     v[7] = csub(e[3], t3);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft8(float2* v) {
+    float2 e[4] = {v[0], v[2], v[4], v[6]};
+    float2 o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<INV>(e);
+    dft4<INV>(o);
+    dft8_join<INV>(v, e, o);
+}
+
+// dft8 of (v0, v1, v2, v3, 0, 0, 0, 0): the first radix-2 step reduces to
+// copies.
+template <bool INV>
+__device__ __forceinline__ void dft8_lo(float2* v) {
+    float2 e[4] = {v[0], v[2]};
+    float2 o[4] = {v[1], v[3]};
+    dft4_lo<INV>(e);
+    dft4_lo<INV>(o);
+    dft8_join<INV>(v, e, o);
 }
 
 template <int R, bool INV>

@@ -110,14 +110,15 @@ __global__ __launch_bounds__(kGridWaves * 64) void k_relay_grid_cols(RelayGridAr
 // convolutions of length M (one per half of the outputs) sharing the forward
 // transform.  In: natural layout, v[e] = a[lane + 64 e], the pre-chirped input
 // in [0, N) and zero above.  Out: natural layout of the M convolution
-// outputs.  hh: the plane's two spectra [2][M], FFT order.
-template <int M>
+// outputs.  hh: the plane's two spectra [2][M], FFT order.  LO: N <= M/2, so
+// the upper half of the input is zero and the forward transform skips it.
+template <int M, bool LO = false>
 __device__ __forceinline__ void bluestein_halves(float2* v, float2* scr, const float2* __restrict__ tw,
                                                  const float2* __restrict__ hh, int lane) {
     using F = WaveFFT<M>;
     constexpr int E = F::E, HE = E / 2;
     static_assert(F::LPW == 1 && E % 2 == 0, "one line per wave");
-    F::template nat_to_perm<false>(v, scr, tw, lane);
+    F::template nat_to_perm<false, LO>(v, scr, tw, lane);
     float2 out[E];
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
@@ -142,13 +143,13 @@ __device__ __forceinline__ void bluestein_halves(float2* v, float2* scr, const f
 // As bluestein_halves, but each output k' (centred k = k' - M/2) is written to
 // dst[k mod M] (FFT order) as soon as its half is done, so no registers hold
 // the first half while the second is transformed.
-template <int M>
+template <int M, bool LO = false>
 __device__ __forceinline__ void bluestein_halves_to(float2* v, float2* scr, const float2* __restrict__ tw,
                                                     const float2* __restrict__ hh, float2* dst, int lane) {
     using F = WaveFFT<M>;
     constexpr int E = F::E, HE = E / 2;
     static_assert(F::LPW == 1 && E % 2 == 0, "one line per wave");
-    F::template nat_to_perm<false>(v, scr, tw, lane);
+    F::template nat_to_perm<false, LO>(v, scr, tw, lane);
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         float2 b[F::NV];
@@ -175,7 +176,8 @@ constexpr int kChirpWaves = 8;
 // share a CU).
 constexpr int kChirpColWaves = 4;
 
-template <int M>
+// LO (N <= M/2): the input rows fill at most the lower half of the line.
+template <int M, bool LO>
 __global__ __launch_bounds__(kChirpWaves * 64) __attribute__((amdgpu_waves_per_eu(M >= 1024 ? 1 : 6, 8))) void k_chirp_rows(ChirpArgs a) {
     using F = WaveFFT<M>;
     constexpr int E = F::E;
@@ -210,10 +212,10 @@ __global__ __launch_bounds__(kChirpWaves * 64) __attribute__((amdgpu_waves_per_e
     for (int e = 0; e < E; ++e) {
         const int n = lane + 64 * e;
         v[e] = make_float2(0.f, 0.f);
-        if (iy < N && n < N) v[e] = cmul(urow[n], cz[n + D]);
+        if ((!LO || 2 * e < E) && iy < N && n < N) v[e] = cmul(urow[n], cz[n + D]);
     }
     float2* scr = sm + wave * SCRP;
-    bluestein_halves<M>(v, scr, tws, hh, lane);
+    bluestein_halves<M, LO>(v, scr, tws, hh, lane);
     // outputs k' = lane + 64 e < M: S[k] with k = k' - M/2, stored at kx = k mod M
     // in the block's staging rows (they overlap other waves' scratch: barrier)
     __syncthreads();
@@ -233,7 +235,11 @@ __global__ __launch_bounds__(kChirpWaves * 64) __attribute__((amdgpu_waves_per_e
     }
 }
 
-template <int M>
+// HALF (N <= M/2 and ny <= M/2): the Bluestein input lines fill at most the
+// lower half (the forward transform skips the rest), and the window rows lie
+// within |m| < M/4, so the output slots e with M/4 <= 64 e < 3M/4 are never
+// stored and the final inverse transform does not form them.
+template <int M, bool HALF>
 __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E;
@@ -287,10 +293,10 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             v[e] = make_float2(0.f, 0.f);
-            if (lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
+            if ((!HALF || 2 * e < E) && lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
         }
         // scaled spectrum column S[s][ky] / c[ky], in FFT order in LDS
-        bluestein_halves_to<M>(v, scr, tws_m, hh, line, lane);
+        bluestein_halves_to<M, HALF>(v, scr, tws_m, hh, line, lane);
         NURSD_WAVE_SYNC();
         float2 x[F::NV];
 #pragma unroll
@@ -308,6 +314,7 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
         float2* row = Yp + (size_t)s * a.ny + half + lane;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
+            if (HALF && 64 * e >= M / 4 && 64 * e < 3 * M / 4) continue;
             const int off = 64 * e < H ? 64 * e : 64 * e - M;
             const int iyo = lane + off + half;
             if (iyo >= 0 && iyo < a.ny) row[off] = x[e];
@@ -321,7 +328,8 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_cols(ChirpArgs a)
 // x and y, zero-pad to the 2M-point oversampled line, inverse FFT
 // -> T2[p][s][jy].  The Bluestein lines (length M) run in the first M slots of
 // the scratch of the 2M-point oversampled line.
-template <int M>
+// LO (N <= M/2): the Bluestein input lines fill at most the lower half.
+template <int M, bool LO>
 __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpArgs a) {
     using F = WaveFFT<M>;
     using B = WaveFFT<2 * M>;
@@ -373,9 +381,9 @@ __global__ __launch_bounds__(kChirpColWaves * 64) void k_chirp_type2_cols(ChirpA
 #pragma unroll
         for (int e = 0; e < EB; ++e) {
             v[e] = make_float2(0.f, 0.f);
-            if (lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
+            if ((!LO || 2 * e < E) && lane + 64 * e < N) v[e] = load_last(srow + 64 * e);
         }
-        bluestein_halves<M>(v, scr, tws_m, hh, lane);
+        bluestein_halves<M, LO>(v, scr, tws_m, hh, lane);
         // scaled spectrum column S[s][ky] / c[ky] (natural), staged to LDS in FFT order
         NURSD_WAVE_SYNC();
 #pragma unroll
@@ -455,57 +463,53 @@ hipError_t launch_relay_grid(const RelayGridArgs& a, hipStream_t s) {
     })
 }
 
+template <int M>
+static hipError_t chirp_rows_m(const ChirpArgs& a, hipStream_t s) {
+    using F = WaveFFT<M>;
+    const dim3 grid((a.N + kChirpWaves - 1) / kChirpWaves, a.g.nb * a.g.nzc);
+    const size_t sh = (size_t)(kChirpWaves * F::SCR + 4 * M) * sizeof(float2);
+    if (2 * a.N <= M) return launch_k(k_chirp_rows<M, true>, grid, kChirpWaves * 64, sh, s, a);
+    return launch_k(k_chirp_rows<M, false>, grid, kChirpWaves * 64, sh, s, a);
+}
+
+template <int M>
+static hipError_t chirp_cols_m(const ChirpArgs& a, hipStream_t s) {
+    using F = WaveFFT<M>;
+    const dim3 grid((M / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, a.g.nb * a.g.nzc);
+    const size_t sh = (size_t)(kChirpColWaves * (F::SCR + 1 + M) + M) * sizeof(float2);
+    if (2 * a.N <= M && 2 * a.ny <= M) return launch_k(k_chirp_cols<M, true>, grid, kChirpColWaves * 64, sh, s, a);
+    return launch_k(k_chirp_cols<M, false>, grid, kChirpColWaves * 64, sh, s, a);
+}
+
+template <int M>
+static hipError_t chirp_type2_cols_m(const ChirpArgs& a, hipStream_t s) {
+    using B = WaveFFT<2 * M>;
+    const dim3 grid((M / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, a.g.nb * a.g.nzc);
+    const size_t sh = (size_t)(kChirpColWaves * (B::SCR + 1) + 2 * M + M) * sizeof(float2);
+    if (2 * a.N <= M) return launch_k(k_chirp_type2_cols<M, true>, grid, kChirpColWaves * 64, sh, s, a);
+    return launch_k(k_chirp_type2_cols<M, false>, grid, kChirpColWaves * 64, sh, s, a);
+}
+
 hipError_t launch_chirp_rows(const ChirpArgs& a, hipStream_t s) {
-    const int planes = a.g.nb * a.g.nzc;
     switch (a.M) {
-        case 512: {
-            using F = WaveFFT<512>;
-            return launch_k(k_chirp_rows<512>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 4 * 512) * sizeof(float2), s, a);
-        }
-        case 1024: {
-            using F = WaveFFT<1024>;
-            return launch_k(k_chirp_rows<1024>, dim3((a.N + kChirpWaves - 1) / kChirpWaves, planes),
-                            kChirpWaves * 64, (size_t)(kChirpWaves * F::SCR + 4 * 1024) * sizeof(float2), s, a);
-        }
+        case 512: return chirp_rows_m<512>(a, s);
+        case 1024: return chirp_rows_m<1024>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s) {
-    const int planes = a.g.nb * a.g.nzc;
     switch (a.M) {
-        case 512: {
-            using F = WaveFFT<512>;
-            return launch_k(k_chirp_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64,
-                            (size_t)(kChirpColWaves * (F::SCR + 1 + 512) + 512) * sizeof(float2), s, a);
-        }
-        case 1024: {
-            using F = WaveFFT<1024>;
-            return launch_k(k_chirp_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64,
-                            (size_t)(kChirpColWaves * (F::SCR + 1 + 1024) + 1024) * sizeof(float2), s, a);
-        }
+        case 512: return chirp_cols_m<512>(a, s);
+        case 1024: return chirp_cols_m<1024>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s) {
-    const int planes = a.g.nb * a.g.nzc;
     switch (a.M) {
-        case 512: {
-            using B = WaveFFT<1024>;
-            return launch_k(k_chirp_type2_cols<512>, dim3((512 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 1024 + 512) * sizeof(float2),
-                            s, a);
-        }
-        case 1024: {
-            using B = WaveFFT<2048>;
-            return launch_k(k_chirp_type2_cols<1024>, dim3((1024 / 2 + 1 + kChirpColWaves - 1) / kChirpColWaves, planes),
-                            kChirpColWaves * 64, (size_t)(kChirpColWaves * (B::SCR + 1) + 2048 + 1024) * sizeof(float2),
-                            s, a);
-        }
+        case 512: return chirp_type2_cols_m<512>(a, s);
+        case 1024: return chirp_type2_cols_m<1024>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

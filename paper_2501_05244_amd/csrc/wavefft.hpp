@@ -48,21 +48,27 @@ __device__ constexpr float kS32[16] = {0.0f, 0.19509032201612827f, 0.38268343236
                                        0.38268343236508977f, 0.19509032201612827f};
 
 // In-register DFT of R = 1..32 points (forward e^{-}, inverse e^{+}).
-template <int R, bool INV>
+// LO: the inputs v[R/2..R-1] are zero (R >= 4) and are not read.
+template <int R, bool INV, bool LO = false>
 __device__ __forceinline__ void dft_reg(float2* v) {
+    static_assert(!LO || R >= 4, "zero upper half needs at least 4 points");
     if constexpr (R == 1) {
         return;
+    } else if constexpr (LO && R == 4) {
+        dft4_lo<INV>(v);
+    } else if constexpr (LO && R == 8) {
+        dft8_lo<INV>(v);
     } else if constexpr (R <= 8) {
         dftR<R, INV>(v);
     } else {
         float2 ev[R / 2], od[R / 2];
 #pragma unroll
         for (int i = 0; i < R / 2; ++i) {
-            ev[i] = v[2 * i];
-            od[i] = v[2 * i + 1];
+            ev[i] = LO && 2 * i >= R / 2 ? make_float2(0.f, 0.f) : v[2 * i];
+            od[i] = LO && 2 * i + 1 >= R / 2 ? make_float2(0.f, 0.f) : v[2 * i + 1];
         }
-        dft_reg<R / 2, INV>(ev);
-        dft_reg<R / 2, INV>(od);
+        dft_reg<R / 2, INV, LO>(ev);
+        dft_reg<R / 2, INV, LO>(od);
 #pragma unroll
         for (int k = 0; k < R / 2; ++k) {
             const float c = R == 16 ? kC16[k] : kC32[k];
@@ -106,14 +112,17 @@ struct WaveFFT {
         return k1 + E * c + 8 * E * d;
     }
 
-    template <bool INV>
+    // LO (one line per wave, E >= 4): the inputs n >= N/2 (slots e >= E/2)
+    // are zero and are not read.
+    template <bool INV, bool LO = false>
     __device__ static __forceinline__ void nat_to_perm(float2* v, float2* scr, const float2* __restrict__ tw,
                                                        int lane) {
+        static_assert(!LO || (LPW == 1 && E >= 4), "zero upper half needs one line of at least 256 points");
         const int a = lane & 7, b = lane >> 3;
 #pragma unroll
         for (int q = 0; q < LPW; ++q) {
             float2* y = v + q * E;
-            dft_reg<E, INV>(y);
+            dft_reg<E, INV, LO>(y);
 #pragma unroll
             for (int k1 = 1; k1 < E; ++k1) y[k1] = twiddle<INV>(y[k1], tw[(lane * k1) & (N - 1)]);
         }
