@@ -339,6 +339,8 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     static_assert(M * RB % (NW * 64) == 0, "tile must divide over the block");
     extern __shared__ float2 sm[];      // two tiles [2][NW][SCRP], then twiddles [M]
     float2* tws = sm + 2 * NW * SCRP;
+    // (staged before the tile request: loads complete in order, so waiting
+    // for the table after it would wait for the tile too)
     for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
     const int zl = by;
     const int iz = a.g.z0 + zl;
@@ -350,8 +352,24 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
     const double py = a.g.pitch_y ? a.g.pitch_y[iz] : a.g.dy;
     const size_t plane_off = (size_t)iz * ny * nx;
     const int b_end = a.g.b0 + a.g.nb;
+    // This thread's share of the block's column tile: entry i = tid + r * NW * 64
+    // holds column s = i / RB of output row iy0 + i % RB.  Since NW * 64 is a
+    // multiple of RB, the row is tid % RB for every r and the column steps by
+    // 64 / LPW.  Rows past ny (ragged last block) load row ny - 1 instead:
+    // their transforms are never stored, and the loads need no branch.  The
+    // first tile is requested before the per-voxel set-up below, which then
+    // overlaps its latency.
+    float2 pre[NPRE];
+    const float2* Yb = a.Yt + (size_t)zl * M * ny;
+    const size_t fstride = (size_t)a.g.nzc * M * ny;  // next frequency, same plane
+    static_assert((NW * 64) % RB == 0, "tile rows repeat with period RB");
+    const unsigned toff = (unsigned)((tid / RB) * ny + min(iy0 + tid % RB, ny - 1));
+    const unsigned tstep = (unsigned)((64 / LPW) * ny);
+#pragma unroll
+    for (int r = 0; r < NPRE; ++r) pre[r] = Yb[toff + r * tstep];
     constexpr int SPG = HALF ? 4 : 8;                   // kept slots per 8-point group
     constexpr int NS = F::GPL * SPG;
+    const double f0c = a.g.f[a.g.b0] / kC, dfc = a.g.df / kC;   // cycles per metre
     float2 acc[NS], ph[NS], st[NS];
     int off[NS];                        // output offset within the plane, -1 outside the window
 #pragma unroll
@@ -376,27 +394,14 @@ __device__ __forceinline__ void propagate_rows_body(const P3Args& a, int bx, int
                 const double x = a.xc + m * px;
                 const double y = a.yc + (iy * a.q - (ny * a.q) / 2) * py;
                 const double dd = dist3(x - a.xp0, y - a.xp1, z - a.xp2);
-                ph[sl] = phase_of(dd, a.g.f[a.g.b0] / kC);
-                st[sl] = phase_of(dd, a.g.df / kC);
+                ph[sl] = phase_of(dd, f0c);
+                st[sl] = phase_of(dd, dfc);
                 if (!a.first) {
                     if (a.coherent) acc[sl] = a.V[plane_off + off[sl]];
                     else acc[sl].x = a.I[plane_off + off[sl]];
                 }
             }
         }
-    // This thread's share of the block's column tile: entry i = tid + r * NW * 64
-    // holds column s = i / RB of output row iy0 + i % RB.  Since NW * 64 is a
-    // multiple of RB, the row is tid % RB for every r and the column steps by
-    // 64 / LPW.  Rows past ny (ragged last block) load row ny - 1 instead:
-    // their transforms are never stored, and the loads need no branch.
-    float2 pre[NPRE];
-    const float2* Yb = a.Yt + (size_t)zl * M * ny;
-    const size_t fstride = (size_t)a.g.nzc * M * ny;  // next frequency, same plane
-    static_assert((NW * 64) % RB == 0, "tile rows repeat with period RB");
-    const unsigned toff = (unsigned)((tid / RB) * ny + min(iy0 + tid % RB, ny - 1));
-    const unsigned tstep = (unsigned)((64 / LPW) * ny);
-#pragma unroll
-    for (int r = 0; r < NPRE; ++r) pre[r] = Yb[toff + r * tstep];
     // Two tiles alternate: while the waves transform their rows of frequency b
     // (each wave uses its own row of the tile as FFT scratch), frequency b+1 is
     // stored into the other tile and b+2 is loaded, with one barrier per step.
