@@ -75,10 +75,16 @@ __device__ __forceinline__ void plane_of(const ChunkGeom& g, int p, int& b, int&
 #endif
 constexpr int kP1Waves = NURSD_P1_WAVES;
 
+// Pitch of a wave's scratch row (float2): the FFT scratch plus 2, so that at
+// M = 512 the transposed read of the block's output (its 8 rows of one
+// column, then of the next) touches distinct LDS bank pairs.
+template <int M>
+constexpr int p1_scrp() { return WaveFFT<M>::SCR + 2; }
+
 template <int M, int NW = kP1Waves>
 __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
     using F = WaveFFT<M>;
-    constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = F::SCR + 1;
+    constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = p1_scrp<M>();
     extern __shared__ float2 sm[];      // [NW][SCRP], twiddles [M], Nyquist samples [LB]
     float2* tws = sm + NW * SCRP;
     for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
@@ -558,7 +564,7 @@ hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s) {
         constexpr int LB = kP1Waves * F::LPW;
         dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
         return launch_rsd(k_kernel_rows<MM>, grid, kP1Waves * 64,
-                          (size_t)(kP1Waves * (F::SCR + 1) + MM + kP1Waves * F::LPW) * sizeof(float2),
+                          (size_t)(kP1Waves * p1_scrp<MM>() + MM + kP1Waves * F::LPW) * sizeof(float2),
                           s, a);
     })
 }
@@ -612,7 +618,7 @@ template <int M, int W>
 static hipError_t p1_grouped(const Group<P1Args>& g, hipStream_t s) {
     using F = WaveFFT<M>;
     return launch_grouped(k_kernel_rows_grouped<M, W>, g, W * 64,
-                          (size_t)(W * (F::SCR + 1) + M + W * F::LPW) * sizeof(float2), s);
+                          (size_t)(W * p1_scrp<M>() + M + W * F::LPW) * sizeof(float2), s);
 }
 template <int M, int W>
 static hipError_t p2_grouped(bool halfy, const Group<P2Args>& g, hipStream_t s) {

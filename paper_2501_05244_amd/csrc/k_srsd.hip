@@ -182,7 +182,8 @@ __global__ __launch_bounds__(kChirpWaves * 64) __attribute__((amdgpu_waves_per_e
     using F = WaveFFT<M>;
     constexpr int E = F::E;
     constexpr int SCRP = F::SCR;
-    constexpr int MP = M + 1;                // staging row of the transposed store
+    constexpr int MP = M + 2;                // staging row of the transposed store (8 rows
+                                             // of one column on distinct bank pairs)
     static_assert(MP <= SCRP, "staging must fit the scratch");
     // [kChirpWaves][SCRP] FFT scratch (later [kChirpWaves][MP] staging), twiddles
     // [M], the plane's chirp spectra [2][M] and chirp [M]
