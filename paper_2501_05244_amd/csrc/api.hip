@@ -50,16 +50,17 @@ int fail(int code, const std::string& msg) {
 constexpr int kSupportedM[] = {64, 128, 256, 512, 1024};
 
 // Spreading tile of the plans' own launches (spread_var(band rows,
-// frequencies per workgroup)), for 3D (depth-mode) plans and others: 4 x 4
-// measured 6 % faster than 8 x 2 at the SPAD workload and 5 % faster in the
-// 3D stage 1 (2 x 8 and 1 x 16 were slower: the walk is not bound by the
-// kernel weights the frequencies share).  Sizes
-// whose tile does not fit LDS keep 8 x 2 (or 8 x 1).
+// frequencies per workgroup)), for 3D (depth-mode) plans and others: one
+// fine row of 16 frequencies measured fastest (SPAD spreading 0.86 ms against
+// 1.03 for 4 x 4 and 0.92 for 2 x 8; 3D stage-1 spreading 13.8 ms against
+// 16.4 and 14.7): every lane of a step then works on one of the 16 copies of
+// a tap row.  Sizes whose tile does not fit LDS fall back to one row of 8
+// frequencies, then to 8 x 2 (or 8 x 1).
 #ifndef NURSD_PLAN_SPREAD_VAR
-#define NURSD_PLAN_SPREAD_VAR 404
+#define NURSD_PLAN_SPREAD_VAR 116
 #endif
 #ifndef NURSD_PLAN3D_SPREAD_VAR
-#define NURSD_PLAN3D_SPREAD_VAR 404
+#define NURSD_PLAN3D_SPREAD_VAR 116
 #endif
 constexpr size_t kAlign = 256;
 
@@ -568,6 +569,7 @@ int run_spectrum(nursd_plan* p, const float2* P, float2* U, char* ws, hipStream_
         fa.Mf = p->Mf;
         fa.b0 = b0;
         fa.nb = nb;
+        fa.br = spread_var_rows(p->spread_var, p->Mf);
         LAUNCH(p, NURSD_STAGE_FINE_Y, FineYArgs, launch_fine_y, fa, s);
     }
     return NURSD_OK;
@@ -1044,7 +1046,8 @@ std::vector<int> choice_candidates(const nursd_batch* bt, int kind, int size) {
     std::vector<int> v;
     switch (kind) {
         case BK_SPREAD:
-            for (int c : {0, spread_var(4, 1), spread_var(4, 2), spread_var(4, 4), spread_var(8, 1), spread_var(16, 1)}) {
+            for (int c : {0, spread_var(1, 8), spread_var(1, 16), spread_var(2, 8), spread_var(4, 1), spread_var(4, 2),
+                          spread_var(4, 4), spread_var(8, 1), spread_var(16, 1)}) {
                 if (!spread_var_ok(size, c)) continue;
                 const int br = spread_var_rows(c, size);
                 bool have = true;
@@ -1325,6 +1328,7 @@ void batch_tables(nursd_batch* bt, const BatchConfig& c, uintptr_t ws_base) {
             f.Mf = Mf;
             f.b0 = 0;
             f.nb = p->F;
+            f.br = BR;
             it2.push_back(f);
             gx2.push_back(p->M / nl);
             gy2.push_back(p->F);
@@ -2259,6 +2263,7 @@ static int nursd_plan_create_body(const nursd_wavelet* wl, const nursd_geometry*
         if ((rc = upload(p, wv, &p->d_w))) return bail(rc);
     }
     p->spread_var = p->mode == NURSD_MODE_GRID3D ? NURSD_PLAN3D_SPREAD_VAR : NURSD_PLAN_SPREAD_VAR;
+    if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = spread_var(1, 8);
     if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = 0;
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);
@@ -2662,7 +2667,7 @@ static int nursd_batch_create_body(nursd_plan* const* plans, int32_t n, int32_t 
         for (int i = 0; i < n; ++i) {
             const nursd_plan* p = plans[i];
             const int class_br = spread_var_rows(batch_choice(bt, BK_SPREAD, p->Mf), p->Mf);
-            for (int br : {4, 8, 16}) {
+            for (int br : {1, 2, 4, 8, 16}) {
                 if (br == spread_var_rows(p->spread_var, p->Mf) || p->Mf / br < 2) continue;
                 if (!bt->autotune && br != class_br) continue;
                 SpreadLists sl;

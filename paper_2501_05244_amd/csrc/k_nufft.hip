@@ -20,6 +20,12 @@
 
 namespace nursd {
 
+#ifndef NURSD_SPREAD_WALK
+#define NURSD_SPREAD_WALK 1
+#endif
+#ifndef NURSD_SPREAD_KB
+#define NURSD_SPREAD_KB 4
+#endif
 constexpr int kSpreadThreads = 1024;
 // LDS row stride of a band: 8 cells of padding put the 8 tap rows of one
 // sample on different banks.
@@ -48,12 +54,15 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     const int e0 = a.band_ptr[band], e1 = a.band_ptr[band + 1];
     const int M = a.M;
     const int y0 = band * kBandRows;
-    float2* T1 = a.T1 + (size_t)by * NF * M * MF;     // chunk-local frequency by * NF
+    // this band of chunk-local frequency by * NF; a frequency's bands are
+    // M * kBandRows apart, so each block writes nf contiguous runs
+    float2* T1 = a.T1 + ((size_t)by * NF * (MF / kBandRows) + band) * M * kBandRows;
+    constexpr size_t kBands = MF / kBandRows;
     if (e0 == e1) {
         // empty band: its transform is zero
         for (int i = tid; i < nf * M * kBandRows; i += kSpreadThreads) {
-            const int f = i / (M * kBandRows), k = (i / kBandRows) % M, r = i % kBandRows;
-            T1[((size_t)f * M + k) * MF + y0 + r] = make_float2(0.f, 0.f);
+            const int f = i / (M * kBandRows), j = i % (M * kBandRows);
+            T1[(size_t)f * kBands * M * kBandRows + j] = make_float2(0.f, 0.f);
         }
         return;
     }
@@ -64,12 +73,78 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     const int wave = tid >> 6, lane = tid & 63;
     const int* rng = a.wave_rng + (band * kSpreadWaves + wave) * 4;
     const int c_lo = rng[2], c_hi = rng[3];             // columns owned by this wave
-    const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
     const float inv_hw = 1.0f / a.half_w;
     const float bl2e = a.beta * 1.4426950408889634f;
     const int w = a.w;
     const int s0 = rng[0], s1 = rng[1];
     const float2* Pb = a.P + (size_t)fa * a.L;
+#if NURSD_SPREAD_WALK == 1
+    // Lane (ti, q): tap column ti of tile row n = q + 8 r (round r), the
+    // pair (frequency n / BR, band row n % BR).  One step applies one sample
+    // to every such pair, so all lanes work when the band's rows lie inside
+    // the sample's taps (always for one-row bands).
+    constexpr int NQ = NF * kBandRows, RND = (NQ + 7) / 8;
+    const int ti = lane & 7, q0 = lane >> 3;
+    // 8 KB entries per round trip: lane (ti, q) fetches entries base + ti + 8 k
+    // (k < KB), with the value of its pair's frequency for each round; step j
+    // takes entry j from lane (j % 8, q) by a lane permute.
+    constexpr int KB = NURSD_SPREAD_KB;
+    for (int base = s0; base < s1; base += 8 * KB) {
+        int packed[KB];
+        float efx[KB], efy[KB];
+        float2 val[KB][RND];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int e = base + ti + 8 * k;
+            packed[k] = 0;
+            efx[k] = efy[k] = 0.f;
+#pragma unroll
+            for (int r = 0; r < RND; ++r) val[k][r] = make_float2(0.f, 0.f);
+            if (e < s1) {
+                const SpreadEntry en = a.ent[e];
+                packed[k] = ((int)en.ix0 & 0xffff) | ((int)en.iy0 << 16);
+                efx[k] = en.fx;
+                efy[k] = en.fy;
+                const float wl = a.wts ? a.wts[en.idx] : 1.0f;     // per-sample weight
+#pragma unroll
+                for (int r = 0; r < RND; ++r) {
+                    const int n = q0 + 8 * r, f = n / kBandRows;
+                    if (n < NQ && f < nf) val[k][r] = cscale(Pb[(size_t)f * a.L + en.idx], wl);
+                }
+            }
+        }
+        const int cnt = min(8 * KB, s1 - base);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int jn = min(8, cnt - 8 * k);
+            for (int jl = 0; jl < jn; ++jl) {
+                const int pk = __builtin_amdgcn_readlane(packed[k], jl);
+                const float fx = lane_f(efx[k], jl), fy = lane_f(efy[k], jl);
+                const int cx = (int)(short)(pk & 0xffff) + ti;
+                const int iy0 = pk >> 16;
+                const bool x_ok = ti < w && cx >= c_lo && cx < c_hi;
+                const float wx = es_kernel(((float)ti - fx) * inv_hw, bl2e);
+#pragma unroll
+                for (int r = 0; r < RND; ++r) {
+                    const int n = q0 + 8 * r;
+                    const int tj = y0 + n % kBandRows - iy0;
+                    float2 v;
+                    v.x = __shfl(val[k][r].x, 8 * q0 + jl);
+                    v.y = __shfl(val[k][r].y, 8 * q0 + jl);
+                    if (x_ok && n < NQ && tj >= 0 && tj < w) {
+                        const float wgt = wx * es_kernel(((float)tj - fy) * inv_hw, bl2e);
+                        float2* cell = &tile[n * LDT + cx];
+                        float2 c = *cell;
+                        c.x = fmaf(v.x, wgt, c.x);
+                        c.y = fmaf(v.y, wgt, c.y);
+                        *cell = c;
+                    }
+                }
+            }
+        }
+    }
+#else
+    const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
     const bool tap_ok = ti < w && tj < w;
     // 64 entries per round trip: each lane fetches one entry and its phasors,
     // then the wave walks them in order, broadcasting one per step.
@@ -111,15 +186,16 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
             }
         }
     }
+#endif
     __syncthreads();
     fft_lines<MF, kSpreadThreads / (NF * kBandRows), false>(tile, LDT, NF * kBandRows, a.tw);
     // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
     for (int i = tid; i < nf * M * kBandRows; i += kSpreadThreads) {
-        const int f = i / (M * kBandRows);
-        const int km = (i / kBandRows) % M, r = i % kBandRows;   // km = kx mod M
+        const int f = i / (M * kBandRows), j = i % (M * kBandRows);
+        const int km = j / kBandRows, r = j % kBandRows;           // km = kx mod M
         const int kf = km < M / 2 ? km : km + (MF - M);           // kx mod MF
         const float2 v = tile[(f * kBandRows + r) * LDT + kf];
-        T1[((size_t)f * M + km) * MF + y0 + r] = cscale(v, a.decx[km]);
+        T1[(size_t)f * kBands * M * kBandRows + j] = cscale(v, a.decx[km]);
     }
 }
 
@@ -127,26 +203,35 @@ constexpr int kFineYThreads = 256;
 constexpr int kFineYLines = 4;
 
 // NL lines of MF points per workgroup, NT / NL threads per line (the
-// batched variants keep 64 threads per line).
+// batched variants keep 64 threads per line).  A band of the spreading holds
+// the NL lines' values of its br rows contiguously, so the block reads runs
+// of NL * br values; LDS lines are padded by 16 so that the lines of one run
+// fall on different banks.
+template <int MF>
+constexpr int fine_y_ls() { return MF + 16; }
+
 template <int MF, int NL = kFineYLines, int NT = kFineYThreads>
 __device__ __forceinline__ void fine_y_body(const FineYArgs& a, int bx, int by) {
-    extern __shared__ float2 buf[];    // [NL][MF]
-    const int M = a.M;
+    constexpr int LS = fine_y_ls<MF>();
+    extern __shared__ float2 buf[];    // [NL][LS]
+    const int M = a.M, br = a.br;
     const int kx0 = bx * NL;
     const int fb = by;
-    const float2* T1 = a.T1 + (size_t)fb * M * MF;
+    const float2* T1 = a.T1 + (size_t)fb * M * MF + (size_t)kx0 * br;
     float2* U = a.U + (size_t)(a.b0 + fb) * M * M;
     const int tid = threadIdx.x;
+    const int run = NL * br;
     for (int i = tid; i < NL * MF; i += NT) {
-        const int l = i / MF, c = i % MF;
-        buf[i] = T1[(size_t)(kx0 + l) * MF + c];
+        const int bnd = i / run, k = i % run;          // band, then (line, row) within the run
+        const int l = k / br, c = bnd * br + k % br;
+        buf[l * LS + c] = T1[(size_t)bnd * M * br + k];
     }
     __syncthreads();
-    fft_lines<MF, NT / NL, false>(buf, MF, NL, a.tw);
+    fft_lines<MF, NT / NL, false>(buf, LS, NL, a.tw);
     for (int i = tid; i < NL * M; i += NT) {
         const int l = i / M, km = i % M;
         const int kf = km < M / 2 ? km : km + (MF - M);
-        U[(size_t)(kx0 + l) * M + km] = cscale(buf[l * MF + kf], a.decy[km]);
+        U[(size_t)(kx0 + l) * M + km] = cscale(buf[l * LS + kf], a.decy[km]);
     }
 }
 
@@ -158,9 +243,9 @@ template <int MF, int BR, int NF>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_grouped(Group<SpreadArgs> g) {
     persistent_loop(g, [](const SpreadArgs& a, int bx, int by) { spread_xfft_body<MF, BR, NF>(a, bx, by); });
 }
-template <int MF>
-__global__ __launch_bounds__(kFineYThreads) void k_fine_y(FineYArgs a) {
-    fine_y_body<MF>(a, blockIdx.x, blockIdx.y);
+template <int MF, int NL>
+__global__ __launch_bounds__(NL * 64) void k_fine_y(FineYArgs a) {
+    fine_y_body<MF, NL, NL * 64>(a, blockIdx.x, blockIdx.y);
 }
 template <int MF, int NL>
 __global__ __launch_bounds__(NL * 64) void k_fine_y_grouped(Group<FineYArgs> g) {
@@ -222,6 +307,11 @@ static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
     switch (a.var) {
         case 0: return spread_plain<MF, spread_band_rows(MF), spread_freqs(MF)>(a, s);
         case spread_var(4, 4): return spread_plain<MF, 4, 4>(a, s);
+        case spread_var(2, 8): return spread_plain<MF, 2, 8>(a, s);
+        case spread_var(1, 16): return spread_plain<MF, 1, 16>(a, s);
+        case spread_var(1, 8): return spread_plain<MF, 1, 8>(a, s);
+        case spread_var(8, 2): return spread_plain<MF, 8, 2>(a, s);
+        case spread_var(16, 1): return spread_plain<MF, 16, 1>(a, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -239,11 +329,29 @@ hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s) {
     }
 }
 
+template <int MF, int NL>
+static hipError_t finey_launch(const FineYArgs& a, hipStream_t s) {
+    const size_t sh = (size_t)NL * fine_y_ls<MF>() * sizeof(float2);
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_fine_y<MF, NL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_fine_y<MF, NL>), dim3(a.M / NL, a.nb), dim3(NL * 64), sh, s, a);
+    return hipGetLastError();
+}
+
+// Lines per workgroup: enough that the reads of a band are runs of at least
+// 16 values (NL * br) where LDS allows.
+template <int MF, int NL>
+constexpr bool fine_y_fits() { return (size_t)NL * fine_y_ls<MF>() * sizeof(float2) <= 160 * 1024; }
+
 template <int MF>
 static hipError_t finey_impl(const FineYArgs& a, hipStream_t s) {
-    size_t sh = (size_t)kFineYLines * MF * sizeof(float2);
-    hipLaunchKernelGGL(k_fine_y<MF>, dim3(a.M / kFineYLines, a.nb), dim3(kFineYThreads), sh, s, a);
-    return hipGetLastError();
+    if constexpr (fine_y_fits<MF, 16>())
+        if (a.br <= 1 && a.M % 16 == 0) return finey_launch<MF, 16>(a, s);
+    if constexpr (fine_y_fits<MF, 8>())
+        if (a.br <= 2 && a.M % 8 == 0) return finey_launch<MF, 8>(a, s);
+    return finey_launch<MF, kFineYLines>(a, s);
 }
 
 hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s) {
@@ -273,6 +381,9 @@ template <int MF>
 static hipError_t spread_grouped_mf(int var, const Group<SpreadArgs>& g, hipStream_t s) {
     switch (var) {
         case 0: return spread_grouped<MF, spread_band_rows(MF), spread_freqs(MF)>(g, s);
+        case spread_var(1, 8): return spread_grouped<MF, 1, 8>(g, s);
+        case spread_var(1, 16): return spread_grouped<MF, 1, 16>(g, s);
+        case spread_var(2, 8): return spread_grouped<MF, 2, 8>(g, s);
         case spread_var(4, 1): return spread_grouped<MF, 4, 1>(g, s);
         case spread_var(4, 2): return spread_grouped<MF, 4, 2>(g, s);
         case spread_var(4, 4): return spread_grouped<MF, 4, 4>(g, s);
@@ -287,14 +398,16 @@ bool spread_var_ok(int Mf, int var) {
     if (Mf < 128 || Mf > 2048 || (Mf & (Mf - 1))) return false;
     if (var == 0) return true;
     const int br = var / 100, nf = var % 100;
-    if (!((br == 4 && (nf == 1 || nf == 2 || nf == 4)) || (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1)))
+    if (!((br == 1 && (nf == 8 || nf == 16)) || (br == 2 && nf == 8) || (br == 4 && (nf == 1 || nf == 2 || nf == 4)) ||
+          (br == 8 && (nf == 1 || nf == 2)) || (br == 16 && nf == 1)))
         return false;
     return spread_fits(Mf, br, nf);
 }
 
 bool spread_var_plain_ok(int Mf, int var) {
-    return var == 0 || (var == spread_var(4, 4) &&
-                        spread_var_ok(Mf, var) && Mf >= 32 && Mf <= 2048);
+    return var == 0 || ((var == spread_var(4, 4) || var == spread_var(2, 8) || var == spread_var(1, 16) ||
+                         var == spread_var(1, 8) || var == spread_var(8, 2) || var == spread_var(16, 1)) &&
+                        spread_fits(Mf, var / 100, var % 100) && Mf >= 32 && Mf <= 2048);
 }
 
 hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s) {
@@ -312,7 +425,7 @@ template <int MF>
 static hipError_t fine_y_grouped_mf(int lines, const Group<FineYArgs>& g, hipStream_t s) {
     switch (lines) {
 #define NURSD_FG(NL) \
-    case NL: return launch_grouped(k_fine_y_grouped<MF, NL>, g, NL * 64, (size_t)NL * MF * sizeof(float2), s);
+    case NL: return launch_grouped(k_fine_y_grouped<MF, NL>, g, NL * 64, (size_t)NL * fine_y_ls<MF>() * sizeof(float2), s);
         NURSD_FG(2) NURSD_FG(4) NURSD_FG(8)
 #undef NURSD_FG
         default: return hipErrorInvalidValue;

@@ -56,7 +56,8 @@ struct SpreadArgs {
     const SpreadEntry* ent;       // entries sorted by band, then u
     const int* band_ptr;          // [nbands + 1]
     const int* wave_rng;          // [nbands][kSpreadWaves][4]: entry range, then column range, of each wave
-    float2* T1;                   // [Fc][M][Mf]: x-transformed bands, kx row-major
+    float2* T1;                   // [Fc][Mf/BR][M][BR]: x-transformed bands of BR fine rows,
+                                  // each band's M kept modes with its rows innermost
     const float* decx;            // [M] (-1)^kx / (phihat(kx) M^2), FFT order
     const float2* tw;             // twiddles of size Mf
     int M, Mf, L, w;
@@ -66,12 +67,13 @@ struct SpreadArgs {
 hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s);
 
 struct FineYArgs {
-    const float2* T1;             // [Fc][M][Mf]
+    const float2* T1;             // [Fc][Mf/br][M][br], as the spreading wrote it
     float2* U;                    // [F][M][M] (kx row, ky column, FFT order)
     const float* decy;            // [M]
     const float2* tw;             // size Mf
     int M, Mf;
     int b0, nb;
+    int br;                       // band rows of the spreading tile that wrote T1
 };
 hipError_t launch_fine_y(const FineYArgs& a, hipStream_t s);
 
