@@ -51,16 +51,17 @@ constexpr int kSupportedM[] = {64, 128, 256, 512, 1024};
 
 // Spreading tile of the plans' own launches (spread_var(band rows,
 // frequencies per workgroup)), for 3D (depth-mode) plans and others: one
-// fine row of 16 frequencies measured fastest (SPAD spreading 0.86 ms against
-// 1.03 for 4 x 4 and 0.92 for 2 x 8; 3D stage-1 spreading 13.8 ms against
-// 16.4 and 14.7): every lane of a step then works on one of the 16 copies of
-// a tap row.  Sizes whose tile does not fit LDS fall back to one row of 8
-// frequencies, then to 8 x 2 (or 8 x 1).
+// fine row of 8 frequencies measured fastest (with 32 frequencies per
+// launch: SPAD spreading 0.77 ms against 0.86 for one row of 16, 0.90 for
+// 2 x 8 and 1.03 for 4 x 4; 3D stage-1 spreading 12.1 ms against 13.1,
+// 14.3 and 16.4): every lane of a step works on one copy of a tap row, and
+// two workgroups share a CU.  Sizes whose tile does not fit LDS fall back
+// to 8 x 2 (or 8 x 1).
 #ifndef NURSD_PLAN_SPREAD_VAR
-#define NURSD_PLAN_SPREAD_VAR 116
+#define NURSD_PLAN_SPREAD_VAR 108
 #endif
 #ifndef NURSD_PLAN3D_SPREAD_VAR
-#define NURSD_PLAN3D_SPREAD_VAR 116
+#define NURSD_PLAN3D_SPREAD_VAR 108
 #endif
 constexpr size_t kAlign = 256;
 
@@ -340,23 +341,24 @@ int bin_relays(const nursd_plan* p, const std::vector<float>& rxy, int BR, Sprea
     // (relays usually cover only part of the period).  Taps of entry e reach
     // columns ix0 .. ix0 + w - 1, so wave columns [c_lo, c_hi) need ix0 in
     // [c_lo - w + 1, c_hi).
-    sl.wave_rng.assign((size_t)sl.nbands * kSpreadWaves * 4, 0);
+    constexpr int R = kSpreadWaves;                      // column ranges per band, one per wave
+    sl.wave_rng.assign((size_t)sl.nbands * R * 4, 0);
     for (int b = 0; b < sl.nbands; ++b) {
         auto first = ents.begin() + sl.band_ptr[b], last = ents.begin() + sl.band_ptr[b + 1];
         const long n = last - first;
-        int bound[kSpreadWaves + 1];
+        int bound[R + 1];
         bound[0] = 0;
-        bound[kSpreadWaves] = Mf;
-        for (int wv = 1; wv < kSpreadWaves; ++wv) {
-            int c = n > 0 ? (first + (n * wv) / kSpreadWaves)->ix0 : (wv * Mf) / kSpreadWaves;
+        bound[R] = Mf;
+        for (int wv = 1; wv < R; ++wv) {
+            int c = n > 0 ? (first + (n * wv) / R)->ix0 : (wv * Mf) / R;
             c = std::min(std::max(c, bound[wv - 1]), Mf);
             bound[wv] = c;
         }
-        for (int wv = 0; wv < kSpreadWaves; ++wv) {
+        for (int wv = 0; wv < R; ++wv) {
             const int lo = bound[wv] - w + 1, hi = bound[wv + 1];
             auto a = std::lower_bound(first, last, lo, [](const E& e, int v) { return e.ix0 < v; });
             auto c = std::lower_bound(first, last, hi, [](const E& e, int v) { return e.ix0 < v; });
-            int* r = &sl.wave_rng[((size_t)b * kSpreadWaves + wv) * 4];
+            int* r = &sl.wave_rng[((size_t)b * R + wv) * 4];
             r[0] = (int)(a - ents.begin());
             r[1] = (int)(c - ents.begin());
             r[2] = bound[wv];
@@ -2157,7 +2159,8 @@ static int nursd_plan_create_body(const nursd_wavelet* wl, const nursd_geometry*
     p->ZC = opt->plane_chunk > 0 ? opt->plane_chunk : (int)std::max(1L, target / p->FC);
     if (p->has_lists() && opt->plane_chunk <= 0) p->ZC = std::max(1, 32 / p->FC);
     p->ZC = std::min(p->ZC, p->nz);
-    p->FCn = std::min(p->F, 16);
+    // frequencies (3D: frequency-depth pairs) per spreading launch
+    p->FCn = std::min(p->mode == NURSD_MODE_GRID3D ? p->F * p->Mz3 : p->F, 32);
 
     // device tables
     {
@@ -2263,7 +2266,6 @@ static int nursd_plan_create_body(const nursd_wavelet* wl, const nursd_geometry*
         if ((rc = upload(p, wv, &p->d_w))) return bail(rc);
     }
     p->spread_var = p->mode == NURSD_MODE_GRID3D ? NURSD_PLAN3D_SPREAD_VAR : NURSD_PLAN_SPREAD_VAR;
-    if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = spread_var(1, 8);
     if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = 0;
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);

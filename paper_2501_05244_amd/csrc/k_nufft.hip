@@ -5,14 +5,17 @@
 // Blur kernel: exponential of semicircle psi(z) = exp(beta (sqrt(1 - z^2) - 1)),
 // |z| <= 1, over w fine cells; oversampling sigma = 2 (fine grid Mf = 2M).
 //
-// k_spread_xfft: one workgroup owns a band of kBandRows fine rows (all Mf
-// columns) of spread_freqs frequencies in LDS (the kernel weights of a sample
-// are computed once for all of them).  Relay samples are pre-binned per band
-// and sorted by x; each wavefront owns a disjoint range of columns (split so
-// the waves' sample counts balance) and walks the samples overlapping it, one sample per step with one lane per kernel
-// tap, so every LDS cell is updated by one wave in a fixed order: no atomics,
-// bitwise reproducible.  The band is then FFT'd along x in LDS and only the
-// M kept modes are written, scaled by the x deconvolution factor.
+// k_spread_xfft: one workgroup owns a band of BR fine rows (all Mf columns)
+// of NF frequencies in LDS.  Relay samples are pre-binned per band and
+// sorted by x; each wavefront owns a disjoint range of columns (split so the
+// waves' sample counts balance) and walks the samples overlapping it, one
+// sample per step, its lanes spread over (tap column, frequency and band
+// row) so the x kernel weight of a sample is computed once for all its
+// copies.  Every LDS cell is updated by one wave in a fixed order: no
+// atomics, bitwise reproducible.  The band is then FFT'd along x in LDS and
+// only the M kept modes are written, scaled by the x deconvolution factor,
+// band-major ([frequency][band][mode][band row]) so each block writes
+// contiguous runs.
 // k_fine_y: FFT along y of each kept kx row, keep M modes, deconvolve in y.
 #include "fft.hpp"
 #include "kernels.hpp"
@@ -20,12 +23,6 @@
 
 namespace nursd {
 
-#ifndef NURSD_SPREAD_WALK
-#define NURSD_SPREAD_WALK 1
-#endif
-#ifndef NURSD_SPREAD_KB
-#define NURSD_SPREAD_KB 4
-#endif
 constexpr int kSpreadThreads = 1024;
 // LDS row stride of a band: 8 cells of padding put the 8 tap rows of one
 // sample on different banks.
@@ -78,7 +75,6 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     const int w = a.w;
     const int s0 = rng[0], s1 = rng[1];
     const float2* Pb = a.P + (size_t)fa * a.L;
-#if NURSD_SPREAD_WALK == 1
     // Lane (ti, q): tap column ti of tile row n = q + 8 r (round r), the
     // pair (frequency n / BR, band row n % BR).  One step applies one sample
     // to every such pair, so all lanes work when the band's rows lie inside
@@ -88,7 +84,7 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     // 8 KB entries per round trip: lane (ti, q) fetches entries base + ti + 8 k
     // (k < KB), with the value of its pair's frequency for each round; step j
     // takes entry j from lane (j % 8, q) by a lane permute.
-    constexpr int KB = NURSD_SPREAD_KB;
+    constexpr int KB = 4;
     for (int base = s0; base < s1; base += 8 * KB) {
         int packed[KB];
         float efx[KB], efy[KB];
@@ -143,50 +139,6 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
             }
         }
     }
-#else
-    const int ti = lane & 7, tj = lane >> 3;    // tap offsets of this lane
-    const bool tap_ok = ti < w && tj < w;
-    // 64 entries per round trip: each lane fetches one entry and its phasors,
-    // then the wave walks them in order, broadcasting one per step.
-    for (int base = s0; base < s1; base += 64) {
-        const int e = base + lane;
-        int packed = 0;
-        float efx = 0.f, efy = 0.f;
-        float2 ep[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) ep[f] = make_float2(0.f, 0.f);
-        if (e < s1) {
-            const SpreadEntry en = a.ent[e];
-            packed = ((int)en.ix0 & 0xffff) | ((int)en.iy0 << 16);
-            efx = en.fx;
-            efy = en.fy;
-            const float wl = a.wts ? a.wts[en.idx] : 1.0f;     // per-sample weight
-#pragma unroll
-            for (int f = 0; f < NF; ++f)
-                if (f < nf) ep[f] = cscale(Pb[(size_t)f * a.L + en.idx], wl);
-        }
-        const int cnt = min(64, s1 - base);
-        for (int j = 0; j < cnt; ++j) {
-            // entry j of the batch, broadcast through scalar registers
-            const int pk = __builtin_amdgcn_readlane(packed, j);
-            const float fx = lane_f(efx, j), fy = lane_f(efy, j);
-            const int cx = (int)(short)(pk & 0xffff) + ti;
-            const int cy = (pk >> 16) + tj;
-            if (tap_ok && cx >= c_lo && cx < c_hi && cy >= y0 && cy < y0 + kBandRows) {
-                const float wgt = es_kernel(((float)ti - fx) * inv_hw, bl2e) * es_kernel(((float)tj - fy) * inv_hw, bl2e);
-#pragma unroll
-                for (int f = 0; f < NF; ++f) {
-                    const float px = lane_f(ep[f].x, j), py = lane_f(ep[f].y, j);
-                    float2* cell = &tile[(f * kBandRows + cy - y0) * LDT + cx];
-                    float2 c = *cell;
-                    c.x = fmaf(px, wgt, c.x);
-                    c.y = fmaf(py, wgt, c.y);
-                    *cell = c;
-                }
-            }
-        }
-    }
-#endif
     __syncthreads();
     fft_lines<MF, kSpreadThreads / (NF * kBandRows), false>(tile, LDT, NF * kBandRows, a.tw);
     // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
