@@ -20,6 +20,7 @@
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "persistent.hpp"
+#include "wavefft.hpp"
 
 namespace nursd {
 
@@ -157,16 +158,17 @@ constexpr int kFineYLines = 4;
 // NL lines of MF points per workgroup, NT / NL threads per line (the
 // batched variants keep 64 threads per line).  A band of the spreading holds
 // the NL lines' values of its br rows contiguously, so the block reads runs
-// of NL * br values; LDS lines are padded by 16 so that the lines of one run
-// fall on different banks.
+// of NL * br values.  LDS lines are 2 br (at most 16) cells longer than MF:
+// the lanes that store one run (l * br + r) then hit distinct banks for the
+// launches' NL * br = 16 or 32.
 template <int MF>
-constexpr int fine_y_ls() { return MF + 16; }
+constexpr int fine_y_ls() { return MF + 16; }      // allocation per line
 
 template <int MF, int NL = kFineYLines, int NT = kFineYThreads>
 __device__ __forceinline__ void fine_y_body(const FineYArgs& a, int bx, int by) {
-    constexpr int LS = fine_y_ls<MF>();
     extern __shared__ float2 buf[];    // [NL][LS]
     const int M = a.M, br = a.br;
+    const int LS = MF + 2 * min(br, 8);
     const int kx0 = bx * NL;
     const int fb = by;
     const float2* T1 = a.T1 + (size_t)fb * M * MF + (size_t)kx0 * br;
@@ -195,6 +197,56 @@ template <int MF, int BR, int NF>
 __global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_grouped(Group<SpreadArgs> g) {
     persistent_loop(g, [](const SpreadArgs& a, int bx, int by) { spread_xfft_body<MF, BR, NF>(a, bx, by); });
 }
+// Fine y with one register-resident transform per wavefront (one line of
+// MF >= 512 points per wave): the block stages its NL lines in LDS as above,
+// then each wave transforms its line in registers, using the line's LDS row
+// as exchange scratch, and stores the kept modes straight from the permuted
+// layout.  Since MF = 2M, the kept modes (k < M/2 or k >= MF - M/2) are the
+// slots d = 0, 1, 6, 7 of every 8-point group, so the last radix stage only
+// forms those.  No block barrier after the load.
+template <int MF, int NL>
+constexpr int fine_y_wave_pitch() { return WaveFFT<MF>::SCR + 16; }
+template <int MF, int NL>
+constexpr size_t fine_y_wave_lds() { return ((size_t)NL * fine_y_wave_pitch<MF, NL>() + MF) * sizeof(float2); }
+
+template <int MF, int NL>
+__global__ __launch_bounds__(NL * 64) void k_fine_y_wave(FineYArgs a) {
+    using F = WaveFFT<MF>;
+    static_assert(F::LPW == 1 && F::GPL * 8 == F::E, "one line per wavefront");
+    extern __shared__ float2 sm[];     // [NL][pitch] lines and exchange scratch, then twiddles [MF]
+    float2* tws = sm + NL * fine_y_wave_pitch<MF, NL>();
+    const int M = a.M, br = a.br;
+    const int LS = F::SCR + 2 * min(br, 8);     // as fine_y_body: lanes of one run on distinct banks
+    const int kx0 = blockIdx.x * NL;
+    const int fb = blockIdx.y;
+    const float2* T1 = a.T1 + (size_t)fb * M * MF + (size_t)kx0 * br;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int i = tid; i < MF; i += NL * 64) tws[i] = a.tw[i];
+    const int run = NL * br;
+    for (int i = tid; i < NL * MF; i += NL * 64) {
+        const int bnd = i / run, k = i % run;
+        const int l = k / br, c = bnd * br + k % br;
+        sm[l * LS + c] = T1[(size_t)bnd * M * br + k];
+    }
+    __syncthreads();
+    float2* line = sm + wave * LS;
+    float2 v[F::NV];
+#pragma unroll
+    for (int e = 0; e < F::E; ++e) v[e] = line[lane + 64 * e];
+    F::template nat_to_perm<false>(v, line, tws, lane);
+    float2* U = a.U + ((size_t)(a.b0 + fb) * M + kx0 + wave) * M;
+#pragma unroll
+    for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+            if (d >= 2 && d < 6) continue;
+            int q;
+            const int k = F::perm_k(lane, h, d, q);
+            const int km = d < 2 ? k : k - (MF - M);
+            U[km] = cscale(v[h * 8 + d], a.decy[km]);
+        }
+}
+
 template <int MF, int NL>
 __global__ __launch_bounds__(NL * 64) void k_fine_y(FineYArgs a) {
     fine_y_body<MF, NL, NL * 64>(a, blockIdx.x, blockIdx.y);
@@ -297,8 +349,27 @@ static hipError_t finey_launch(const FineYArgs& a, hipStream_t s) {
 template <int MF, int NL>
 constexpr bool fine_y_fits() { return (size_t)NL * fine_y_ls<MF>() * sizeof(float2) <= 160 * 1024; }
 
+template <int MF, int NL>
+static hipError_t finey_wave_launch(const FineYArgs& a, hipStream_t s) {
+    constexpr size_t sh = fine_y_wave_lds<MF, NL>();
+    static_assert(sh <= 160 * 1024, "fine-y lines must fit LDS");
+    if (sh > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_fine_y_wave<MF, NL>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sh);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_fine_y_wave<MF, NL>), dim3(a.M / NL, a.nb), dim3(NL * 64), sh, s, a);
+    return hipGetLastError();
+}
+
 template <int MF>
 static hipError_t finey_impl(const FineYArgs& a, hipStream_t s) {
+    if constexpr (MF == 512 || MF == 1024) {
+        if (a.Mf == 2 * a.M && a.M % 16 == 0) {
+            if (a.br <= 1) return finey_wave_launch<MF, 16>(a, s);
+            if (a.br <= 2) return finey_wave_launch<MF, 8>(a, s);
+            return finey_wave_launch<MF, 4>(a, s);
+        }
+    }
     if constexpr (fine_y_fits<MF, 16>())
         if (a.br <= 1 && a.M % 16 == 0) return finey_launch<MF, 16>(a, s);
     if constexpr (fine_y_fits<MF, 8>())
