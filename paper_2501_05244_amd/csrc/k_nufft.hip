@@ -25,10 +25,13 @@
 namespace nursd {
 
 constexpr int kSpreadThreads = 1024;
-// LDS row stride of a band: 8 cells of padding put the 8 tap rows of one
-// sample on different banks.
+// LDS row stride of a band: rows of 512 or 1024 points are transformed along
+// x by one wavefront each and double as its exchange scratch (the wave
+// transform's padded tiles, (MF / 64) * 8 * RP cells); 8 further cells put
+// the rows of one sample's step on different banks.
+constexpr int spread_row_stride(int MF) { return (MF >= 512 && MF <= 1024 ? MF / 64 * 8 * NURSD_WFFT_RP : MF) + 8; }
 template <int MF>
-constexpr int spread_row_stride() { return MF + 8; }
+constexpr int spread_row_stride() { return spread_row_stride(MF); }
 
 // psi(z) = exp(beta (sqrt(1 - z^2) - 1)) with the hardware square root and
 // base-2 exponential (beta_log2e = beta / ln 2).
@@ -141,7 +144,31 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
         }
     }
     __syncthreads();
-    fft_lines<MF, kSpreadThreads / (NF * kBandRows), false>(tile, LDT, NF * kBandRows, a.tw);
+    if constexpr (MF >= 512 && MF <= 1024) {
+        // one row per wavefront: register transform with the row as its
+        // exchange scratch (twiddles read through the caches), then the
+        // kept modes (the octants d = 0, 1, 6, 7 of MF = 2M) back in place
+        using F = WaveFFT<MF>;
+        static_assert(F::LPW == 1 && LDT >= F::SCR, "a band row must hold the wave transform's scratch");
+        if (wave < NF * kBandRows) {
+            float2* row = tile + wave * LDT;
+            float2 v[F::NV];
+#pragma unroll
+            for (int e = 0; e < F::E; ++e) v[e] = row[lane + 64 * e];
+            F::template nat_to_perm<false>(v, row, a.tw, lane);
+#pragma unroll
+            for (int h = 0; h < F::GPL; ++h)
+#pragma unroll
+                for (int d = 0; d < 8; ++d) {
+                    if (d >= 2 && d < 6) continue;
+                    int q;
+                    row[F::perm_k(lane, h, d, q)] = v[h * 8 + d];
+                }
+        }
+        __syncthreads();
+    } else {
+        fft_lines<MF, kSpreadThreads / (NF * kBandRows), false>(tile, LDT, NF * kBandRows, a.tw);
+    }
     // keep modes kx in I_M: FFT index kx mod MF, stored at kx mod M
     for (int i = tid; i < nf * M * kBandRows; i += kSpreadThreads) {
         const int f = i / (M * kBandRows), j = i % (M * kBandRows);
@@ -190,7 +217,7 @@ __device__ __forceinline__ void fine_y_body(const FineYArgs& a, int bx, int by) 
 }
 
 template <int MF>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft(SpreadArgs a) {
+__global__ __launch_bounds__(kSpreadThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spread_xfft(SpreadArgs a) {
     spread_xfft_body<MF>(a, blockIdx.x, blockIdx.y);
 }
 template <int MF, int BR, int NF>
@@ -279,15 +306,18 @@ static hipError_t launch_grouped(K kernel, const G& g, int threads, size_t sh, h
     return hipGetLastError();
 }
 
+// At most 64 VGPRs (8 waves per SIMD), so that two workgroups of tiles
+// within 80 KB share a CU; the register transform of the x pass would
+// otherwise take 68.
 template <int MF, int BR, int NF>
-__global__ __launch_bounds__(kSpreadThreads) void k_spread_xfft_var(SpreadArgs a) {
+__global__ __launch_bounds__(kSpreadThreads) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_spread_xfft_var(SpreadArgs a) {
     spread_xfft_body<MF, BR, NF>(a, blockIdx.x, blockIdx.y);
 }
 
 // A spreading tile (BR rows of NF frequencies, row stride MF + 8) fits LDS
 // and the in-LDS transform keeps at least one wavefront per line.
 constexpr bool spread_fits(int MF, int BR, int NF) {
-    return BR * NF <= 16 && (size_t)BR * NF * (MF + 8) * sizeof(float2) <= 160 * 1024 && MF / BR >= 2;
+    return BR * NF <= 16 && (size_t)BR * NF * spread_row_stride(MF) * sizeof(float2) <= 160 * 1024 && MF / BR >= 2;
 }
 
 template <int MF, int BR, int NF>
@@ -321,6 +351,7 @@ static hipError_t spread_impl(const SpreadArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_spread_xfft(const SpreadArgs& a, hipStream_t s) {
+    if (a.Mf != 2 * a.M) return hipErrorInvalidValue;     // kept modes: the octants of sigma = 2
     switch (a.Mf) {
         case 32: return spread_impl<32>(a, s);
         case 64: return spread_impl<64>(a, s);
