@@ -237,15 +237,15 @@ template <int MF, int NL>
 constexpr size_t fine_y_wave_lds() { return ((size_t)NL * fine_y_wave_pitch<MF, NL>() + MF) * sizeof(float2); }
 
 template <int MF, int NL>
-__global__ __launch_bounds__(NL * 64) void k_fine_y_wave(FineYArgs a) {
+__device__ __forceinline__ void fine_y_wave_body(const FineYArgs& a, int bx, int by) {
     using F = WaveFFT<MF>;
     static_assert(F::LPW == 1 && F::GPL * 8 == F::E, "one line per wavefront");
     extern __shared__ float2 sm[];     // [NL][pitch] lines and exchange scratch, then twiddles [MF]
     float2* tws = sm + NL * fine_y_wave_pitch<MF, NL>();
     const int M = a.M, br = a.br;
     const int LS = F::SCR + 2 * min(br, 8);     // as fine_y_body: lanes of one run on distinct banks
-    const int kx0 = blockIdx.x * NL;
-    const int fb = blockIdx.y;
+    const int kx0 = bx * NL;
+    const int fb = by;
     const float2* T1 = a.T1 + (size_t)fb * M * MF + (size_t)kx0 * br;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int i = tid; i < MF; i += NL * 64) tws[i] = a.tw[i];
@@ -275,12 +275,27 @@ __global__ __launch_bounds__(NL * 64) void k_fine_y_wave(FineYArgs a) {
 }
 
 template <int MF, int NL>
+__global__ __launch_bounds__(NL * 64) void k_fine_y_wave(FineYArgs a) {
+    fine_y_wave_body<MF, NL>(a, blockIdx.x, blockIdx.y);
+}
+
+template <int MF, int NL>
 __global__ __launch_bounds__(NL * 64) void k_fine_y(FineYArgs a) {
     fine_y_body<MF, NL, NL * 64>(a, blockIdx.x, blockIdx.y);
 }
+// Batched: the wave transform for 512- and 1024-point lines (the batch's
+// scenes all have Mf = 2M), the LDS transform otherwise.
 template <int MF, int NL>
 __global__ __launch_bounds__(NL * 64) void k_fine_y_grouped(Group<FineYArgs> g) {
-    persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_body<MF, NL, NL * 64>(a, bx, by); });
+    if constexpr (MF == 512 || MF == 1024)
+        persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_wave_body<MF, NL>(a, bx, by); });
+    else
+        persistent_loop(g, [](const FineYArgs& a, int bx, int by) { fine_y_body<MF, NL, NL * 64>(a, bx, by); });
+}
+template <int MF, int NL>
+constexpr size_t fine_y_grouped_lds() {
+    if constexpr (MF == 512 || MF == 1024) return fine_y_wave_lds<MF, NL>();
+    else return (size_t)NL * fine_y_ls<MF>() * sizeof(float2);
 }
 
 
@@ -479,7 +494,7 @@ template <int MF>
 static hipError_t fine_y_grouped_mf(int lines, const Group<FineYArgs>& g, hipStream_t s) {
     switch (lines) {
 #define NURSD_FG(NL) \
-    case NL: return launch_grouped(k_fine_y_grouped<MF, NL>, g, NL * 64, (size_t)NL * fine_y_ls<MF>() * sizeof(float2), s);
+    case NL: return launch_grouped(k_fine_y_grouped<MF, NL>, g, NL * 64, fine_y_grouped_lds<MF, NL>(), s);
         NURSD_FG(2) NURSD_FG(4) NURSD_FG(8)
 #undef NURSD_FG
         default: return hipErrorInvalidValue;
