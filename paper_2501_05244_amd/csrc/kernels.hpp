@@ -341,6 +341,8 @@ constexpr int spread_var_rows(int var, int Mf) { return var ? var / 100 : spread
 constexpr int spread_var_freqs(int var, int Mf) { return var ? var % 100 : spread_freqs(Mf); }
 bool spread_var_ok(int Mf, int var);
 bool spread_var_plain_ok(int Mf, int var);   // variants of the plain (per-plan) launch
+// The spreading and fine-y launches keep the modes of a sigma = 2 grid: every
+// item has Mf = 2M, as every plan's fine grid does (launch_spread_xfft checks).
 hipError_t launch_spread_xfft_grouped(int Mf, int var, const Group<SpreadArgs>& g, hipStream_t s);
 hipError_t launch_fine_y_grouped(int Mf, int lines, const Group<FineYArgs>& g, hipStream_t s);
 hipError_t launch_kernel_rows_grouped(int M, int nw, const Group<P1Args>& g, hipStream_t s);
