@@ -147,6 +147,13 @@ typedef struct {
      * weights are copied at plan creation; gradients (nursd_adjoint) are
      * taken with respect to the unweighted P and positions. */
     const float* weights_dev;
+    /* Spreading tile of the type-1 NUFFT (NUFFT section, the blur step):
+     * band rows x 100 + frequencies per workgroup, one of 108, 116, 208, 404,
+     * 802, 1601 (108 = one fine row of 8 frequencies); 0 = the library's
+     * choice.  Any tile gives bit-identical results (each fine-grid cell
+     * takes its samples in the same order); a tile whose LDS footprint does
+     * not fit the plan's fine grid is rejected with NURSD_ERR_ARG. */
+    int32_t spread_tile;
 } nursd_options;
 
 typedef struct nursd_plan nursd_plan;

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("n_relay", c_int32), ("pad", c_double), ("sigma_os", c_double), ("tol", c_double),
         ("M", c_int32), ("freq_chunk", c_int32), ("plane_chunk", c_int32),
-        ("upsample_q", c_int32), ("weights_dev", c_void_p),
+        ("upsample_q", c_int32), ("weights_dev", c_void_p), ("spread_tile", c_int32),
     ]
 
 

@@ -45,7 +45,8 @@ class Plan:
                  bins=None, coherent=True, sigma_rel=0.2, pad=2.0, tol=1e-6, M=0, freq_chunk=0,
                  plane_chunk=0, xp=(0.0, 0.0, 0.0), zref=0.0, alpha=None, plane_ptr=None,
                  voxel_xy: torch.Tensor | None = None, relay_z: torch.Tensor | None = None, z_mid=0.0, dz3=0.0,
-                 mz3=0, kernel_inv_r=True, upsample_q=1, weights: torch.Tensor | None = None, stream=None):
+                 mz3=0, kernel_inv_r=True, upsample_q=1, weights: torch.Tensor | None = None, spread_tile=0,
+                 stream=None):
         self._lib = _lib.load()
         self.handle = None
         L = relay_xy.shape[0]
@@ -97,6 +98,7 @@ class Plan:
         opt.pad, opt.tol, opt.M = pad, tol, M
         opt.freq_chunk, opt.plane_chunk = freq_chunk, plane_chunk
         opt.upsample_q = int(upsample_q)
+        opt.spread_tile = int(spread_tile)
         if weights is not None:
             _need(weights, torch.float32, (L,), "weights")
             opt.weights_dev = weights.data_ptr()      # copied by nursd_plan_create

@@ -2265,8 +2265,15 @@ static int nursd_plan_create_body(const nursd_wavelet* wl, const nursd_geometry*
             if (!std::isfinite(v)) return bail(fail(NURSD_ERR_ARG, "non-finite sample weight"));
         if ((rc = upload(p, wv, &p->d_w))) return bail(rc);
     }
-    p->spread_var = p->mode == NURSD_MODE_GRID3D ? NURSD_PLAN3D_SPREAD_VAR : NURSD_PLAN_SPREAD_VAR;
-    if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = 0;
+    if (opt->spread_tile) {
+        if (!spread_var_plain_ok(p->Mf, opt->spread_tile))
+            return bail(fail(NURSD_ERR_ARG, "spreading tile " + std::to_string(opt->spread_tile) +
+                                                 " is not available for a fine grid of " + std::to_string(p->Mf)));
+        p->spread_var = opt->spread_tile;
+    } else {
+        p->spread_var = p->mode == NURSD_MODE_GRID3D ? NURSD_PLAN3D_SPREAD_VAR : NURSD_PLAN_SPREAD_VAR;
+        if (!spread_var_plain_ok(p->Mf, p->spread_var)) p->spread_var = 0;
+    }
     if ((rc = build_spread_lists(p, rxy))) return bail(rc);
     layout_workspace(p);
     // device address of the fixed scratch of nursd_forward_hist_static on
