@@ -43,10 +43,13 @@ __global__ __launch_bounds__(kT2Waves * 64) void k_type2_cols(Type2Args a) {
     for (int i = threadIdx.x; i < M; i += kT2Waves * 64) tws_m[i] = a.tw_m[i];
     for (int i = threadIdx.x; i < MF; i += kT2Waves * 64) tws_f[i] = a.tw_f[i];
     __syncthreads();
-    const int p = blockIdx.y;
+    // each XCD takes a contiguous run of (plane, kx block) items: the planes
+    // of one frequency share its spectrum rows, which then stay in that L2
+    const int vb = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int bxx = vb % gridDim.x, p = vb / gridDim.x;
     const int b = a.g.b0 + p / a.g.nzc;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int kx = blockIdx.x * kT2Waves + wave;
+    const int kx = bxx * kT2Waves + wave;
     if (kx > H) return;
     float2* scr = sm + wave * SCRP;
     const float2* Bt = a.Bt + (size_t)p * (H + 1) * a.BS;
@@ -143,10 +146,13 @@ __global__ __launch_bounds__(kT2RowWaves * 64) void k_type2_band(Type2Args a) {
     extern __shared__ float2 sm[];          // tile [RB][TP] / scratch and rows [RB][SCR], twiddles MF
     float2* tws = sm + RB * G::SCR;
     for (int i = threadIdx.x; i < MF; i += kT2RowWaves * 64) tws[i] = a.tw_f[i];
-    const int p = blockIdx.y;
+    // neighbouring bands of a plane (which share the cache lines of the
+    // column outputs they read) run on the same XCD
+    const int vb = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int p = vb / gridDim.x;
+    const int band = vb % gridDim.x;
     const int zl = p % a.g.nzc, bl = p / a.g.nzc;
     const int iz = a.g.z0 + zl;
-    const int band = blockIdx.x;
     const int jy0 = a.row_lo[iz] + band * RB;
     if (jy0 > a.row_hi[iz]) return;         // block-uniform
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
