@@ -235,15 +235,7 @@ hipError_t launch_chirp_cols(const ChirpArgs& a, hipStream_t s);
 // oversampled line, inverse FFT along y -> T2 (type-2 output of eq. NURSD2_SRSD).
 hipError_t launch_chirp_type2_cols(const ChirpArgs& a, hipStream_t s);
 
-// Workgroups are handed to the 8 XCDs round-robin by linear id.  This maps a
-// linear id to a work item so that each XCD gets one contiguous run of work
-// items (neighbouring items then share that XCD's L2).
-constexpr int kXcds = 8;
-__device__ __forceinline__ int xcd_contiguous(int lin, int total) {
-    const int x = lin % kXcds, k = lin / kXcds;
-    const int start = x * (total / kXcds) + min(x, total % kXcds);
-    return start + k;
-}
+// xcd_contiguous (persistent.hpp) maps workgroup ids to XCD-contiguous runs of work items.
 
 // Load of data read for the last time (an intermediate the next kernels do
 // not need): marked non-temporal, so the caches evict it first and keep what

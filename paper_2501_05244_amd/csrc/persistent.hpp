@@ -8,6 +8,16 @@
 
 namespace nursd {
 
+// Workgroups are handed to the 8 XCDs round-robin by linear id.  This maps a
+// linear id to a work item so that each XCD gets one contiguous run of work
+// items (neighbouring items then share that XCD's L2).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_contiguous(int lin, int total) {
+    const int x = lin % kXcds, k = lin / kXcds;
+    const int start = x * (total / kXcds) + min(x, total % kXcds);
+    return start + k;
+}
+
 template <typename Args>
 struct Group {
     const Args* items;     // [n] argument blocks
