@@ -85,9 +85,9 @@ __device__ __forceinline__ void spread_xfft_body(const SpreadArgs& a, int bx, in
     // the sample's taps (always for one-row bands).
     constexpr int NQ = NF * kBandRows, RND = (NQ + 7) / 8;
     const int ti = lane & 7, q0 = lane >> 3;
-    // 8 KB entries per round trip: lane (ti, q) fetches entries base + ti + 8 k
-    // (k < KB), with the value of its pair's frequency for each round; step j
-    // takes entry j from lane (j % 8, q) by a lane permute.
+    // 8 * KB entries per round trip: lane (ti, q) fetches entries base + ti +
+    // 8 k (k < KB), with the value of its pair's frequency for each round;
+    // step j takes entry j from lane (j % 8, q) by a lane permute.
     constexpr int KB = 4;
     for (int base = s0; base < s1; base += 8 * KB) {
         int packed[KB];
