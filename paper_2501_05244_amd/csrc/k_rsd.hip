@@ -85,9 +85,9 @@ template <int M, int NW = kP1Waves>
 __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by) {
     using F = WaveFFT<M>;
     constexpr int H = M / 2, E = F::E, LPW = F::LPW, SCRP = p1_scrp<M>();
-    extern __shared__ float2 sm[];      // [NW][SCRP], twiddles [M], Nyquist samples [LB]
+    extern __shared__ float2 sm[];      // [NW][SCRP], twiddles [TWN], Nyquist samples [LB]
     float2* tws = sm + NW * SCRP;
-    for (int i = threadIdx.x; i < M; i += NW * 64) tws[i] = a.tw[i];
+    for (int i = threadIdx.x; i < F::TWN; i += NW * 64) tws[i] = a.tw[i];
     const int p = by;
     int b, iz;
     plane_of(a.g, p, b, iz);
@@ -102,7 +102,7 @@ __device__ __forceinline__ void kernel_rows_body(const P1Args& a, int bx, int by
     // 0; the block computes those LB samples once, one per thread, instead of
     // every wave spending a whole slot on one lane.
     constexpr bool NYQ_LDS = E >= 2;
-    float2* nyq = tws + M;
+    float2* nyq = tws + F::TWN;
     if (NYQ_LDS && tid < LB) {
         const int my = my0 + tid;
         const double ry = (my <= H ? my : 0) * py, rx = H * px;
@@ -564,7 +564,7 @@ hipError_t launch_kernel_rows(const P1Args& a, hipStream_t s) {
         constexpr int LB = kP1Waves * F::LPW;
         dim3 grid((MM / 2 + 1 + LB - 1) / LB, planes);
         return launch_rsd(k_kernel_rows<MM>, grid, kP1Waves * 64,
-                          (size_t)(kP1Waves * p1_scrp<MM>() + MM + kP1Waves * F::LPW) * sizeof(float2),
+                          (size_t)(kP1Waves * p1_scrp<MM>() + F::TWN + kP1Waves * F::LPW) * sizeof(float2),
                           s, a);
     })
 }
@@ -618,7 +618,7 @@ template <int M, int W>
 static hipError_t p1_grouped(const Group<P1Args>& g, hipStream_t s) {
     using F = WaveFFT<M>;
     return launch_grouped(k_kernel_rows_grouped<M, W>, g, W * 64,
-                          (size_t)(W * p1_scrp<M>() + M + W * F::LPW) * sizeof(float2), s);
+                          (size_t)(W * p1_scrp<M>() + F::TWN + W * F::LPW) * sizeof(float2), s);
 }
 template <int M, int W>
 static hipError_t p2_grouped(bool halfy, const Group<P2Args>& g, hipStream_t s) {

@@ -97,6 +97,10 @@ struct WaveFFT {
     // lane strides off multiples of the bank count); BP per tile.
     static constexpr int RP = NURSD_WFFT_RP, BP = 8 * RP;
     static constexpr int SCR = LPW * E * BP;             // LDS scratch per wave (float2)
+    // Twiddle entries the transforms read: tw[lane k1] (lane < 64, k1 < E)
+    // and tw[E a c] (a, c < 8), neither of which wraps; a kernel that stages
+    // the table in LDS needs only these.
+    static constexpr int TWN = (63 * (E - 1) > 49 * E ? 63 * (E - 1) : 49 * E) + 1;
     static_assert(NV == 8 * GPL, "layout");
 
     __device__ static __forceinline__ void decode(int gi, int& q, int& k1, int& x) {
