@@ -413,9 +413,9 @@ def main():
         measured = {"bytes_per_step": b, "GBs": round(b / (ms * 1e-3) / 1e9, 1),
                     "frac_of_peak": round(b / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
                     "source": "profiles/spad_forward_hbm_counters.md"}
-    # The survey's streaming model of the propagation (a figure of the model,
-    # not of the bytes this design moves: it counts a full M^2 kernel spectrum
-    # per plane where only the quadrant is stored).
+    # A streaming model of the propagation (a figure of the model, not of the
+    # bytes this design moves: it counts a full M^2 kernel spectrum per plane
+    # where only the quadrant is stored).
     model = {"bytes_per_step": path_model_bytes(plan.info, w),
              "note": "streaming-model bytes (24M^2+16MN+16N^2 per plane + histogram); not measured traffic"}
 
