@@ -168,6 +168,32 @@ def test_forward_degenerate_sizes(device, L, F, nz, nx, ny):
     assert rel(I.cpu().numpy(), np.abs(Vref)) < TOL
 
 
+@pytest.mark.parametrize("L,nx,ny,M", [(1, 200, 1, 512), (2, 260, 3, 1024)])
+def test_forward_degenerate_large_frames(device, L, nx, ny, M):
+    """One or two relays on 512- and 1024-point frames with 9 frequencies:
+    nearly every spreading band is empty, the last group of the 8-frequency
+    spreading tile holds one frequency, and the x transform of the fine rows
+    is the register-resident one."""
+    print("case: degenerate large frame", L, nx, ny, M, flush=True)
+    rng = np.random.default_rng(L)
+    dx = 0.02
+    F = 9
+    g = scenes.Grid(x0=-dx * nx / 2, y0=-0.01, dx=dx, dy=dx, nx=nx, ny=ny, z=np.array([0.4]))
+    xy = np.stack([rng.uniform(-0.18, 0.18, L), rng.uniform(-0.12, 0.12, L)], 1).astype(np.float32)
+    wl = scenes.Wavelet(lambda_c=0.06, n_time=512, dt=8e-12, t0=0.0, n_freq=F, bins=np.arange(12, 12 + F))
+    w = scenes.Workload("degenerate_large", xy, np.array([0.01, -0.02, 0.0]), wl, g)
+    P = (rng.normal(size=(F, L)) + 1j * rng.normal(size=(F, L))).astype(np.complex64)
+    plan = plan_for(w, device)
+    fr = o.frame_for_workload(w)
+    assert plan.info["M"] == fr.M == M
+    V, I = plan.forward_phasor(torch.from_numpy(P).to(device))
+    _, f = o.wavelet_bins(0.06, 512, 8e-12, F, w.wavelet.bins)
+    Vref = o.nursd_grid(P.astype(np.complex128), xy.astype(np.float64), f, fr, g, w.xp)
+    assert V.shape == Vref.shape
+    assert rel(V.cpu().numpy(), Vref) < TOL
+    assert rel(I.cpu().numpy(), np.abs(Vref)) < TOL
+
+
 def test_forward_incoherent(device):
     w, P = ragged_case(seed=6)
     plan = plan_for(w, device, coherent=False)

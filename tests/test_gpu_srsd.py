@@ -50,6 +50,22 @@ def test_srsd_small(device, n, chunks):
     assert rel(I.cpu().numpy(), np.abs(ref)) < TOL
 
 
+@pytest.mark.parametrize("n,L,zs", [(256, 1, (0.9,)), (255, 2, (0.6, 1.4))])
+def test_srsd_few_relays(device, n, L, zs):
+    """One or two relays, one or two planes, an odd window: the Bluestein
+    lines are nearly empty and the window is not a multiple of the tiles."""
+    print("case: srsd few relays", n, L, zs, flush=True)
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P = srsd_case(n, seed=5, L=L, zs=zs)
+    plan = plan_from_workload(w, device)
+    assert plan.info["M"] == o.frame_for_workload(w).M == 512
+    V, I = plan.forward_phasor(torch.from_numpy(P).to(device))
+    _, f = o.wavelet_bins(0.06, 4096, 4e-12, 2, w.wavelet.bins)
+    ref = oracle_srsd(w, P, f)
+    assert rel(V.cpu().numpy(), ref) < TOL
+    assert rel(I.cpu().numpy(), np.abs(ref)) < TOL
+
+
 def test_srsd_rejects_bad_geometry(device):
     from paper_2501_05244_amd.api import plan_from_workload
     w, P = srsd_case(256, seed=1)
