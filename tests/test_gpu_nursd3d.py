@@ -62,6 +62,26 @@ def test_nursd3d_rejects_bad_geometry(device):
         plan_from_workload(w, device)
 
 
+def test_nursd3d_spreading_tiles_identical(device):
+    """The spreading tile option applies to the depth copies of the 3D stage
+    1 too: every tile gives the default's volume bit for bit (M = 256, 16
+    depth copies of 2 frequencies, 2,048 relays on a curved wall)."""
+    from paper_2501_05244_amd.api import plan_from_workload
+    w, P = case(9, n=128, L=2048, F=2, zs=(0.6, 1.4), amp=0.03, z_mid=0.04, dz3=0.02, mz3=16, dx=1.0 / 128)
+    Pd = torch.from_numpy(P).to(device)
+    ref = None
+    for tile in (0, 108, 116, 208, 404, 802, 1601):
+        print(f"case: nursd3d spreading tile {tile}", flush=True)
+        plan = plan_from_workload(w, device, spread_tile=tile)
+        assert plan.info["M"] == 256
+        V, _ = plan.forward_phasor(Pd, intensity=False)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = V.clone()
+        else:
+            assert torch.equal(V, ref), f"tile {tile} differs from the default"
+
+
 @pytest.mark.slow
 def test_nursd3d_medium(device):
     """2,048 relays on a curved wall, 128 x 128 voxels (M = 256), depth grid of
