@@ -272,13 +272,13 @@ def secondary(w_spad, dev) -> dict:
 
 
 KERNEL_SOURCES = ("k_rsd.hip", "k_nufft.hip", "k_phasor.hip", "kernels.hpp", "wavefft.hpp", "fft.hpp", "persistent.hpp",
-                  "api.hip")
+                  "api.hip", "host_plan.hpp")
 
 
 def kernel_source_hash() -> str:
     """SHA-256 over the sources of the forward kernels and of the host code
-    that chunks their launches; a counter summary taken on other sources no
-    longer describes the launches that run."""
+    that chunks their launches and bins the relay samples; a counter summary
+    taken on other sources no longer describes the launches that run."""
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:

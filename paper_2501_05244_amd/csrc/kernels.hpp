@@ -2,6 +2,7 @@
 // translation units and the host-side C-ABI implementation.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "host_plan.hpp"
 #include "persistent.hpp"
 #include <cstddef>
 #include <cstdint>
@@ -11,27 +12,11 @@ namespace nursd {
 constexpr double kC = 299792458.0;   // speed of light [m/s]
 constexpr int kMaxLog = 13;          // twiddle tables for N = 2^0 .. 2^12
 
-// Binned relay sample, one per (sample or periodic image, band) it touches.
-// In centred fine-grid cells the sample sits at (ix0 + fx, iy0 + fy); its
-// w x w taps are cells ix0 .. ix0 + w - 1 (x) and iy0 .. iy0 + w - 1 (y).
-// Splitting the integer base from the fraction keeps the tap offsets exact
-// to float precision on grids of any size.
-struct SpreadEntry {
-    short ix0, iy0;
-    float fx, fy;
-    int idx;     // relay index into P
-};
-
 // Fine-grid rows per spreading band (one band of one frequency fills LDS).
 constexpr int spread_band_rows(int) { return 8; }
 // Frequencies spread by one workgroup: the kernel weights of a sample are
 // computed once and applied to each of them (one LDS tile per frequency).
 constexpr int spread_freqs(int Mf) { return Mf <= 1024 ? 2 : 1; }
-// Wavefronts per spreading workgroup; each owns a contiguous range of fine
-// columns of the band (chosen on the host so the waves walk similar numbers
-// of samples).
-constexpr int kSpreadWaves = 16;
-
 struct TwTables {
     const float2* t[kMaxLog];   // t[n][m] = e^{-2 pi j m / 2^n}
 };
