@@ -12,11 +12,14 @@
 // sample per step, its lanes spread over (tap column, frequency and band
 // row) so the x kernel weight of a sample is computed once for all its
 // copies.  Every LDS cell is updated by one wave in a fixed order: no
-// atomics, bitwise reproducible.  The band is then FFT'd along x in LDS and
-// only the M kept modes are written, scaled by the x deconvolution factor,
-// band-major ([frequency][band][mode][band row]) so each block writes
+// atomics, bitwise reproducible.  Each band row is then transformed along x
+// (512- and 1024-point rows by one wavefront each in registers, with the row
+// itself as exchange scratch; other sizes by the block-level LDS transform)
+// and only the M kept modes are written, scaled by the x deconvolution
+// factor, band-major ([frequency][band][mode][band row]) so each block writes
 // contiguous runs.
-// k_fine_y: FFT along y of each kept kx row, keep M modes, deconvolve in y.
+// k_fine_y / k_fine_y_wave: FFT along y of each kept kx column, keep M modes,
+// deconvolve in y.
 #include "fft.hpp"
 #include "kernels.hpp"
 #include "persistent.hpp"
