@@ -79,6 +79,24 @@ def test_spad_full_launch_8_bins_16_planes(device, spad_hist):
     assert rel(I[zi], np.abs(Vref)) < TOL
 
 
+def test_spad_forward_bitwise_reproducible(device, spad_hist):
+    """The full SPAD forward from histograms, as the benchmark times it, gives
+    the same volume bit for bit when repeated and when a second plan is built
+    from the same inputs (fixed spreading order, no atomics)."""
+    print("case: spad forward bitwise reproducible", flush=True)
+    w = scenes.config_spad(render=False)
+    H = torch.from_numpy(spad_hist).to(device)
+    plan = plan_for(w, device)
+    V1, I1 = plan.forward_hist(H)
+    V2, I2 = plan.forward_hist(H)
+    plan_b = plan_for(w, device)
+    V3, I3 = plan_b.forward_hist(H)
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(V1)).all()
+    assert torch.equal(V1, V2) and torch.equal(I1, I2)
+    assert torch.equal(V1, V3) and torch.equal(I1, I3)
+
+
 def test_nursd3d_m512(device):
     """3D NURSD with the non-planar workload's frame (M = 512, depth grid of
     16 at 2 cm around z_mid = 6 cm): 2,048 of its relays on the curved wall,
